@@ -1,0 +1,573 @@
+"""Pins for the CPU oracle: brute force, known answers, closed forms, statistics.
+
+Nothing here retypes the oracle's formulas: each check derives the expected
+value another way (point-in-cube tests on floats instead of Morton keys,
+Python tuple sorting instead of lexsort, published known-answer vectors,
+integrals and moments of the Gaussian, finite differences, sampling
+statistics).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cut, lod, philox, splat
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+NONE = 0xFFFFFFFF
+
+
+# ---------------------------------------------------------------------------
+# Philox
+
+def _kat_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(t, 16) for t in line.split()])
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for r in rows:
+        out = philox.philox4x32_10(*r[:6])
+        assert [int(o) for o in out] == r[6:]
+
+
+def test_philox_uniformity():
+    ids = np.arange(1 << 18, dtype=np.uint64)
+    U = philox.particle_uniform(ids, 0, 12345)
+    assert U.min() >= 1 and U.max() <= (1 << 32)
+    r = (U - 1).astype(np.uint64)
+    hist = np.bincount((r >> np.uint64(24)).astype(np.int64), minlength=256)
+    exp = len(ids) / 256
+    chi2 = ((hist - exp) ** 2 / exp).sum()
+    assert chi2 < 255 + 6 * math.sqrt(2 * 255)          # ~6 sigma
+    for b in range(32):
+        ones = int(((r >> np.uint64(b)) & np.uint64(1)).sum())
+        assert abs(ones - len(ids) / 2) < 6 * math.sqrt(len(ids) / 4)
+
+
+def test_philox_depends_on_snapshot_and_seed():
+    a = philox.particle_uniform(np.arange(64), 0, 7)
+    b = philox.particle_uniform(np.arange(64), 1, 7)
+    c = philox.particle_uniform(np.arange(64), 0, 8)
+    assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# ---------------------------------------------------------------------------
+# brute-force octree built from float point-in-cube tests
+
+def _in_cube(x, y, z, cx, cy, cz, d):
+    """Membership of the half-open depth-d cube; the face at 1.0 belongs to the last cell."""
+    side = 2.0 ** -d
+    res = np.ones(len(x), dtype=bool)
+    for a, c in ((x, cx), (y, cy), (z, cz)):
+        a = a.astype(np.float64)
+        lo, hi = c * side, (c + 1) * side
+        res &= (a >= lo) & ((a < hi) | ((c == (1 << d) - 1) & (a == 1.0)))
+    return res
+
+
+def _brute_keys(x, y, z, D):
+    """Key by descending the octree: at each depth pick the octant by midpoint tests."""
+    keys = []
+    for i in range(len(x)):
+        key = 0
+        c = [0, 0, 0]
+        for d in range(D):
+            octant = 0
+            for ax, a in enumerate((x[i], y[i], z[i])):
+                mid = (c[ax] * 2 + 1) * 2.0 ** -(d + 1)
+                bit = 1 if float(a) >= mid else 0
+                c[ax] = c[ax] * 2 + bit
+                octant |= bit << ax
+            key = key * 8 + octant
+        keys.append(key)
+    return keys
+
+
+def _brute_tree(x, y, z, m, n, D, ids, K):
+    """Recursive construction; returns nodes in breadth-first order as dicts."""
+    out = []
+    level = [(0, 0, 0, 0, -1)]           # (cx, cy, cz, d, parent)
+    while level:
+        nxt = []
+        for (cx, cy, cz, d, par) in level:
+            members = np.nonzero(_in_cube(x, y, z, cx, cy, cz, d))[0]
+            if len(members) == 0:
+                continue
+            idx = len(out)
+            node = dict(c=(cx, cy, cz), d=d, parent=par, members=members,
+                        mass=math.fsum(m[members].astype(np.float64).tolist()))
+            if len(members) > n:
+                order = sorted(members.tolist(), key=lambda i: (int(K[i]), int(ids[i])))
+                node["top"] = order[:n]
+                node["witness"] = order[n]
+            out.append(node)
+            if len(members) > n and d < D:
+                for o in range(8):
+                    ccx, ccy, ccz = cx * 2 + (o & 1), cy * 2 + ((o >> 1) & 1), cz * 2 + ((o >> 2) & 1)
+                    nxt.append((ccx, ccy, ccz, d + 1, idx))
+        level = nxt
+    return out
+
+
+def _tiny_set(rng, N, dup=False):
+    x = rng.random(N).astype(np.float32)
+    y = rng.random(N).astype(np.float32)
+    z = rng.random(N).astype(np.float32)
+    # points on cell faces and on the far faces of the cube
+    k = max(1, N // 10)
+    x[:k] = (rng.integers(0, 17, k) / 16.0).astype(np.float32)
+    y[k:2 * k] = np.float32(1.0)
+    if dup:
+        x[-k:] = x[0]; y[-k:] = y[0]; z[-k:] = z[0]
+    m = rng.uniform(0.5, 2.0, N).astype(np.float32)
+    return x, y, z, m
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_keys_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    x, y, z, _ = _tiny_set(rng, 300)
+    for D in (0, 1, 3, 5):
+        cx, cy, cz = (lod.cell_coords(a, D) for a in (x, y, z))
+        keys = lod.interleave(cx, cy, cz, D)
+        assert [int(k) for k in keys] == _brute_keys(x, y, z, D)
+        # key >> 3(D-d) is the depth-d key
+        for d in range(D + 1):
+            kd = lod.interleave(*(lod.cell_coords(a, d) for a in (x, y, z)), d)
+            assert np.array_equal(keys >> np.uint64(3 * (D - d)), kd)
+
+
+@pytest.mark.parametrize("seed,n,D,alpha,dup", [
+    (0, 1, 2, 1, False), (1, 2, 3, 1, False), (2, 3, 3, 0, False), (3, 5, 2, -1, False),
+    (4, 7, 3, 1, True), (5, 3, 1, 1, True), (6, 20, 3, 1, False), (7, 4, 0, 1, False),
+])
+def test_tree_selection_brute_force(seed, n, D, alpha, dup):
+    rng = np.random.default_rng(100 + seed)
+    N = int(rng.integers(40, 400))
+    x, y, z, m = _tiny_set(rng, N, dup)
+    t = lod.lod_build(x, y, z, m, n=n, D=D, alpha=alpha, seed=seed * 17 + 3)
+    ids = np.arange(N)
+    # K by particle (oracle keeps it by sorted position)
+    K = np.zeros(N, dtype=np.uint64); K[t.order] = t.K
+    w = np.zeros(N, dtype=np.int64); w[t.order] = t.w.astype(np.int64)
+
+    # sort order: Python tuple sort of (key, index)
+    keys = _brute_keys(x, y, z, D)
+    assert t.order.tolist() == sorted(range(N), key=lambda i: (keys[i], i))
+
+    # density: brute-force count of particles sharing the depth-D cube
+    for i in range(0, N, 7):
+        c = [int(lod.cell_coords(np.array([a]), D)[0]) for a in (x[i], y[i], z[i])]
+        assert w[i] == int(_in_cube(x, y, z, *c, D).sum())
+
+    nodes = _brute_tree(x, y, z, m, n, D, ids, K)
+    assert t.n_nodes == len(nodes)
+    for v, nd in enumerate(nodes):
+        assert int(t.depth[v]) == nd["d"]
+        (cx, cy, cz), d = lod.node_origin(t, v)
+        assert (cx, cy, cz) == nd["c"]
+        assert int(t.parent[v]) == (NONE if nd["parent"] < 0 else nd["parent"])
+        assert int(t.part_count[v]) == len(nd["members"])
+        b = int(t.part_begin[v])
+        assert sorted(t.order[b:b + len(nd["members"])].tolist()) == nd["members"].tolist()
+        assert t.node_mass[v] == nd["mass"]
+        pb, pc = int(t.pt_begin[v]), int(t.pt_count[v])
+        stored = sorted(t.pt_id[pb:pb + pc].tolist())
+        if "top" in nd:
+            assert stored == sorted(nd["top"])
+            assert t.order[t.witness[v]] == nd["witness"]
+        else:
+            assert stored == nd["members"].tolist()
+    # first_child / child_mask consistency
+    for v in range(t.n_nodes):
+        kids = [u for u in range(t.n_nodes) if int(t.parent[u]) == v]
+        if kids:
+            assert int(t.first_child[v]) == kids[0]
+            assert kids == list(range(kids[0], kids[0] + len(kids)))
+            octs = [(int(t.prefix[u]) & 7) for u in kids]
+            assert int(t.child_mask[v]) == sum(1 << o for o in octs)
+        else:
+            assert int(t.first_child[v]) == NONE and int(t.child_mask[v]) == 0
+
+
+def test_bottom_up_equals_direct():
+    """The level-by-level construction over children's top-(n+1) sets gives the direct sets."""
+    s = synth.small_clustered(20000, 11)
+    n = 50
+    t = lod.lod_build(s.x, s.y, s.z, s.m, n=n, D=5, alpha=1, seed=9)
+    top = {}
+    for v in range(t.n_nodes - 1, -1, -1):
+        if int(t.part_count[v]) <= n:
+            continue
+        fc = int(t.first_child[v])
+        if fc == NONE:
+            b, c = int(t.part_begin[v]), int(t.part_count[v])
+            cand = list(range(b, b + c))
+        else:
+            cand = []
+            u = fc
+            while u < t.n_nodes and int(t.parent[u]) == v:
+                if int(t.part_count[u]) > n:
+                    cand += top[u]
+                else:
+                    b, c = int(t.part_begin[u]), int(t.part_count[u])
+                    cand += list(range(b, b + c))
+                u += 1
+        cand.sort(key=lambda p: (int(t.K[p]), int(t.order[p])))
+        top[v] = cand[:n + 1]
+        pb = int(t.pt_begin[v])
+        assert sorted(top[v][:n]) == t.pt_pos[pb:pb + n].tolist()
+        assert top[v][n] == t.witness[v]
+
+
+def test_invariants_config1():
+    s = synth.config1()
+    n, D = 4096, 4
+    t = lod.lod_build(s.x, s.y, s.z, s.m, n=n, D=D, alpha=1, seed=0)
+    N = s.n
+    leaf = t.first_child == NONE
+    # I1: leaf ranges partition [0, N)
+    lb = t.part_begin[leaf].astype(np.int64); lc = t.part_count[leaf].astype(np.int64)
+    o = np.argsort(lb)
+    assert lb[o][0] == 0 and np.all(lb[o][1:] == (lb[o] + lc[o])[:-1]) and (lb[o] + lc[o])[-1] == N
+    # I2 / I8
+    assert np.all(t.pt_count <= n)
+    internal = ~leaf
+    assert np.array_equal(internal, (t.part_count > n) & (t.depth < D))
+    assert np.all(t.pt_count[internal] == n)
+    small = leaf & (t.part_count <= n)
+    assert np.all(t.pt_count[small] == t.part_count[small])
+    # I7: children counts sum to the parent's
+    for v in np.nonzero(internal)[0]:
+        kids = np.nonzero(t.parent == v)[0]
+        assert t.part_count[kids].sum() == t.part_count[v]
+    # I9: every particle's key prefix equals its node's prefix
+    for v in range(t.n_nodes):
+        b, c, d = int(t.part_begin[v]), int(t.part_count[v]), int(t.depth[v])
+        assert np.all((t.skey[b:b + c] >> np.uint64(3 * (D - d))) == t.prefix[v])
+    # I3: an internal node's selection comes from its children's stored points
+    for v in np.nonzero(internal)[0]:
+        kids = np.nonzero(t.parent == v)[0]
+        pool = set()
+        for u in kids:
+            pb, pc = int(t.pt_begin[u]), int(t.pt_count[u])
+            pool |= set(t.pt_pos[pb:pb + pc].tolist())
+        pb = int(t.pt_begin[v])
+        assert set(t.pt_pos[pb:pb + n].tolist()) <= pool
+    # I5: stored masses sum to the node mass
+    for v in range(t.n_nodes):
+        pb, pc = int(t.pt_begin[v]), int(t.pt_count[v])
+        tot = math.fsum(t.pt_mass[pb:pb + pc].astype(np.float64).tolist())
+        if int(t.part_count[v]) <= n:
+            assert tot == t.node_mass[v]
+        else:
+            assert abs(tot - t.node_mass[v]) <= (2.0 ** -24 + 1e-12) * t.node_mass[v]
+    # I6: decode within half a quantisation step (+ float32 rounding)
+    for v in range(0, t.n_nodes, 3):
+        (cx, cy, cz), d = lod.node_origin(t, v)
+        pb, pc = int(t.pt_begin[v]), int(t.pt_count[v])
+        ids = t.order[t.pt_pos[pb:pb + pc]]
+        for a, q, c in ((s.x, t.qx, cx), (s.y, t.qy, cy), (s.z, t.qz, cz)):
+            dec = lod.decode(q[pb:pb + pc], c, d).astype(np.float64)
+            err = np.abs(a[ids].astype(np.float64) - dec)
+            assert np.all(err <= 2.0 ** -(d + 17) + 2.0 ** -24)
+    # mass conservation at every level
+    assert abs(t.node_mass[0] - math.fsum(s.m.astype(np.float64).tolist())) == 0.0
+
+
+def test_alpha0_inclusion_probability():
+    """alpha = 0: every particle of a node with N_node = 10, n = 3 is kept with probability 3/10."""
+    rng = np.random.default_rng(5)
+    x = (0.1 + 0.01 * rng.random(10)).astype(np.float32)
+    y = x.copy(); z = x.copy()
+    m = np.ones(10, np.float32)
+    trials = 3000
+    hits = np.zeros(10)
+    for seed in range(trials):
+        t = lod.lod_build(x, y, z, m, n=3, D=0, alpha=0, seed=seed)
+        hits[t.pt_id[:3].astype(np.int64)] += 1
+    p = 0.3
+    sd = math.sqrt(trials * p * (1 - p))
+    assert np.all(np.abs(hits - trials * p) < 5 * sd)
+
+
+def test_alpha0_equal_masses():
+    """alpha = 0 with equal masses: every stored mass of a selecting node is M_node / n."""
+    s = synth.small_clustered(5000, 3)
+    t = lod.lod_build(s.x, s.y, s.z, s.m, n=64, D=3, alpha=0, seed=1)
+    for v in range(t.n_nodes):
+        if int(t.part_count[v]) > 64:
+            pb = int(t.pt_begin[v])
+            want = np.float32(t.node_mass[v] / 64)
+            got = t.pt_mass[pb:pb + 64]
+            assert np.all(np.abs(got.view(np.int32).astype(np.int64) - np.array(want).view(np.int32)) <= 1)
+
+
+def test_priority_sampling_unbiased():
+    """Before the rescale, the estimate sum(m/p) over the kept points is unbiased for M."""
+    rng = np.random.default_rng(8)
+    N = 60
+    x = rng.random(N).astype(np.float32) * np.float32(0.5)
+    x[:20] = np.float32(0.01) + np.float32(0.001) * rng.random(20).astype(np.float32)
+    y = x.copy(); z = x.copy()
+    m = rng.uniform(0.2, 3.0, N).astype(np.float32)
+    M = math.fsum(m.astype(np.float64).tolist())
+    est = []
+    for seed in range(2000):
+        t = lod.lod_build(x, y, z, m, n=12, D=3, L_rho=3, alpha=1, seed=seed)
+        est.append(t.pt_mhat[:12].sum())
+    est = np.array(est)
+    se = est.std() / math.sqrt(len(est))
+    assert abs(est.mean() - M) < 5 * se
+
+
+def test_quantisation_edges():
+    x = np.array([0.0, 0.5, 0.25, 1.0, 0.75], np.float32)
+    y = np.array([1.0, 0.5, 0.0, 1.0, 0.25], np.float32)
+    z = np.array([0.0, 0.0, 0.0, 1.0, 0.5], np.float32)
+    m = np.ones(5, np.float32)
+    t = lod.lod_build(x, y, z, m, n=1, D=2, alpha=1, seed=0)
+    for v in range(t.n_nodes):
+        (cx, cy, cz), d = lod.node_origin(t, v)
+        pb, pc = int(t.pt_begin[v]), int(t.pt_count[v])
+        for k in range(pb, pb + pc):
+            i = int(t.order[t.pt_pos[k]])
+            for a, q, c in ((x, t.qx, cx), (y, t.qy, cy), (z, t.qz, cz)):
+                if float(a[i]) == c * 2.0 ** -d:
+                    assert q[k] == 0                      # node origin -> 0
+                if float(a[i]) == 1.0:
+                    assert q[k] == 65535                  # far face -> clamp
+
+
+def test_empty_and_single():
+    e = np.zeros(0, np.float32)
+    t = lod.lod_build(e, e, e, e, n=4, D=3)
+    assert t.n_nodes == 0 and t.n_points == 0
+    o = np.array([0.3], np.float32)
+    t = lod.lod_build(o, o, o, np.ones(1, np.float32), n=4, D=3)
+    assert t.n_nodes == 1 and t.n_points == 1 and int(t.first_child[0]) == NONE
+
+
+def test_batch_equals_separate_snapshots():
+    a = synth.small_clustered(3000, 1)
+    b = synth.small_clustered(1700, 2)
+    x = np.concatenate([a.x, b.x]); y = np.concatenate([a.y, b.y])
+    z = np.concatenate([a.z, b.z]); m = np.concatenate([a.m, b.m])
+    off = np.array([0, a.n, a.n + b.n])
+    tb = lod.lod_build(x, y, z, m, n=40, D=4, seed=3, snap_offsets=off)
+    for s, snap in enumerate((a, b)):
+        # the batched Philox counter carries the snapshot index; a single build
+        # of snapshot 1 would use snapshot 0, so compare the structure only
+        ts = lod.lod_build(snap.x, snap.y, snap.z, snap.m, n=40, D=4, seed=3)
+        mine = np.nonzero((tb.prefix >> np.uint64(3) * tb.depth.astype(np.uint64)) == s)[0]
+        assert len(mine) == ts.n_nodes
+        assert np.array_equal(tb.part_count[mine], ts.part_count)
+        assert np.array_equal(tb.depth[mine], ts.depth)
+        if s == 0:
+            pts = np.concatenate([np.arange(int(tb.pt_begin[v]), int(tb.pt_begin[v]) + int(tb.pt_count[v]))
+                                  for v in mine])
+            assert np.array_equal(tb.pt_id[pts], ts.pt_id)
+            assert np.array_equal(tb.pt_mass[pts], ts.pt_mass)
+
+
+@pytest.mark.parametrize("bad", ["nan", "neg", "big", "mass"])
+def test_domain_errors(bad):
+    x = np.array([0.1, 0.2], np.float32); y = x.copy(); z = x.copy(); m = np.ones(2, np.float32)
+    if bad == "nan":
+        x[0] = np.nan
+    elif bad == "neg":
+        y[1] = -1e-7
+    elif bad == "big":
+        z[0] = np.float32(1.0000001)
+    else:
+        m[1] = -1.0
+    with pytest.raises(lod.OracleError):
+        lod.lod_build(x, y, z, m, n=1, D=2)
+
+
+# ---------------------------------------------------------------------------
+# splat
+
+def test_splat_gaussian_mass_and_moments():
+    """A wide kernel integrates to the point mass, with variance sigma^2 per axis."""
+    cam = splat.Camera(0, 64, 64)
+    x = np.array([0.5 + 0.3 / 64], np.float32)
+    y = np.array([0.5 - 0.2 / 64], np.float32)
+    for sigma in (1.0, 2.5):
+        img = splat.render(cam, x, y, np.zeros(1, np.float32), np.array([3.0], np.float32),
+                           sigma=sigma, radius_sigmas=6.0)
+        assert abs(img.sum() - 3.0) < 3e-6 * 3.0 + 1e-9
+        jj, ii = np.mgrid[0:64, 0:64]
+        u, v = float(x[0]) * 64, float(y[0]) * 64
+        cu = ((ii + 0.5) * img).sum() / img.sum()
+        cv = ((jj + 0.5) * img).sum() / img.sum()
+        assert abs(cu - u) < 1e-6 and abs(cv - v) < 1e-6
+        var = (((ii + 0.5 - u) ** 2) * img).sum() / img.sum()
+        assert abs(var - sigma ** 2) < 1e-4          # point-sampled Gaussian: variance sigma^2
+
+
+def test_splat_footprint_and_symmetry():
+    cam = splat.Camera(0, 32, 32)
+    x = np.array([10.5 / 32], np.float32); y = np.array([20.5 / 32], np.float32)
+    img = splat.render(cam, x, y, np.zeros(1, np.float32), np.ones(1, np.float32))
+    nz = np.argwhere(img > 0)
+    assert nz[:, 0].min() == 17 and nz[:, 0].max() == 23      # 7 rows when centred
+    assert nz[:, 1].min() == 7 and nz[:, 1].max() == 13
+    sub = img[17:24, 7:14]
+    assert np.allclose(sub, sub.T) and np.allclose(sub, sub[::-1, ::-1])
+    assert img[20, 10] == img.max()
+    x2 = np.array([10.8 / 32], np.float32)
+    img2 = splat.render(cam, x2, y, np.zeros(1, np.float32), np.ones(1, np.float32))
+    assert np.count_nonzero(img2[20]) == 6                     # off-centre: 6 columns
+
+
+def test_splat_linearity_and_shift():
+    s = synth.small_clustered(3000, 4)
+    cam = splat.Camera(0, 64, 64)
+    a = splat.render(cam, s.x[:1500], s.y[:1500], s.z[:1500], s.m[:1500])
+    b = splat.render(cam, s.x[1500:], s.y[1500:], s.z[1500:], s.m[1500:])
+    ab = splat.render(cam, s.x, s.y, s.z, s.m)
+    assert np.allclose(a + b, ab, rtol=1e-13, atol=0)
+    # an exact whole-pixel shift moves the image (points kept away from the border)
+    keep = (s.x > 0.2) & (s.x < 0.7)
+    xs = s.x[keep]; ys = s.y[keep]
+    sh = (xs.astype(np.float64) + 5.0 / 64).astype(np.float32)
+    ok = (sh.astype(np.float64) - xs.astype(np.float64)) == 5.0 / 64
+    base = splat.render(cam, xs[ok], ys[ok], ys[ok], s.m[keep][ok])
+    moved = splat.render(cam, sh[ok], ys[ok], ys[ok], s.m[keep][ok])
+    assert np.allclose(moved[:, 5:], base[:, :-5], rtol=1e-12, atol=0)
+
+
+def test_splat_pixel_sampler_matches_render():
+    s = synth.small_clustered(2000, 6)
+    cam = splat.Camera(1, 48, 40, pos=(0.5, 0.5, -0.8), right=(1, 0, 0), up=(0, 1, 0),
+                       fwd=(0, 0, 1), F=40.0, near=0.01)
+    img = splat.render(cam, s.x, s.y, s.z, s.m)
+    pi = [3, 20, 24, 47, 10]; pj = [4, 20, 19, 39, 30]
+    vals = splat.render_pixels(cam, s.x, s.y, s.z, s.m, pi, pj)
+    assert np.allclose(vals, img[pj, pi], rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("proj", [0, 1])
+def test_splat_adjoint_finite_differences(proj):
+    rng = np.random.default_rng(3)
+    Np = 40
+    x = (0.3 + 0.4 * rng.random(Np)).astype(np.float32)
+    y = (0.3 + 0.4 * rng.random(Np)).astype(np.float32)
+    z = (0.3 + 0.4 * rng.random(Np)).astype(np.float32)
+    m = rng.uniform(0.5, 1.5, Np).astype(np.float32)
+    if proj == 0:
+        cam = splat.Camera(0, 32, 32)
+    else:
+        cam = splat.Camera(1, 32, 32, pos=(0.5, 0.5, -1.0), right=(1, 0, 0), up=(0, 1, 0),
+                           fwd=(0, 0, 1), F=30.0, near=0.01)
+    g = rng.standard_normal((32, 32))
+    gm, gp = splat.render_backward(cam, x, y, z, m, g)
+    # mass: the image is linear in m, so the FD is exact up to rounding
+    for k in range(0, Np, 7):
+        mm = m.copy(); mm[k] = np.float32(0.0)
+        base = (splat.render(cam, x, y, z, mm) * g).sum()
+        mm[k] = np.float32(1.0)
+        one = (splat.render(cam, x, y, z, mm) * g).sum()
+        assert abs((one - base) - gm[k]) < 1e-9 * (1 + abs(gm[k]))
+    # positions: a float64 re-evaluation of the same blobs, central differences
+    R = 3.0
+    m64 = m.astype(np.float64)
+
+    def loss64(px, py, pz):
+        tot = 0.0
+        for k in range(Np):
+            if proj == 0:
+                u, v = px[k] * 32, py[k] * 32
+            else:
+                dx, dy, dz = px[k] - 0.5, py[k] - 0.5, pz[k] + 1.0
+                u = 30.0 * dx / dz + 16; v = 30.0 * dy / dz + 16
+            for j in range(32):
+                for i in range(32):
+                    ox, oy = u - (i + 0.5), v - (j + 0.5)
+                    if abs(ox) <= R and abs(oy) <= R:
+                        tot += m64[k] * math.exp(-(ox * ox + oy * oy) / 2) / (2 * math.pi) * g[j, i]
+        return tot
+    px, py, pz = (a.astype(np.float64) for a in (x, y, z))
+    h = 1e-7
+    for k in range(0, Np, 9):
+        # skip points within 10h (in pixels) of a truncation edge
+        u, v, keep, _, _, _ = splat.project(cam, x[k:k + 1], y[k:k + 1], z[k:k + 1])
+        fu = (u[0] - 0.5) % 1.0; fv = (v[0] - 0.5) % 1.0
+        if min(fu, 1 - fu, fv, 1 - fv) < 1e-3:
+            continue
+        for ax, arr in enumerate((px, py, pz)):
+            if proj == 0 and ax == 2:
+                assert gp[k, 2] == 0.0
+                continue
+            old = arr[k]
+            arr[k] = old + h; lp = loss64(px, py, pz)
+            arr[k] = old - h; lm = loss64(px, py, pz)
+            arr[k] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - gp[k, ax]) < 2e-4 * (1 + abs(fd))
+
+
+# ---------------------------------------------------------------------------
+# view-dependent cut
+
+def _leaf_cover(t, chosen):
+    """Every leaf has exactly one ancestor-or-self in the cut."""
+    chosen = set(int(v) for v in chosen)
+    for v in range(t.n_nodes):
+        if int(t.first_child[v]) != NONE:
+            continue
+        hits, u = 0, v
+        while True:
+            hits += u in chosen
+            p = int(t.parent[u])
+            if p == NONE:
+                break
+            u = p
+        assert hits == 1
+
+
+def test_cut_orthographic_uniform_depth():
+    s = synth.config1()
+    t = lod.lod_build(s.x, s.y, s.z, s.m, n=64, D=6, seed=0)
+    for tau in (1.0, 2.0, 4.0, 8.0):
+        cam = splat.Camera(0, 256, 256)
+        c = cut.select(t, cam, tau, 64)
+        _leaf_cover(t, c)
+        # brute force: stop at the first depth with W 2^-d / n^(1/3) <= tau
+        dstar = next(d for d in range(0, 64) if 256 * 2.0 ** -d <= tau * 4.0)
+        for v in c:
+            internal = int(t.first_child[v]) != NONE
+            assert (not internal and int(t.depth[v]) <= dstar) or int(t.depth[v]) == dstar
+
+
+def test_cut_perspective_cover_and_monotone():
+    s = synth.config1()
+    t = lod.lod_build(s.x, s.y, s.z, s.m, n=64, D=6, seed=0)
+    cam = splat.Camera(1, 256, 256, pos=(0.5, 0.5, -0.9), right=(1, 0, 0), up=(0, 1, 0),
+                       fwd=(0, 0, 1), F=221.7, near=0.01)
+    drawn = []
+    for tau in (8.0, 4.0, 2.0, 1.0, 0.5):
+        c = cut.select(t, cam, tau, 64)
+        _leaf_cover(t, c)
+        drawn.append(int(t.pt_count[c].astype(np.int64).sum()))
+    assert drawn == sorted(drawn)          # smaller tau draws more points
+    inside = splat.Camera(1, 256, 256, pos=(0.30, 0.30, 0.30), F=221.7, near=0.01)
+    c = cut.select(t, inside, 1e9, 64)
+    _leaf_cover(t, c)
+    # with an enormous tau only the camera's own cube chain is opened
+    for v in c:
+        p = int(t.parent[v])
+        if p != NONE:
+            (cx, cy, cz), d = lod.node_origin(t, p)
+            side = 2.0 ** -d
+            assert all(cc * side <= 0.30 <= (cc + 1) * side for cc in (cx, cy, cz))
