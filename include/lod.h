@@ -1,0 +1,251 @@
+/*
+ * lod.h -- C ABI of liblod.so: octree level-of-detail build and point splat
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Szalay, Springel, Lemson, "GPU-Based Interactive Visualization of
+ * Billion Point Cosmological Simulations" (arXiv:0811.2055).  The octree
+ * paragraph defines the structure: a spatial octree in which all data of a
+ * node or leaf is represented by at most n points, surplus points being
+ * thinned by a density-weighted random subselection, children holding the
+ * parent's data at eight times the detail.  The quantisation paragraph
+ * stores every coordinate in 2 bytes spanning the containing block.  The
+ * rendering paragraph draws each point as a smeared blob; the block-choice
+ * paragraph draws near regions from deep in the tree and far ones from
+ * shallow nodes.
+ *
+ * Conventions shared by every entry point:
+ *  - Every pointer named "device" is GPU memory owned by the caller; the
+ *    library allocates nothing and keeps no state between calls.  Each call
+ *    only enqueues work on `stream` (a hipStream_t; NULL = the null stream)
+ *    and returns; results are valid once the stream has reached them.
+ *  - Arguments are checked on the host before anything is enqueued; a bad
+ *    argument returns LOD_EINVAL (or LOD_EUNSUPPORTED / LOD_ECAPACITY) and
+ *    enqueues nothing.  Data-dependent errors found on the device (a
+ *    position outside [0,1] or NaN, a negative or NaN mass, an output
+ *    capacity exceeded) are reported through the tree's device status word
+ *    (counts[2], LOD_STATUS_* bits); outputs are undefined when it is not 0.
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef LOD_H
+#define LOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LOD_OK = 0,
+  LOD_EINVAL = -1,        /* bad argument (null pointer, out-of-range parameter) */
+  LOD_EDOMAIN = -2,       /* input outside the method's domain (host-detected) */
+  LOD_ENOMEM = -3,        /* workspace smaller than the plan requires */
+  LOD_EDEVICE = -4,       /* a HIP call failed (launch error, no device) */
+  LOD_ECAPACITY = -5,     /* an output array is smaller than its bound */
+  LOD_EUNSUPPORTED = -6   /* a valid request this build does not handle */
+} lod_status;
+
+/* device status word bits (lod_tree.counts[2]) */
+#define LOD_STATUS_DOMAIN   1u   /* a position outside [0,1]/NaN or a mass < 0/NaN */
+#define LOD_STATUS_CAPACITY 2u   /* node or point capacity exceeded */
+#define LOD_STATUS_OFFSETS  4u   /* snapshot offsets not monotone / not ending at N */
+
+#define LOD_NONE 0xFFFFFFFFu     /* "no node" in parent / first_child */
+
+typedef void *lod_stream_t;      /* hipStream_t */
+
+/* Build parameters.  n: maximum points stored per node (the paper uses
+ * 16000).  max_depth D in [0,10]: leaves are at depth <= D, the root at 0.
+ * density_level L in [0,D]: the density weight of a particle is the number
+ * of particles in its depth-L cell.  alpha in {-1,0,+1}: the keep
+ * probability grows with density^alpha.  seed: Philox4x32-10 key.
+ * mode: 0 = one selection launch per node (reference schedule; reads the
+ *           level sizes back to the host, so it synchronises the stream),
+ *       1 = one selection launch per level over all of its nodes.
+ * All modes produce identical bytes. */
+typedef struct {
+  uint32_t n;
+  uint32_t max_depth;
+  uint32_t density_level;
+  int32_t alpha;
+  uint64_t seed;
+  uint32_t mode;
+  uint32_t select_threads;   /* 0 = tuned default; else 64..1024, multiple of 64 */
+} lod_params;
+
+/* Particle input, structure of arrays, all device float32 [n_particles].
+ * Positions must lie in [0,1]; masses >= 0.  A batch of snapshots is
+ * concatenated; snap_offsets (device, uint64 [n_snapshots+1], first 0,
+ * non-decreasing, last n_particles) delimits them, or is NULL for a single
+ * snapshot.  A particle's id is its index within its snapshot.  Each
+ * snapshot gets its own tree; the snapshot index is prefixed to the keys,
+ * enters the Philox counter, and the forest is stored breadth first over
+ * all snapshots. */
+typedef struct {
+  const float *x, *y, *z, *mass;
+  uint64_t n_particles;
+  const uint64_t *snap_offsets;
+  uint32_t n_snapshots;
+} lod_input;
+
+/* Output tree, all device arrays owned by the caller.
+ * Node table (node_capacity entries, breadth-first order, Morton order
+ * within a level): prefix = Morton key of the node's cell at its depth with
+ * the snapshot index above it; depth; parent (LOD_NONE for roots);
+ * first_child (LOD_NONE for leaves; children are contiguous, ascending
+ * octant); child_mask (bit o set when octant o exists); part_begin /
+ * part_count = the node's range in Morton-sorted particle order; pt_begin /
+ * pt_count = its stored points; node_mass = float64 sum of its particles'
+ * masses.
+ * Stored points (point_capacity entries, grouped by node in node order,
+ * ascending sorted position within a node): pt_id = particle id within its
+ * snapshot; qx,qy,qz = min(floor(a 2^(d+16)) - (c_d << 16), 65535) relative
+ * to the storing node's cell c_d at depth d; pt_mass = stored float32 mass.
+ * counts: device uint64[3] = {n_nodes, n_points, status bits}. */
+typedef struct {
+  uint64_t *prefix;
+  uint8_t *depth;
+  uint32_t *parent;
+  uint32_t *first_child;
+  uint8_t *child_mask;
+  uint64_t *part_begin;
+  uint64_t *part_count;
+  uint64_t *pt_begin;
+  uint32_t *pt_count;
+  double *node_mass;
+  uint32_t *pt_id;
+  uint16_t *qx, *qy, *qz;
+  float *pt_mass;
+  uint64_t node_capacity, point_capacity;
+  uint64_t *counts;
+} lod_tree;
+
+/* Camera.  projection 0: orthographic along +z onto the xy face of the unit
+ * cube, u = x W, v = y H.  projection 1: perspective from pos with the
+ * orthonormal basis (right, up, fwd), focal length F in pixels, points with
+ * camera depth <= near_z culled; u = F xc/zc + W/2, v = F yc/zc + H/2.
+ * Image row j covers v in [j, j+1), column i covers u in [i, i+1). */
+typedef struct {
+  uint32_t projection;
+  uint32_t W, H;
+  float pos[3], right[3], up[3], fwd[3];
+  float F, near_z;
+} lod_camera;
+
+/* Gaussian blob of standard deviation sigma_px pixels, truncated to the
+ * square |ox|,|oy| <= radius_sigmas * sigma_px, normalised by 1/(2 pi s^2).
+ * sigma_px in (0, 8], radius_sigmas in (0, 6]. */
+typedef struct {
+  float sigma_px;
+  float radius_sigmas;
+} splat_params;
+
+/* ---- level-of-detail build ------------------------------------------- */
+
+/* Host only; no device work.  Returns the workspace size lod_build needs and
+ * upper bounds on the node and point counts:
+ *   nodes  <= n_snapshots + 8 D floor(N / (n+1))
+ *   points <= N + n D floor(N / (n+1)).
+ * Errors: LOD_EINVAL for null pointers or parameters out of range,
+ * LOD_EUNSUPPORTED when 3D key bits plus snapshot bits exceed 32 or a
+ * snapshot could hold 2^31 particles or more. */
+lod_status lod_build_plan(const lod_input *in, const lod_params *p,
+                          size_t *workspace_bytes, uint64_t *node_cap_bound,
+                          uint64_t *point_cap_bound);
+
+/* Build the tree of `in` into `out` (octree paragraph; quantisation
+ * paragraph).  Steps, all on the device: cell keys and 16-bit fractional
+ * positions; stable LSD radix sort of (key, id, position, mass); node
+ * table level by level; density weights; Philox draws and integer
+ * selection keys; per node holding more than n particles, the n smallest
+ * (key, id) taken bottom up from the children's n+1 smallest; float64
+ * mass renormalisation; 16-bit quantisation; output.  No host
+ * synchronisation; safe to capture in a HIP graph.  workspace: device,
+ * >= the planned size, 256-byte aligned.  LOD_ECAPACITY when
+ * out->node_capacity or point_capacity is below the plan's bound. */
+lod_status lod_build(const lod_input *in, const lod_params *p, void *workspace,
+                     size_t workspace_bytes, lod_tree *out, lod_stream_t stream);
+
+/* ---- view-dependent cut (block-choice paragraph) ---------------------- */
+
+/* Workspace bytes lod_select needs for a tree of node_capacity nodes. */
+lod_status lod_select_plan(uint64_t node_capacity, size_t *workspace_bytes);
+
+/* Choose the nodes to draw for `cam`: from each root, descend while the node
+ * has children and either the camera is inside its cube (perspective only)
+ * or its projected point spacing exceeds tau_px pixels; spacing of a depth-d
+ * node is W 2^-d / n^(1/3) (orthographic) or F 2^-d / (n^(1/3) dist),
+ * dist = |node centre - cam.pos| (float64).  Writes the chosen node indices
+ * in node order to node_ids (device, cap entries) and their count to
+ * *n_selected (device uint64).  The tree is read on the device; its node
+ * count comes from tree->counts.  Status bit LOD_STATUS_CAPACITY is set in
+ * tree->counts[2] if more than cap nodes are chosen. */
+lod_status lod_select(const lod_tree *tree, const lod_camera *cam, float tau_px,
+                      uint32_t n, uint32_t *node_ids, uint64_t cap,
+                      uint64_t *n_selected, void *workspace, size_t workspace_bytes,
+                      lod_stream_t stream);
+
+/* ---- additive point splat (rendering paragraph) ----------------------- */
+
+/* Workspace bytes for splatting up to max_points points with cam/sp. */
+lod_status splat_plan(uint64_t max_points, const lod_camera *cam, const splat_params *sp,
+                      size_t *workspace_bytes);
+
+/* image[j*W + i] = sum_k m_k exp(-(ox^2+oy^2)/(2 s^2)) / (2 pi s^2) over
+ * points whose truncated blob covers pixel (i,j); ox = fl(u - (i+1/2)),
+ * oy = fl(v - (j+1/2)) in float32 from the pinned projection sequence
+ * (no fused multiply-add); sums accumulated in float32 with compensation.
+ * x,y,z,m: device float32 [count]; image: device float32 [H*W], overwritten. */
+lod_status splat_render(const float *x, const float *y, const float *z, const float *m,
+                        uint64_t count, const lod_camera *cam, const splat_params *sp,
+                        void *workspace, size_t workspace_bytes, float *image,
+                        lod_stream_t stream);
+
+/* Workspace bytes for splat_render_lod on a tree of node_capacity nodes
+ * drawing at most max_points points. */
+lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,
+                          const splat_params *sp, size_t *workspace_bytes);
+
+/* Render the stored points of the nodes node_ids[0 .. *n_ids) (device
+ * arrays, count on the device) of `tree`, decoding each point from its
+ * node: a = float32 nearest (c 2^16 + q + 1/2) 2^-(d+16).  max_points bounds
+ * the points drawn (workspace sizing); more sets LOD_STATUS_CAPACITY. */
+lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids,
+                            const uint64_t *n_ids, uint64_t max_points,
+                            const lod_camera *cam, const splat_params *sp,
+                            void *workspace, size_t workspace_bytes, float *image,
+                            lod_stream_t stream);
+
+/* Adjoint of splat_render: given dL/dimage (device float32 [H*W]) write
+ * dL/dm (device float32 [count]) and dL/dx, dL/dy, dL/dz (device float32
+ * [count] each; any of them may be NULL to skip).  The derivative of the
+ * truncation indicator is taken as zero.  Culled points get zero. */
+lod_status splat_render_backward(const float *x, const float *y, const float *z,
+                                 const float *m, uint64_t count, const lod_camera *cam,
+                                 const splat_params *sp, const float *grad_image,
+                                 float *grad_m, float *grad_x, float *grad_y,
+                                 float *grad_z, lod_stream_t stream);
+
+/* ---- introspection ----------------------------------------------------- */
+
+/* Device pointers into a lod_build workspace, valid after a build with the
+ * same input sizes and parameters.  which: 0 sorted keys (uint32, snapshot
+ * bits above 3D key bits), 1 sorted particle index (uint32, global), 2
+ * density w (uint32, sorted order), 3 selection key K (uint64, sorted
+ * order), 4 per-node witness sorted position (uint32, LOD_NONE if none).
+ * For tests and diagnostics. */
+lod_status lod_workspace_view(const lod_input *in, const lod_params *p, void *workspace,
+                              uint32_t which, void **device_ptr, uint64_t *count);
+
+/* Static description of an error code. */
+const char *lod_status_string(lod_status s);
+
+/* Library version string. */
+const char *lod_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOD_H */

@@ -1,0 +1,196 @@
+// C ABI of liblod.so: host-side argument checks, workspace plans and launch
+// sequencing.  Every check runs before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "lod.h"
+#include "lod_internal.hpp"
+
+namespace {
+
+lod_status check_params(const lod_input *in, const lod_params *p) {
+  if (!in || !p) return LOD_EINVAL;
+  if (p->n < 1) return LOD_EINVAL;
+  if (p->max_depth > 10) return LOD_EINVAL;
+  if (p->density_level > p->max_depth) return LOD_EINVAL;
+  if (p->alpha < -1 || p->alpha > 1) return LOD_EINVAL;
+  if (p->mode > 1) return LOD_EINVAL;
+  if (p->select_threads && (p->select_threads % 64 || p->select_threads < 64 || p->select_threads > 1024))
+    return LOD_EINVAL;
+  const uint32_t ns = in->snap_offsets ? in->n_snapshots : 1;
+  if (in->snap_offsets && in->n_snapshots < 1) return LOD_EINVAL;
+  if (lodh::key_bits(*p, ns) > 32) return LOD_EUNSUPPORTED;
+  // sorted positions are 32-bit; a single snapshot's ids must stay below 2^31
+  if (in->n_particles >= 0xFFFFFFFFull) return LOD_EUNSUPPORTED;
+  if (!in->snap_offsets && in->n_particles >= (1ull << 31)) return LOD_EUNSUPPORTED;
+  return LOD_OK;
+}
+
+lod_status check_inputs(const lod_input *in, const lod_params *p) {
+  lod_status s = check_params(in, p);
+  if (s != LOD_OK) return s;
+  if (in->n_particles && (!in->x || !in->y || !in->z || !in->mass)) return LOD_EINVAL;
+  return LOD_OK;
+}
+
+bool check_camera(const lod_camera *c, const splat_params *sp) {
+  if (!c || !sp) return false;
+  if (c->projection > 1 || c->W == 0 || c->H == 0 || c->W > 16384 || c->H > 16384) return false;
+  if (!(sp->sigma_px > 0.0f && sp->sigma_px <= 8.0f)) return false;
+  if (!(sp->radius_sigmas > 0.0f && sp->radius_sigmas <= 6.0f)) return false;
+  if (c->projection == 1) {
+    if (!(c->near_z > 0.0f) || !std::isfinite(c->F) || !(c->F > 0.0f)) return false;
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(c->pos[i]) || !std::isfinite(c->right[i]) || !std::isfinite(c->up[i]) ||
+          !std::isfinite(c->fwd[i]))
+        return false;
+  }
+  return true;
+}
+
+bool tree_arrays_ok(const lod_tree *t) {
+  return t && t->prefix && t->depth && t->parent && t->first_child && t->child_mask && t->part_begin &&
+         t->part_count && t->pt_begin && t->pt_count && t->node_mass && t->pt_id && t->qx && t->qy && t->qz &&
+         t->pt_mass && t->counts;
+}
+
+}  // namespace
+
+extern "C" {
+
+lod_status lod_build_plan(const lod_input *in, const lod_params *p, size_t *workspace_bytes,
+                          uint64_t *node_cap_bound, uint64_t *point_cap_bound) {
+  if (!workspace_bytes || !node_cap_bound || !point_cap_bound) return LOD_EINVAL;
+  lod_status s = check_params(in, p);
+  if (s != LOD_OK) return s;
+  const uint32_t ns = in->snap_offsets ? in->n_snapshots : 1;
+  lodh::BuildLayout L = lodh::build_layout(in->n_particles, *p, ns);
+  *workspace_bytes = L.total;
+  *node_cap_bound = L.node_cap;
+  *point_cap_bound = L.point_cap;
+  return LOD_OK;
+}
+
+lod_status lod_build(const lod_input *in, const lod_params *p, void *workspace, size_t workspace_bytes,
+                     lod_tree *out, lod_stream_t stream) {
+  lod_status s = check_inputs(in, p);
+  if (s != LOD_OK) return s;
+  if (!tree_arrays_ok(out) || !workspace) return LOD_EINVAL;
+  if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
+  const uint32_t ns = in->snap_offsets ? in->n_snapshots : 1;
+  lodh::BuildLayout L = lodh::build_layout(in->n_particles, *p, ns);
+  if (workspace_bytes < L.total) return LOD_ENOMEM;
+  if (out->node_capacity < L.node_cap || out->point_capacity < L.point_cap) return LOD_ECAPACITY;
+  return lodh::launch_build(*in, *p, workspace, L, *out, (hipStream_t)stream);
+}
+
+lod_status lod_select_plan(uint64_t node_capacity, size_t *workspace_bytes) {
+  if (!workspace_bytes) return LOD_EINVAL;
+  *workspace_bytes = lodh::cut_workspace(node_capacity);
+  return LOD_OK;
+}
+
+lod_status lod_select(const lod_tree *tree, const lod_camera *cam, float tau_px, uint32_t n, uint32_t *node_ids,
+                      uint64_t cap, uint64_t *n_selected, void *workspace, size_t workspace_bytes,
+                      lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !cam || !node_ids || !n_selected || !workspace) return LOD_EINVAL;
+  if (n < 1 || !(tau_px > 0.0f) || !std::isfinite(tau_px) || cap == 0) return LOD_EINVAL;
+  splat_params dummy{1.0f, 3.0f};
+  if (!check_camera(cam, &dummy)) return LOD_EINVAL;
+  if (workspace_bytes < lodh::cut_workspace(tree->node_capacity)) return LOD_ENOMEM;
+  return lodh::launch_cut(*tree, *cam, tau_px, n, node_ids, cap, n_selected, workspace, (hipStream_t)stream);
+}
+
+lod_status splat_plan(uint64_t max_points, const lod_camera *cam, const splat_params *sp, size_t *workspace_bytes) {
+  if (!workspace_bytes || !check_camera(cam, sp)) return LOD_EINVAL;
+  lodh::SplatLayout L;
+  lod_status s = lodh::splat_layout(max_points, *cam, *sp, L);
+  if (s != LOD_OK) return s;
+  *workspace_bytes = L.total;
+  return LOD_OK;
+}
+
+lod_status splat_render(const float *x, const float *y, const float *z, const float *m, uint64_t count,
+                        const lod_camera *cam, const splat_params *sp, void *workspace, size_t workspace_bytes,
+                        float *image, lod_stream_t stream) {
+  if (!check_camera(cam, sp) || !image || !workspace) return LOD_EINVAL;
+  if (count && (!x || !y || !z || !m)) return LOD_EINVAL;
+  if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
+  lodh::SplatLayout L;
+  lod_status s = lodh::splat_layout(count, *cam, *sp, L);
+  if (s != LOD_OK) return s;
+  if (workspace_bytes < L.total) return LOD_ENOMEM;
+  return lodh::launch_splat(x, y, z, m, count, nullptr, *cam, *sp, workspace, L, image, nullptr,
+                            (hipStream_t)stream);
+}
+
+lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                            uint64_t max_points, const lod_camera *cam, const splat_params *sp, void *workspace,
+                            size_t workspace_bytes, float *image, lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !node_ids || !n_ids || !check_camera(cam, sp) || !image || !workspace)
+    return LOD_EINVAL;
+  if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
+  lodh::LodDrawLayout D = lodh::lod_draw_layout(tree->node_capacity, max_points);
+  lodh::SplatLayout L;
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L);
+  if (s != LOD_OK) return s;
+  if (workspace_bytes < D.total + L.total) return LOD_ENOMEM;
+  s = lodh::launch_lod_gather(*tree, node_ids, n_ids, workspace, D, (hipStream_t)stream);
+  if (s != LOD_OK) return s;
+  char *W = (char *)workspace;
+  return lodh::launch_splat((const float *)(W + D.x), (const float *)(W + D.y), (const float *)(W + D.z),
+                            (const float *)(W + D.m), D.max_points, (const uint64_t *)(W + D.count), *cam, *sp,
+                            W + D.total, L, image, tree->counts + 2, (hipStream_t)stream);
+}
+
+lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,
+                          const splat_params *sp, size_t *workspace_bytes) {
+  if (!workspace_bytes || !check_camera(cam, sp)) return LOD_EINVAL;
+  lodh::LodDrawLayout D = lodh::lod_draw_layout(node_capacity, max_points);
+  lodh::SplatLayout L;
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L);
+  if (s != LOD_OK) return s;
+  *workspace_bytes = D.total + L.total;
+  return LOD_OK;
+}
+
+lod_status splat_render_backward(const float *x, const float *y, const float *z, const float *m, uint64_t count,
+                                 const lod_camera *cam, const splat_params *sp, const float *grad_image,
+                                 float *grad_m, float *grad_x, float *grad_y, float *grad_z, lod_stream_t stream) {
+  if (!check_camera(cam, sp) || !grad_image || !grad_m) return LOD_EINVAL;
+  if (count && (!x || !y || !z || !m)) return LOD_EINVAL;
+  return lodh::launch_splat_backward(x, y, z, m, count, *cam, *sp, grad_image, grad_m, grad_x, grad_y, grad_z,
+                                     (hipStream_t)stream);
+}
+
+lod_status lod_workspace_view(const lod_input *in, const lod_params *p, void *workspace, uint32_t which,
+                              void **device_ptr, uint64_t *count) {
+  lod_status s = check_params(in, p);
+  if (s != LOD_OK) return s;
+  if (!workspace || !device_ptr || !count || which > 4) return LOD_EINVAL;
+  const uint32_t ns = in->snap_offsets ? in->n_snapshots : 1;
+  lodh::BuildLayout L = lodh::build_layout(in->n_particles, *p, ns);
+  const int kb = lodh::key_bits(*p, ns);
+  const int passes = kb > 8 ? (kb + 7) / 8 : 1;
+  *device_ptr = lodh::workspace_view(workspace, L, which, in->n_particles, passes, count);
+  return LOD_OK;
+}
+
+const char *lod_status_string(lod_status s) {
+  switch (s) {
+    case LOD_OK: return "ok";
+    case LOD_EINVAL: return "invalid argument";
+    case LOD_EDOMAIN: return "input outside the method's domain";
+    case LOD_ENOMEM: return "workspace too small";
+    case LOD_EDEVICE: return "HIP call failed";
+    case LOD_ECAPACITY: return "output capacity below the bound";
+    case LOD_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char *lod_version(void) { return "liblod 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,1087 @@
+// Octree level-of-detail build for gfx950 (octree and quantisation
+// paragraphs of arXiv:0811.2055; readings fixed in the oracle's docstrings).
+//
+// Data path (all device-resident, one stream, no host synchronisation):
+//   keygen     x,y,z -> sort key (snapshot | 3D-bit Morton), 48-bit fraction,
+//              domain check, digit-0 tile histograms
+//   radix sort stable LSD, 8-bit digits, reduce-then-scan: per-tile digit
+//              histograms, one device scan, scatter with wave-ballot ranks and
+//              LDS-staged coalesced writes; payload (id, fraction, mass) rides
+//              along so nothing is gathered at random afterwards
+//   density    run lengths of equal depth-L cells (block max/min scans), then
+//              Philox U and the integer selection key K per sorted position
+//   tree       level by level: octant boundaries by binary search, one-block
+//              compaction of the next level
+//   leaves     float64 node masses; leaves holding <= n copy their particles
+//   selection  bottom up, per node holding > n: radix select of the (n+1)-th
+//              smallest (K, id) over the children's top lists or own range,
+//              then an order-preserving compaction; float64 renormalisation,
+//              16-bit quantisation and output
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "lod.h"
+#include "lod_device.hpp"
+#include "lod_internal.hpp"
+#include "lod_scan.hpp"
+
+using namespace lodk;
+
+namespace {
+
+constexpr int TB = 256;          // threads per block for streaming kernels
+constexpr int ITEMS = 16;        // elements per thread
+constexpr int TILE = TB * ITEMS; // elements per tile (4096)
+constexpr int RADIX = 256;
+constexpr uint32_t STATUS_INTERNAL = 8u;
+
+// ---------------------------------------------------------------------------
+// parameters passed by value to kernels
+
+struct BuildArgs {
+  uint64_t N;
+  uint32_t n;
+  int D;
+  int shift_rho;       // 3 (D - L)
+  int alpha;
+  uint64_t seed;
+  uint32_t n_snap;
+  const uint64_t *snap_off;   // device [n_snap+1] or null
+  uint64_t node_cap, point_cap;
+  uint64_t *counts;           // device [3]
+};
+
+__device__ __forceinline__ uint32_t snapshot_of(const BuildArgs &a, uint64_t e) {
+  if (a.n_snap <= 1 || !a.snap_off) return 0;
+  // largest s with snap_off[s] <= e
+  uint32_t lo = 0, hi = a.n_snap;   // answer in [0, n_snap)
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a.snap_off[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t local_id(const BuildArgs &a, uint32_t snap, uint32_t gidx) {
+  return (a.n_snap <= 1 || !a.snap_off) ? (uint64_t)gidx : (uint64_t)gidx - a.snap_off[snap];
+}
+
+// ---------------------------------------------------------------------------
+// snapshot offsets check (one block)
+
+__global__ void k_check_offsets(BuildArgs a) {
+  if (!a.snap_off || a.n_snap <= 1) return;
+  bool bad = false;
+  for (uint32_t s = threadIdx.x; s < a.n_snap; s += blockDim.x) {
+    uint64_t lo = a.snap_off[s], hi = a.snap_off[s + 1];
+    if (hi < lo || hi - lo >= (1ull << 31)) bad = true;
+  }
+  if (threadIdx.x == 0 && (a.snap_off[0] != 0 || a.snap_off[a.n_snap] != a.N)) bad = true;
+  if (bad) atomicOr((unsigned long long *)&a.counts[2], (unsigned long long)LOD_STATUS_OFFSETS);
+}
+
+// ---------------------------------------------------------------------------
+// keygen: key, 48-bit fraction, domain check, digit-0 tile histogram
+
+__global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, const float *__restrict__ y,
+                                               const float *__restrict__ z, const float *__restrict__ m,
+                                               BuildArgs a, uint32_t *__restrict__ key,
+                                               uint64_t *__restrict__ lo, uint32_t *__restrict__ thist,
+                                               uint64_t n_tiles) {
+  __shared__ uint32_t hist[RADIX];
+  __shared__ int bad;
+  for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const uint64_t tile = blockIdx.x;
+  const int D = a.D;
+  const uint32_t cmask = (1u << D) - 1u;
+  bool my_bad = false;
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint64_t e = tile * TILE + (uint64_t)i * TB + threadIdx.x;
+    if (e >= a.N) break;
+    uint32_t X, Y, Z;
+    bool ok = fixed_coord(x[e], D, X);
+    ok &= fixed_coord(y[e], D, Y);
+    ok &= fixed_coord(z[e], D, Z);
+    const float me = m[e];
+    ok &= (me >= 0.0f) && (me <= 3.4028235e38f);
+    my_bad |= !ok;
+    const uint32_t cx = (X >> 16) & cmask, cy = (Y >> 16) & cmask, cz = (Z >> 16) & cmask;
+    uint32_t k = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    const uint32_t snap = snapshot_of(a, e);
+    if (a.n_snap > 1) k |= (uint32_t)(((uint64_t)snap << (3 * D)) & 0xFFFFFFFFull);
+    key[e] = k;
+    lo[e] = (uint64_t)(X & 0xFFFFu) | ((uint64_t)(Y & 0xFFFFu) << 16) | ((uint64_t)(Z & 0xFFFFu) << 32);
+    atomicAdd(&hist[k & 0xFFu], 1u);
+  }
+  if (my_bad) bad = 1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < RADIX; i += TB) thist[(uint64_t)i * n_tiles + tile] = hist[i];
+  if (threadIdx.x == 0 && bad)
+    atomicOr((unsigned long long *)&a.counts[2], (unsigned long long)LOD_STATUS_DOMAIN);
+}
+
+// per-tile digit histogram for passes after the first
+__global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key, uint64_t N, int shift,
+                                                uint32_t *__restrict__ thist, uint64_t n_tiles) {
+  __shared__ uint32_t hist[RADIX];
+  for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
+  __syncthreads();
+  const uint64_t tile = blockIdx.x;
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint64_t e = tile * TILE + (uint64_t)i * TB + threadIdx.x;
+    if (e >= N) break;
+    atomicAdd(&hist[(key[e] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RADIX; i += TB) thist[(uint64_t)i * n_tiles + tile] = hist[i];
+}
+
+// Stable scatter of one LSD pass.  Wave w of the block owns tile elements
+// [w*1024, (w+1)*1024); in round r lane l holds element w*1024 + r*64 + l, so
+// element order is (w, r, l).  Ranks within a wave come from 8 ballots (the
+// lanes sharing the digit) and a wave-private LDS counter per digit.
+template <bool FIRST>
+__global__ __launch_bounds__(TB) void k_scatter(uint64_t N, int shift, const uint32_t *__restrict__ thist,
+                                                uint64_t n_tiles,
+                                                const uint32_t *__restrict__ key_in,
+                                                const uint32_t *__restrict__ idx_in,
+                                                const uint64_t *__restrict__ lo_in,
+                                                const float *__restrict__ m_in,
+                                                uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
+                                                uint64_t *__restrict__ lo_out, float *__restrict__ m_out) {
+  constexpr int NW = TB / WAVE;               // 4 waves
+  constexpr int PER_WAVE = TILE / NW;         // 1024
+  constexpr int ROUNDS = PER_WAVE / WAVE;     // 16
+  __shared__ uint32_t wcnt[NW][RADIX];
+  __shared__ uint32_t bin_start[RADIX];       // tile-local start of each digit
+  __shared__ uint32_t gofs[RADIX];            // global start of this tile's digit run
+  __shared__ uint64_t stage[TILE];
+  __shared__ uint32_t tmp[TB / WAVE + 1];
+
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = threadIdx.x / WAVE;
+  const uint64_t tile = blockIdx.x;
+  const uint64_t tbase = tile * TILE;
+  for (int i = threadIdx.x; i < NW * RADIX; i += TB) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+  uint32_t dig[ROUNDS];
+  uint32_t rnk[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
+    const bool valid = e < N;
+    const uint32_t d = valid ? ((key_in[e] >> shift) & 0xFFu) : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    uint32_t old = valid ? wcnt[w][d] : 0u;
+    if (valid && below == 0) wcnt[w][d] = old + cnt;
+    dig[r] = d;
+    rnk[r] = old + below;
+  }
+  __syncthreads();
+  // per digit: wave prefix (in place) and tile total
+  uint32_t tot = 0;
+  if (threadIdx.x < RADIX) {
+    const int d = threadIdx.x;
+    for (int ww = 0; ww < NW; ++ww) {
+      uint32_t c = wcnt[ww][d];
+      wcnt[ww][d] = tot;
+      tot += c;
+    }
+    gofs[d] = thist[(uint64_t)d * n_tiles + tile];
+  }
+  uint32_t dummy;
+  uint32_t st = block_excl_scan<uint32_t>(threadIdx.x < RADIX ? tot : 0u, tmp, dummy);
+  if (threadIdx.x < RADIX) bin_start[threadIdx.x] = st;
+  __syncthreads();
+
+  // tile-local slot of each element
+  uint32_t slot[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) slot[r] = bin_start[dig[r]] + wcnt[w][dig[r]] + rnk[r];
+  const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, N - tbase);
+
+  // stage keys; derive each output slot's global position
+  uint64_t gpos[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
+    if (e < N) stage[slot[r]] = key_in[e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+    gpos[i] = ~0ull;
+    if (s < tile_n) {
+      const uint32_t k = (uint32_t)stage[s];
+      const uint32_t d = (k >> shift) & 0xFFu;
+      gpos[i] = (uint64_t)gofs[d] + (s - bin_start[d]);
+      key_out[gpos[i]] = k;
+    }
+  }
+  __syncthreads();
+  // ids
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
+    if (e < N) stage[slot[r]] = FIRST ? (uint64_t)e : (uint64_t)idx_in[e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+    if (s < tile_n) idx_out[gpos[i]] = (uint32_t)stage[s];
+  }
+  __syncthreads();
+  // fractions
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
+    if (e < N) stage[slot[r]] = lo_in[e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+    if (s < tile_n) lo_out[gpos[i]] = stage[s];
+  }
+  __syncthreads();
+  // masses
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
+    if (e < N) stage[slot[r]] = (uint64_t)__float_as_uint(m_in[e]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+    if (s < tile_n) m_out[gpos[i]] = __uint_as_float((uint32_t)stage[s]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// density (run length of equal depth-L cells) and selection keys
+
+template <bool MAXOP>
+__device__ __forceinline__ uint64_t block_incl_scan_op(uint64_t v, uint64_t *tmp) {
+  // inclusive max- or min-scan over threads in index order
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    uint64_t t = __shfl_up(v, o, WAVE);
+    if (lane >= o) v = MAXOP ? max(v, t) : min(v, t);
+  }
+  if (lane == WAVE - 1) tmp[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t run = MAXOP ? 0ull : ~0ull;
+    for (int ww = 0; ww < nw; ++ww) {
+      uint64_t t = tmp[ww];
+      tmp[ww] = run;
+      run = MAXOP ? max(run, t) : min(run, t);
+    }
+  }
+  __syncthreads();
+  uint64_t pre = tmp[wid];
+  __syncthreads();
+  return MAXOP ? max(pre, v) : min(pre, v);
+}
+
+// Blocked layout: thread t owns tile elements [t*ITEMS, t*ITEMS+ITEMS).  A
+// run's start is the largest run-start position at or before an element, its
+// end the smallest run-end position after it; both come from a thread-local
+// pass plus a block scan, and runs crossing the tile edge are closed by a
+// binary search over the sorted keys.
+__global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__restrict__ skey,
+                                                const uint32_t *__restrict__ sidx,
+                                                uint32_t *__restrict__ w_out, uint64_t *__restrict__ K_out) {
+  __shared__ uint32_t cell[TILE + 2];     // cell[i+1] = cell of element base+i
+  __shared__ uint64_t tmp[TB / WAVE + 1];
+  __shared__ uint64_t incl_max[TB];
+  __shared__ uint64_t rev_min[TB];
+  __shared__ uint64_t first_start, last_end;
+  const uint64_t N = a.N;
+  const uint64_t base = (uint64_t)blockIdx.x * TILE;
+  const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, N - base);
+  const int sh = a.shift_rho;
+  for (int i = threadIdx.x; i < TILE + 2; i += TB) {
+    const int64_t e = (int64_t)base + i - 1;
+    uint32_t c = 0xFFFFFFFFu;
+    if (e >= 0 && (uint64_t)e < N && i <= (int)tile_n + 1) c = skey[e] >> sh;
+    cell[i] = c;
+  }
+  __syncthreads();
+  const bool has_prev = base > 0;
+  const bool has_next = base + tile_n < N;
+  if (threadIdx.x == 0) {
+    uint64_t s0 = base;
+    if (has_prev && cell[0] == cell[1]) {
+      const uint32_t c = cell[1];
+      uint64_t lo = 0, hi = base;
+      while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if ((skey[mid] >> sh) < c) lo = mid + 1; else hi = mid;
+      }
+      s0 = lo;
+    }
+    first_start = s0;
+    uint64_t e0 = base + tile_n;
+    if (has_next && cell[tile_n] == cell[tile_n + 1]) {
+      const uint32_t c = cell[tile_n];
+      uint64_t lo = base + tile_n, hi = N;
+      while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if ((skey[mid] >> sh) <= c) lo = mid + 1; else hi = mid;
+      }
+      e0 = lo;
+    }
+    last_end = e0;
+  }
+  __syncthreads();
+  const int t0 = threadIdx.x * ITEMS;
+  // run starts: thread-local running max of start positions
+  uint64_t st[ITEMS];
+  uint64_t runmax = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int li = t0 + i;
+    const bool starts = (li == 0) ? (!has_prev || cell[0] != cell[1]) : (cell[li] != cell[li + 1]);
+    if (li < (int)tile_n && starts) runmax = max(runmax, base + li);
+    st[i] = runmax;
+  }
+  incl_max[threadIdx.x] = block_incl_scan_op<true>(runmax, tmp);
+  // run ends: thread-local suffix min of end positions (exclusive end index)
+  uint64_t en[ITEMS];
+  uint64_t runmin = ~0ull;
+#pragma unroll
+  for (int i = ITEMS - 1; i >= 0; --i) {
+    const int li = t0 + i;
+    if (li < (int)tile_n) {
+      if (li == (int)tile_n - 1) runmin = min(runmin, last_end);
+      else if (cell[li + 1] != cell[li + 2]) runmin = min(runmin, base + li + 1);
+    }
+    en[i] = runmin;
+  }
+  __syncthreads();
+  // suffix over threads: thread t scans the value of thread TB-1-t
+  rev_min[threadIdx.x] = runmin;
+  __syncthreads();
+  const uint64_t mirrored = rev_min[TB - 1 - threadIdx.x];
+  __syncthreads();
+  rev_min[threadIdx.x] = block_incl_scan_op<false>(mirrored, tmp);
+  __syncthreads();
+  const uint64_t prev_max = max(first_start, threadIdx.x ? incl_max[threadIdx.x - 1] : 0ull);
+  // min over threads > t == reversed inclusive scan at position TB-2-t
+  const uint64_t next_min = (threadIdx.x < TB - 1) ? rev_min[TB - 2 - threadIdx.x] : ~0ull;
+  const int sdb = 3 * a.D;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int li = t0 + i;
+    if (li >= (int)tile_n) break;
+    const uint64_t e = base + li;
+    const uint64_t rs = max(st[i], prev_max);
+    const uint64_t re = min(en[i], next_min);
+    const uint32_t w = (uint32_t)(re - rs);
+    const uint32_t k = skey[e];
+    const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)k >> sdb) : 0u;
+    const uint64_t U = particle_U(local_id(a, snap, sidx[e]), snap, a.seed);
+    w_out[e] = w;
+    K_out[e] = selection_key(U, w, a.alpha);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tree, level by level
+
+struct TreeArgs {
+  uint64_t *prefix;
+  uint8_t *depth;
+  uint32_t *parent;
+  uint32_t *first_child;
+  uint8_t *child_mask;
+  uint64_t *part_begin;
+  uint64_t *part_count;
+  uint64_t *pt_begin;
+  uint32_t *pt_count;
+  double *node_mass;
+  uint32_t *pt_id;
+  uint16_t *qx, *qy, *qz;
+  float *pt_mass;
+  // workspace
+  uint32_t *lvl;      // [D+3] level starts; lvl[d+1] = end of level d
+  uint32_t *cs;       // [node_cap * 9] octant starts (sorted positions) of internal nodes
+  uint32_t *sel_idx;  // [node_cap] index among selecting nodes of its level, or NONE
+  uint32_t *wit;      // [node_cap] witness sorted position, or NONE
+};
+
+__device__ __forceinline__ void set_status(const BuildArgs &a, uint32_t bits) {
+  atomicOr((unsigned long long *)&a.counts[2], (unsigned long long)bits);
+}
+
+// Roots: one per non-empty snapshot (single block).
+__global__ __launch_bounds__(1024) void k_roots(BuildArgs a, TreeArgs t, const uint32_t *__restrict__ skey) {
+  __shared__ uint32_t tmp[1024 / WAVE + 1];
+  __shared__ uint32_t base_nodes, base_sel;
+  if (threadIdx.x == 0) { base_nodes = 0; base_sel = 0; t.lvl[0] = 0; }
+  __syncthreads();
+  const int D = a.D;
+  for (uint32_t s0 = 0; s0 < a.n_snap; s0 += blockDim.x) {
+    const uint32_t s = s0 + threadIdx.x;
+    uint64_t lo = 0, hi = 0;
+    if (s < a.n_snap) {
+      if (a.n_snap == 1) { lo = 0; hi = a.N; }
+      else {
+        const uint64_t k0 = (uint64_t)s << (3 * D), k1 = (uint64_t)(s + 1) << (3 * D);
+        uint64_t l = 0, h = a.N;
+        while (l < h) { uint64_t mid = l + ((h - l) >> 1); if ((uint64_t)skey[mid] < k0) l = mid + 1; else h = mid; }
+        lo = l; h = a.N;
+        while (l < h) { uint64_t mid = l + ((h - l) >> 1); if ((uint64_t)skey[mid] < k1) l = mid + 1; else h = mid; }
+        hi = l;
+      }
+    }
+    const uint32_t ne = (s < a.n_snap && hi > lo) ? 1u : 0u;
+    const uint32_t se = (ne && hi - lo > a.n) ? 1u : 0u;
+    uint32_t tot_n, tot_s;
+    uint32_t on = block_excl_scan<uint32_t>(ne, tmp, tot_n);
+    uint32_t os = block_excl_scan<uint32_t>(se, tmp, tot_s);
+    if (ne) {
+      const uint32_t v = base_nodes + on;
+      if (v < a.node_cap) {
+        t.prefix[v] = s; t.depth[v] = 0; t.parent[v] = NONE; t.first_child[v] = NONE;
+        t.child_mask[v] = 0; t.part_begin[v] = lo; t.part_count[v] = hi - lo;
+        t.sel_idx[v] = se ? base_sel + os : NONE; t.wit[v] = NONE;
+      } else set_status(a, LOD_STATUS_CAPACITY);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) { base_nodes += tot_n; base_sel += tot_s; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) t.lvl[1] = min((uint64_t)base_nodes, a.node_cap);
+}
+
+// Octant boundaries of the internal nodes of level d: 8 lanes per node.
+__global__ __launch_bounds__(TB) void k_octants(BuildArgs a, TreeArgs t, const uint32_t *__restrict__ skey, int d) {
+  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
+  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const int sh = 3 * (a.D - d - 1);
+  for (uint64_t g = gtid; g < (uint64_t)(e - b) * 8; g += stride) {
+    const uint32_t v = b + (uint32_t)(g >> 3);
+    const uint32_t o = (uint32_t)(g & 7);
+    const uint64_t cnt = t.part_count[v];
+    if (!(cnt > a.n && d < a.D)) continue;
+    const uint64_t lo = t.part_begin[v], hi = lo + cnt;
+    uint64_t start = lo;
+    if (o) {
+      const uint64_t target = ((t.prefix[v] << 3) | o) << sh;
+      uint64_t l = lo, h = hi;
+      while (l < h) { uint64_t mid = l + ((h - l) >> 1); if ((uint64_t)skey[mid] < target) l = mid + 1; else h = mid; }
+      start = l;
+    }
+    t.cs[(uint64_t)v * 9 + o] = (uint32_t)start;
+    if (o == 7) t.cs[(uint64_t)v * 9 + 8] = (uint32_t)hi;
+  }
+}
+
+// Emit level d+1 from level d (single block): child offsets by block scans.
+__global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
+  __shared__ uint32_t tmp[1024 / WAVE + 1];
+  __shared__ uint32_t run_nodes, run_sel;
+  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
+  if (threadIdx.x == 0) { run_nodes = 0; run_sel = 0; }
+  __syncthreads();
+  const uint32_t next_base = e;
+  for (uint32_t v0 = b; v0 < e; v0 += blockDim.x) {
+    const uint32_t v = v0 + threadIdx.x;
+    uint32_t nkids = 0, nsel = 0, mask = 0;
+    uint32_t st[9];
+    if (v < e && t.part_count[v] > a.n && d < a.D) {
+#pragma unroll
+      for (int o = 0; o < 9; ++o) st[o] = t.cs[(uint64_t)v * 9 + o];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const uint32_t c = st[o + 1] - st[o];
+        if (c) { mask |= 1u << o; ++nkids; if (c > a.n) ++nsel; }
+      }
+    }
+    uint32_t tk, ts;
+    const uint32_t ok = block_excl_scan<uint32_t>(nkids, tmp, tk);
+    const uint32_t os = block_excl_scan<uint32_t>(nsel, tmp, ts);
+    if (v < e) {
+      t.child_mask[v] = (uint8_t)mask;
+      if (nkids) {
+        uint32_t c = next_base + run_nodes + ok;
+        uint32_t sidx = run_sel + os;
+        if ((uint64_t)c + nkids > a.node_cap) {
+          set_status(a, LOD_STATUS_CAPACITY);
+          t.first_child[v] = NONE;
+        } else {
+          t.first_child[v] = c;
+          const uint64_t pfx = t.prefix[v] << 3;
+          for (int o = 0; o < 8; ++o) {
+            const uint32_t cnt = st[o + 1] - st[o];
+            if (!cnt) continue;
+            t.prefix[c] = pfx | (uint64_t)o;
+            t.depth[c] = (uint8_t)(d + 1);
+            t.parent[c] = v;
+            t.first_child[c] = NONE;
+            t.child_mask[c] = 0;
+            t.part_begin[c] = st[o];
+            t.part_count[c] = cnt;
+            t.sel_idx[c] = cnt > a.n ? sidx++ : NONE;
+            t.wit[c] = NONE;
+            ++c;
+          }
+        }
+      } else {
+        t.first_child[v] = NONE;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) { run_nodes += tk; run_sel += ts; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    uint64_t end = (uint64_t)next_base + run_nodes;
+    t.lvl[d + 2] = (uint32_t)min(end, a.node_cap);
+  }
+}
+
+// pt_count for every slot < node_cap (0 beyond the node count) and n_nodes.
+__global__ __launch_bounds__(TB) void k_ptcount(BuildArgs a, TreeArgs t, int D) {
+  const uint32_t nn = t.lvl[D + 1];
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.node_cap;
+       v += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t c = 0;
+    if (v < nn) c = (uint32_t)min(t.part_count[v], (uint64_t)a.n);
+    t.pt_count[v] = v < nn ? c : 0u;
+    t.pt_begin[v] = c;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[0] = nn;
+}
+
+__global__ void k_ptfinish(BuildArgs a, TreeArgs t) {
+  // total = last exclusive offset + last count (both over node_cap slots)
+  const uint64_t last = a.node_cap - 1;
+  const uint64_t total = t.pt_begin[last] + t.pt_count[last];
+  a.counts[1] = total;
+  if (total > a.point_cap) set_status(a, LOD_STATUS_CAPACITY);
+}
+
+// ---------------------------------------------------------------------------
+// leaves: float64 node mass; leaves holding <= n copy their particles
+
+struct Sorted {
+  const uint32_t *key;
+  const uint32_t *idx;
+  const uint64_t *lo;
+  const float *m;
+  const uint32_t *w;
+  const uint64_t *K;
+};
+
+__device__ __forceinline__ void write_point(const BuildArgs &a, const TreeArgs &t, const Sorted &s,
+                                            uint64_t pos, uint64_t out, int d, float mass) {
+  const uint32_t k = s.key[pos];
+  const int D = a.D;
+  const uint32_t kk = D ? (k & (uint32_t)((1ull << (3 * D)) - 1)) : 0u;
+  const uint32_t cx = compact3(kk), cy = compact3(kk >> 1), cz = compact3(kk >> 2);
+  const uint64_t l = s.lo[pos];
+  const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)k >> (3 * D)) : 0u;
+  t.pt_id[out] = (uint32_t)local_id(a, snap, s.idx[pos]);
+  t.qx[out] = quant_at(cx, (uint32_t)(l & 0xFFFFu), D, d);
+  t.qy[out] = quant_at(cy, (uint32_t)((l >> 16) & 0xFFFFu), D, d);
+  t.qz[out] = quant_at(cz, (uint32_t)((l >> 32) & 0xFFFFu), D, d);
+  t.pt_mass[out] = mass;
+}
+
+__global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s) {
+  __shared__ double red[TB / WAVE + 1];
+  const uint32_t nn = t.lvl[a.D + 1];
+  const bool cap_ok = a.counts[1] <= a.point_cap;
+  for (uint32_t v = blockIdx.x; v < nn; v += gridDim.x) {
+    if (t.first_child[v] != NONE) continue;
+    const uint64_t b = t.part_begin[v], c = t.part_count[v];
+    double acc = 0.0;
+    for (uint64_t i = threadIdx.x; i < c; i += TB) acc += (double)s.m[b + i];
+    const double M = block_reduce_sum<double>(acc, red);
+    if (threadIdx.x == 0) t.node_mass[v] = M;
+    if (c <= a.n && cap_ok) {
+      const uint64_t ob = t.pt_begin[v];
+      const int d = t.depth[v];
+      for (uint64_t i = threadIdx.x; i < c; i += TB) write_point(a, t, s, b + i, ob + i, d, s.m[b + i]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, int d) {
+  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
+  for (uint32_t v = b + blockIdx.x * blockDim.x + threadIdx.x; v < e; v += gridDim.x * blockDim.x) {
+    const uint32_t fc = t.first_child[v];
+    if (fc == NONE) continue;
+    const int nk = __popc((uint32_t)t.child_mask[v]);
+    double M = 0.0;
+    for (int k = 0; k < nk; ++k) M += t.node_mass[fc + k];
+    t.node_mass[v] = M;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// selection: per node holding > n particles, the n+1 smallest (K, id)
+
+constexpr int SMALL = 512;
+
+struct SelArgs {
+  const uint32_t *top_prev;   // children's lists (level d+1)
+  uint32_t *top_cur;          // this level's lists
+  uint32_t n_minus_1;         // N - 1
+};
+
+struct Segs {
+  uint32_t nseg;
+  uint64_t base[9];   // start sorted position (range) or list offset (list)
+  uint32_t len[9];
+  uint32_t is_list[9];
+};
+
+// Candidate j of segment k as a sorted position; list entries are clamped
+// below N so that a list left unwritten by a failed child cannot send a read
+// out of bounds (the failure itself is reported through the status word).
+__device__ __forceinline__ uint32_t seg_pos(const Segs &g, const SelArgs &sa, int k, uint32_t j) {
+  return g.is_list[k] ? min(sa.top_prev[g.base[k] + j], sa.n_minus_1) : (uint32_t)(g.base[k] + j);
+}
+
+// Selects for node v; must be called by the whole block.  BS = blockDim.x.
+__device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
+                            uint32_t v, int d) {
+  __shared__ Segs g;
+  __shared__ uint32_t hist[RADIX];
+  __shared__ uint64_t ck[SMALL];
+  __shared__ uint32_t cidx[SMALL];
+  __shared__ uint32_t cpos[SMALL];
+  __shared__ uint32_t ccount;
+  __shared__ uint64_t red64[1024 / WAVE + 1];
+  __shared__ uint32_t red32[1024 / WAVE + 1];
+  __shared__ uint64_t sh_kt;
+  __shared__ uint32_t sh_it, sh_pt;
+  __shared__ uint32_t sh_b, sh_below, sh_cnt;
+  const uint32_t n = a.n;
+  const int BS = blockDim.x;
+  if (threadIdx.x == 0) {
+    const uint32_t fc = t.first_child[v];
+    uint32_t ns = 0;
+    if (fc == NONE) {
+      g.base[0] = t.part_begin[v]; g.len[0] = (uint32_t)t.part_count[v]; g.is_list[0] = 0; ns = 1;
+    } else {
+      const int nk = __popc((uint32_t)t.child_mask[v]);
+      for (int k = 0; k < nk; ++k) {
+        const uint32_t u = fc + k;
+        if (t.part_count[u] > n) {
+          g.base[ns] = (uint64_t)t.sel_idx[u] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
+        } else {
+          g.base[ns] = t.part_begin[u]; g.len[ns] = (uint32_t)t.part_count[u]; g.is_list[ns] = 0;
+        }
+        ++ns;
+      }
+    }
+    g.nseg = ns;
+  }
+  __syncthreads();
+  const int nseg = (int)g.nseg;
+
+  // pass 0: largest K among the candidates
+  uint64_t mx = 0;
+  for (int k = 0; k < nseg; ++k)
+    for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) mx = max(mx, s.K[seg_pos(g, sa, k, j)]);
+  {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) mx = max(mx, (uint64_t)__shfl_xor(mx, o, WAVE));
+    if (lane == 0) red64[wid] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t r = 0;
+      for (int ww = 0; ww < BS / WAVE; ++ww) r = max(r, red64[ww]);
+      red64[0] = r;
+    }
+    __syncthreads();
+    mx = red64[0];
+    __syncthreads();
+  }
+  // radix select over K, then over id among equal K
+  int kshift = mx ? 64 - __clzll(mx) : 0;   // K >> kshift == kp for all candidates
+  uint64_t kp = 0;
+  int phase = 0;                             // 0: K bits, 1: id bits
+  int ishift = 32;
+  uint32_t ip = 0;
+  uint32_t r = n;                            // 0-based rank of the witness among in-play
+  uint32_t inplay = 0;
+  for (int k = 0; k < nseg; ++k) inplay += g.len[k];
+  while (inplay > SMALL && !(phase == 1 && ishift == 0)) {
+    if (phase == 0 && kshift == 0) { phase = 1; continue; }
+    const int wb = phase == 0 ? min(8, kshift) : min(8, ishift);
+    const int sft = (phase == 0 ? kshift : ishift) - wb;
+    for (int i = threadIdx.x; i < RADIX; i += BS) hist[i] = 0;
+    __syncthreads();
+    for (int k = 0; k < nseg; ++k)
+      for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) {
+        const uint32_t p = seg_pos(g, sa, k, j);
+        const uint64_t K = s.K[p];
+        bool match;
+        uint32_t dg;
+        if (phase == 0) {
+          match = (kshift >= 64) ? true : ((K >> kshift) == kp);
+          dg = (uint32_t)((K >> sft) & ((1u << wb) - 1));
+        } else {
+          const uint32_t id = s.idx[p];
+          match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
+          dg = (id >> sft) & ((1u << wb) - 1);
+        }
+        if (match) atomicAdd(&hist[dg], 1u);
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t below = 0, bsel = 0, cnt = 0;
+      for (uint32_t b = 0; b < (1u << wb); ++b) {
+        const uint32_t h = hist[b];
+        if (r < below + h) { bsel = b; cnt = h; break; }
+        below += h;
+      }
+      sh_b = bsel; sh_below = below; sh_cnt = cnt;
+    }
+    __syncthreads();
+    r -= sh_below;
+    inplay = sh_cnt;
+    if (phase == 0) { kp = (kp << wb) | sh_b; kshift = sft; }
+    else { ip = (ip << wb) | sh_b; ishift = sft; }
+    __syncthreads();
+  }
+  // collect the in-play candidates and rank them exactly
+  if (threadIdx.x == 0) ccount = 0;
+  __syncthreads();
+  for (int k = 0; k < nseg; ++k)
+    for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) {
+      const uint32_t p = seg_pos(g, sa, k, j);
+      const uint64_t K = s.K[p];
+      bool match;
+      if (phase == 0) match = (kshift >= 64) ? true : ((K >> kshift) == kp);
+      else {
+        const uint32_t id = s.idx[p];
+        match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
+      }
+      if (match) {
+        const uint32_t slot = atomicAdd(&ccount, 1u);
+        if (slot < SMALL) { ck[slot] = K; cidx[slot] = s.idx[p]; cpos[slot] = p; }
+      }
+    }
+  __syncthreads();
+  const uint32_t cc = min(ccount, (uint32_t)SMALL);
+  if (threadIdx.x == 0) sh_pt = NONE;
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < cc; e += BS) {
+    const uint64_t Ke = ck[e];
+    const uint32_t Ie = cidx[e];
+    uint32_t rank = 0;
+    for (uint32_t f = 0; f < cc; ++f) {
+      const uint64_t Kf = ck[f];
+      rank += (Kf < Ke || (Kf == Ke && cidx[f] < Ie)) ? 1u : 0u;
+    }
+    if (rank == r) { sh_kt = Ke; sh_it = Ie; sh_pt = cpos[e]; }
+  }
+  __syncthreads();
+  if (sh_pt == NONE || ccount > SMALL) {
+    if (threadIdx.x == 0) set_status(a, STATUS_INTERNAL);
+    __syncthreads();
+    return;
+  }
+  const uint64_t Kt = sh_kt;
+  const uint32_t It = sh_it;
+  // order-preserving compaction of (K, id) <= (Kt, It)
+  uint32_t *out = sa.top_cur + (uint64_t)t.sel_idx[v] * (n + 1);
+  uint32_t written = 0;
+  for (int k = 0; k < nseg; ++k) {
+    const uint32_t L = g.len[k];
+    for (uint32_t j0 = 0; j0 < L; j0 += BS) {
+      const uint32_t j = j0 + threadIdx.x;
+      uint32_t f = 0, p = 0;
+      if (j < L) {
+        p = seg_pos(g, sa, k, j);
+        const uint64_t K = s.K[p];
+        f = (K < Kt || (K == Kt && s.idx[p] <= It)) ? 1u : 0u;
+      }
+      uint32_t tot;
+      const uint32_t o = block_excl_scan<uint32_t>(f, red32, tot);
+      if (f && written + o <= n) out[written + o] = p;
+      written += tot;
+    }
+  }
+  if (threadIdx.x == 0) {
+    t.wit[v] = sh_pt;
+    if (written != n + 1) set_status(a, STATUS_INTERNAL);
+  }
+  __syncthreads();
+}
+
+// One block per node of level d (grid-stride); non-selecting nodes skipped.
+__global__ __launch_bounds__(1024) void k_select_level(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
+  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
+  for (uint32_t v = b + blockIdx.x; v < e; v += gridDim.x) {
+    if (t.part_count[v] <= a.n) continue;
+    select_node(a, t, s, sa, v, d);
+  }
+}
+
+// Per-node launch: node v_rank-th of level d (mode 0).
+__global__ __launch_bounds__(1024) void k_select_one(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d,
+                                                     uint32_t rank) {
+  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
+  const uint32_t v = b + rank;
+  if (v >= e || t.part_count[v] <= a.n) return;
+  select_node(a, t, s, sa, v, d);
+}
+
+// Renormalised masses, quantisation and output for the selecting nodes of level d.
+__global__ __launch_bounds__(TB) void k_sel_output(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
+  __shared__ double red[TB / WAVE + 1];
+  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
+  const uint32_t n = a.n;
+  const bool cap_ok = a.counts[1] <= a.point_cap;
+  const int alpha = a.alpha;
+  for (uint32_t v = b + blockIdx.x; v < e; v += gridDim.x) {
+    if (t.part_count[v] <= n || !cap_ok) continue;
+    const uint32_t pt = t.wit[v];
+    if (pt == NONE) continue;
+    const uint32_t *list = sa.top_cur + (uint64_t)t.sel_idx[v] * (n + 1);
+    const uint32_t kt = s.key[pt];
+    const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
+    const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
+    const double tau = weight_pow(s.w[pt], alpha) * 4294967296.0 / (double)Ut;
+    double acc = 0.0;
+    for (uint32_t j = threadIdx.x; j <= n; j += TB) {
+      const uint32_t p = min(list[j], sa.n_minus_1);
+      if (p == pt) continue;
+      const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
+      acc += (double)s.m[p] / pr;
+    }
+    const double tot = block_reduce_sum<double>(acc, red);
+    const double scale = t.node_mass[v] / tot;
+    const uint64_t ob = t.pt_begin[v];
+    for (uint32_t j = threadIdx.x; j <= n; j += TB) {
+      const uint32_t p = min(list[j], sa.n_minus_1);
+      if (p == pt) continue;
+      const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
+      const double mhat = (double)s.m[p] / pr;
+      const uint64_t o = ob + j - (p > pt ? 1u : 0u);
+      write_point(a, t, s, p, o, d, (float)(scale * mhat));
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace lodh {
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
+  BuildLayout L{};
+  const uint64_t Np = N ? N : 1;
+  const uint64_t tiles = (Np + TILE - 1) / TILE;
+  L.tiles = tiles;
+  uint64_t per_level = N / ((uint64_t)p.n + 1);
+  L.node_cap = (uint64_t)n_snap + 8ull * p.max_depth * per_level;
+  if (L.node_cap == 0) L.node_cap = 1;
+  L.point_cap = N + (uint64_t)p.n * p.max_depth * per_level;
+  if (L.point_cap == 0) L.point_cap = 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  L.keyA = take(4 * Np); L.keyB = take(4 * Np);
+  L.idxA = take(4 * Np); L.idxB = take(4 * Np);
+  L.loA = take(8 * Np); L.loB = take(8 * Np);
+  L.mA = take(4 * Np); L.mB = take(4 * Np);
+  L.thist = take(4 * (size_t)RADIX * tiles);
+  L.scan32 = take(4 * scan_tmp_elems<uint32_t>((uint64_t)RADIX * tiles));
+  L.scan64 = take(8 * scan_tmp_elems<uint64_t>(L.node_cap));
+  L.w = take(4 * Np);
+  L.K = take(8 * Np);
+  L.lvl = take(4 * (size_t)(p.max_depth + 4));
+  L.cs = take(4 * 9 * (size_t)L.node_cap);
+  L.sel_idx = take(4 * (size_t)L.node_cap);
+  L.wit = take(4 * (size_t)L.node_cap);
+  L.top0 = take(4 * Np);
+  L.top1 = take(4 * Np);
+  L.total = off;
+  return L;
+}
+
+int key_bits(const lod_params &p, uint32_t n_snap) {
+  int sb = 0;
+  while ((1ull << sb) < n_snap) ++sb;
+  return 3 * (int)p.max_depth + sb;
+}
+
+lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, const BuildLayout &L,
+                        lod_tree &out, hipStream_t st) {
+  char *W = (char *)ws;
+  const uint64_t N = in.n_particles;
+  const uint32_t n_snap = in.snap_offsets ? in.n_snapshots : 1;
+  BuildArgs a{};
+  a.N = N; a.n = p.n; a.D = (int)p.max_depth; a.shift_rho = 3 * ((int)p.max_depth - (int)p.density_level);
+  a.alpha = p.alpha; a.seed = p.seed; a.n_snap = n_snap; a.snap_off = in.snap_offsets;
+  a.node_cap = L.node_cap; a.point_cap = out.point_capacity; a.counts = out.counts;
+
+  // fills instead of memsets: the build may be captured into a graph
+  fill_u64(out.counts, 3, 0, st);
+  uint32_t *lvl = (uint32_t *)(W + L.lvl);
+  fill_u32(lvl, p.max_depth + 4, 0, st);
+  if (N == 0) return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+
+  hipLaunchKernelGGL(k_check_offsets, dim3(1), dim3(256), 0, st, a);
+
+  uint32_t *keyA = (uint32_t *)(W + L.keyA), *keyB = (uint32_t *)(W + L.keyB);
+  uint32_t *idxA = (uint32_t *)(W + L.idxA), *idxB = (uint32_t *)(W + L.idxB);
+  uint64_t *loA = (uint64_t *)(W + L.loA), *loB = (uint64_t *)(W + L.loB);
+  float *mA = (float *)(W + L.mA), *mB = (float *)(W + L.mB);
+  uint32_t *thist = (uint32_t *)(W + L.thist);
+  uint32_t *scan32 = (uint32_t *)(W + L.scan32);
+  const uint64_t tiles = (N + TILE - 1) / TILE;
+  const uint64_t hist_n = (uint64_t)RADIX * tiles;
+
+  hipLaunchKernelGGL(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a,
+                     keyA, loA, thist, tiles);
+  const int kb = key_bits(p, n_snap);
+  const int passes = std::max(1, (kb + 7) / 8);
+  // pass 0: keys/fractions from keygen (A), ids implicit, masses from the input; writes B
+  device_scan<uint32_t>(thist, hist_n, scan32, st);
+  hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 0, thist, tiles,
+                     keyA, (const uint32_t *)nullptr, loA, in.mass, keyB, idxB, loB, mB);
+  uint32_t *ks = keyB, *is = idxB; uint64_t *ls = loB; float *ms = mB;
+  uint32_t *kd = keyA, *id = idxA; uint64_t *ld = loA; float *md = mA;
+  for (int ps = 1; ps < passes; ++ps) {
+    hipLaunchKernelGGL(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
+    device_scan<uint32_t>(thist, hist_n, scan32, st);
+    hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 8 * ps, thist, tiles,
+                       ks, is, ls, ms, kd, id, ld, md);
+    std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(ms, md);
+  }
+  Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint64_t *)(W + L.K)};
+
+  hipLaunchKernelGGL(k_density, dim3((unsigned)tiles), dim3(TB), 0, st, a, ks, is,
+                     (uint32_t *)(W + L.w), (uint64_t *)(W + L.K));
+
+  TreeArgs t{};
+  t.prefix = out.prefix; t.depth = out.depth; t.parent = out.parent; t.first_child = out.first_child;
+  t.child_mask = out.child_mask; t.part_begin = out.part_begin; t.part_count = out.part_count;
+  t.pt_begin = out.pt_begin; t.pt_count = out.pt_count; t.node_mass = out.node_mass;
+  t.pt_id = out.pt_id; t.qx = out.qx; t.qy = out.qy; t.qz = out.qz; t.pt_mass = out.pt_mass;
+  t.lvl = lvl; t.cs = (uint32_t *)(W + L.cs); t.sel_idx = (uint32_t *)(W + L.sel_idx);
+  t.wit = (uint32_t *)(W + L.wit);
+
+  const int D = (int)p.max_depth;
+  hipLaunchKernelGGL(k_roots, dim3(1), dim3(1024), 0, st, a, t, ks);
+  const uint64_t per_level = N / ((uint64_t)p.n + 1) + n_snap;
+  const unsigned oct_grid = (unsigned)std::min<uint64_t>(4096, (per_level * 8 + TB - 1) / TB + 1);
+  for (int d = 0; d < D; ++d) {
+    hipLaunchKernelGGL(k_octants, dim3(oct_grid), dim3(TB), 0, st, a, t, ks, d);
+    hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, st, a, t, d);
+  }
+  // level D has no children: its end was written by the last emit (or roots)
+  const unsigned cap_grid = (unsigned)std::min<uint64_t>(4096, (L.node_cap + TB - 1) / TB);
+  hipLaunchKernelGGL(k_ptcount, dim3(cap_grid), dim3(TB), 0, st, a, t, D);
+  device_scan<uint64_t>(out.pt_begin, L.node_cap, (uint64_t *)(W + L.scan64), st);
+  hipLaunchKernelGGL(k_ptfinish, dim3(1), dim3(1), 0, st, a, t);
+
+  const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
+  hipLaunchKernelGGL(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
+
+  uint32_t *top[2] = {(uint32_t *)(W + L.top0), (uint32_t *)(W + L.top1)};
+  // the per-node reference schedule needs the level sizes on the host
+  std::vector<uint32_t> hl;
+  std::vector<uint64_t> hcount;
+  if (p.mode == 0) {
+    hl.resize(D + 4);
+    if (hipMemcpyAsync(hl.data(), lvl, 4 * (D + 4), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return LOD_EDEVICE;
+    hcount.resize(hl[D + 1] + 1);
+    if (hl[D + 1] &&
+        (hipMemcpyAsync(hcount.data(), out.part_count, 8ull * hl[D + 1], hipMemcpyDeviceToHost, st) != hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+      return LOD_EDEVICE;
+  }
+  const unsigned sel_threads = p.select_threads ? p.select_threads : 256;
+  const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
+  for (int d = D; d >= 0; --d) {
+    if (d < D)
+      hipLaunchKernelGGL(k_internal_mass, dim3((unsigned)std::min<uint64_t>(1024, L.node_cap / TB + 1)),
+                         dim3(TB), 0, st, a, t, d);
+    SelArgs sa{top[(d + 1) & 1], top[d & 1], (uint32_t)(N - 1)};
+    if (p.mode == 0) {
+      // reference schedule: one launch per selecting node of this level
+      for (uint32_t v = hl[d]; v < hl[d + 1]; ++v) {
+        if (hcount[v] <= p.n) continue;
+        hipLaunchKernelGGL(k_select_one, dim3(1), dim3(sel_threads), 0, st, a, t, s, sa, d, v - hl[d]);
+      }
+    } else {
+      hipLaunchKernelGGL(k_select_level, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
+    }
+    hipLaunchKernelGGL(k_sel_output, dim3(sel_grid), dim3(TB), 0, st, a, t, s, sa, d);
+  }
+  return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+}
+
+namespace {
+template <typename T>
+__global__ void k_fill(T *p, uint64_t n, T v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+}  // namespace
+
+void fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st) {
+  if (!n) return;
+  const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill<uint64_t>, dim3(g), dim3(256), 0, st, p, n, v);
+}
+
+void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (!n) return;
+  const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(g), dim3(256), 0, st, p, n, v);
+}
+
+void *workspace_view(void *ws, const BuildLayout &L, uint32_t which, uint64_t N, int passes, uint64_t *count) {
+  char *W = (char *)ws;
+  const bool inB = (passes % 2) == 1;
+  switch (which) {
+    case 0: *count = N; return W + (inB ? L.keyB : L.keyA);
+    case 1: *count = N; return W + (inB ? L.idxB : L.idxA);
+    case 2: *count = N; return W + L.w;
+    case 3: *count = N; return W + L.K;
+    case 4: *count = L.node_cap; return W + L.wit;
+    default: *count = 0; return nullptr;
+  }
+}
+
+}  // namespace lodh

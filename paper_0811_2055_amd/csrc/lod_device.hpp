@@ -1,0 +1,155 @@
+// Device-side building blocks for the gfx950 level-of-detail path.
+// Wave64 throughout: ballots are 64-bit, lane masks are 64-bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lod.h"
+
+namespace lodk {
+
+constexpr int WAVE = 64;
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
+// (k0,k1); a round maps (c0,c1,c2,c3) to (hi(M1 c2)^c1^k0, lo(M1 c2),
+// hi(M0 c0)^c3^k1, lo(M0 c0)); the key is bumped by the Weyl constants
+// between rounds.  Only output word 0 is used by the method.
+__device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return c0;
+}
+
+// U = word0 + 1 in [1, 2^32] for particle `id` of snapshot `snap`.
+__device__ __forceinline__ uint64_t particle_U(uint64_t id, uint32_t snap, uint64_t seed) {
+  return (uint64_t)philox_word0((uint32_t)id, (uint32_t)(id >> 32), snap, 0u,
+                                (uint32_t)seed, (uint32_t)(seed >> 32)) + 1ull;
+}
+
+// Integer selection key; smaller is kept first.
+__device__ __forceinline__ uint64_t selection_key(uint64_t U, uint32_t w, int alpha) {
+  if (alpha > 0) return (U << 31) / (uint64_t)w;
+  if (alpha == 0) return U << 31;
+  return U * (uint64_t)w;
+}
+
+// w^alpha as float64 (alpha in {-1,0,1}).
+__device__ __forceinline__ double weight_pow(uint32_t w, int alpha) {
+  if (alpha > 0) return (double)w;
+  if (alpha == 0) return 1.0;
+  return 1.0 / (double)w;
+}
+
+// ---------------------------------------------------------------------------
+// Morton: spread the low 10 bits of v to every third bit.
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x3FFu;
+  return v;
+}
+
+// Fixed point X = min(floor(a 2^(D+16)), 2^(D+16)-1) for a in [0,1]; the
+// product is exact (power-of-two scaling) and floor of a float is a float.
+// Returns false for NaN or a outside [0,1].
+__device__ __forceinline__ bool fixed_coord(float a, int D, uint32_t &X) {
+  if (!(a >= 0.0f && a <= 1.0f)) { X = 0; return false; }
+  const float s = ldexpf(a, D + 16);
+  uint32_t v = (uint32_t)floorf(s);
+  const uint32_t top = (1u << (D + 16)) - 1u;
+  X = v > top ? top : v;
+  return true;
+}
+
+// q at depth d <= D from the depth-D cell coordinate and the 16 low bits.
+__device__ __forceinline__ uint16_t quant_at(uint32_t cD, uint32_t lo16, int D, int d) {
+  const uint32_t X = (cD << 16) | lo16;
+  return (uint16_t)((X >> (D - d)) & 0xFFFFu);
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of one value per thread (LDS, any blockDim that
+// is a multiple of 64 and <= 1024).  `tmp` holds >= blockDim/64 + 1 entries.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T t = __shfl_up(v, o, WAVE);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *tmp, T &total) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+  T inc = wave_incl_scan(v);
+  if (lane == WAVE - 1) tmp[wid] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (int w = 0; w < nw; ++w) { T t = tmp[w]; tmp[w] = run; run += t; }
+    tmp[nw] = run;
+  }
+  __syncthreads();
+  T res = tmp[wid] + inc - v;
+  total = tmp[nw];
+  __syncthreads();
+  return res;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_reduce_sum(T v, T *tmp) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  if (lane == 0) tmp[wid] = v;
+  __syncthreads();
+  T r = 0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < nw; ++w) r += tmp[w];
+    tmp[nw] = r;
+  }
+  __syncthreads();
+  r = tmp[nw];
+  __syncthreads();
+  return r;
+}
+
+// lower_bound over a sorted uint32 array in [lo, hi) for the first element >= key.
+__device__ __forceinline__ uint64_t lower_bound_u32(const uint32_t *a, uint64_t lo, uint64_t hi,
+                                                    uint32_t key) {
+  while (lo < hi) {
+    uint64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace lodk

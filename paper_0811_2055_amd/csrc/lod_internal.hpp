@@ -1,0 +1,76 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lod.h"
+
+namespace lodh {
+
+// Byte offsets of the build workspace arrays (256-byte aligned).
+struct BuildLayout {
+  uint64_t tiles, node_cap, point_cap;
+  size_t keyA, keyB, idxA, idxB, loA, loB, mA, mB;
+  size_t thist, scan32, scan64;
+  size_t w, K;
+  size_t lvl, cs, sel_idx, wit;
+  size_t top0, top1;
+  size_t total;
+};
+
+BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap);
+int key_bits(const lod_params &p, uint32_t n_snap);
+lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, const BuildLayout &L,
+                        lod_tree &out, hipStream_t st);
+void *workspace_view(void *ws, const BuildLayout &L, uint32_t which, uint64_t N, int passes,
+                     uint64_t *count);
+
+// Splat workspace layout.
+struct SplatLayout {
+  uint32_t tiles_x, tiles_y, n_tiles;
+  uint64_t max_points, max_pairs, max_slices;
+  size_t tile_count, tile_off, tile_cursor, slice_off, scan_tmp, counters;
+  size_t bu, bv, bm, partial;
+  size_t total;
+};
+
+constexpr int SPLAT_TS = 16;           // tile edge in pixels
+constexpr uint32_t SPLAT_MAX_TILES = 8192;
+constexpr uint32_t SPLAT_SLICE = 2048; // points per accumulation slice
+
+lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_params &sp,
+                        SplatLayout &L);
+// count_dev: if non-null the point count is read on the device and `count`
+// is only an upper bound.
+lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, uint64_t count,
+                        const uint64_t *count_dev, const lod_camera &cam, const splat_params &sp,
+                        void *ws, const SplatLayout &L, float *image, uint64_t *status_word,
+                        hipStream_t st);
+lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m,
+                                 uint64_t count, const lod_camera &cam, const splat_params &sp,
+                                 const float *grad, float *gm, float *gx, float *gy, float *gz,
+                                 hipStream_t st);
+
+// LOD render: decode the chosen nodes' points into workspace arrays.
+struct LodDrawLayout {
+  uint64_t max_ids, max_points;
+  size_t offs, scan_tmp, x, y, z, m, count;
+  size_t total;
+};
+LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points);
+lod_status launch_lod_gather(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                             void *ws, const LodDrawLayout &L, hipStream_t st);
+
+// View-dependent cut.
+size_t cut_workspace(uint64_t node_capacity);
+lod_status launch_cut(const lod_tree &tree, const lod_camera &cam, float tau_px, uint32_t n,
+                      uint32_t *node_ids, uint64_t cap, uint64_t *n_selected, void *ws,
+                      hipStream_t st);
+
+// small utilities
+void fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
+void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+
+}  // namespace lodh

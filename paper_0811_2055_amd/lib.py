@@ -1,0 +1,400 @@
+"""ctypes binding of liblod.so (include/lod.h).  Argument marshalling only:
+every step of the path runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current stream.
+
+The library must have been built (``paper_0811_2055_amd/build.py`` or
+``__graft_entry__.build()``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblod.so")
+
+LOD_OK, LOD_EINVAL, LOD_EDOMAIN, LOD_ENOMEM, LOD_EDEVICE, LOD_ECAPACITY, LOD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_DOMAIN, STATUS_CAPACITY, STATUS_OFFSETS, STATUS_INTERNAL = 1, 2, 4, 8
+NONE = 0xFFFFFFFF
+
+EXPORTS = [
+    "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
+    "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
+    "lod_workspace_view", "lod_status_string", "lod_version",
+]
+
+
+class LodError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("max_depth", C.c_uint32), ("density_level", C.c_uint32),
+                ("alpha", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_uint32),
+                ("select_threads", C.c_uint32)]
+
+
+class Input(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("mass", C.c_void_p),
+                ("n_particles", C.c_uint64), ("snap_offsets", C.c_void_p), ("n_snapshots", C.c_uint32)]
+
+
+class TreeC(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in (
+        "prefix", "depth", "parent", "first_child", "child_mask", "part_begin", "part_count",
+        "pt_begin", "pt_count", "node_mass", "pt_id", "qx", "qy", "qz", "pt_mass")] + [
+        ("node_capacity", C.c_uint64), ("point_capacity", C.c_uint64), ("counts", C.c_void_p)]
+
+
+class CameraC(C.Structure):
+    _fields_ = [("projection", C.c_uint32), ("W", C.c_uint32), ("H", C.c_uint32),
+                ("pos", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3),
+                ("fwd", C.c_float * 3), ("F", C.c_float), ("near_z", C.c_float)]
+
+
+class SplatParamsC(C.Structure):
+    _fields_ = [("sigma_px", C.c_float), ("radius_sigmas", C.c_float)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblod.so (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0811_2055_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    st = C.c_int
+    lib.lod_build_plan.argtypes = [C.POINTER(Input), C.POINTER(Params), C.POINTER(C.c_size_t),
+                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    lib.lod_build.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_size_t, C.POINTER(TreeC), P]
+    lib.lod_select_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
+    lib.lod_select.argtypes = [C.POINTER(TreeC), C.POINTER(CameraC), C.c_float, C.c_uint32, P,
+                               C.c_uint64, P, P, C.c_size_t, P]
+    lib.splat_plan.argtypes = [C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC), C.POINTER(C.c_size_t)]
+    lib.splat_render.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC),
+                                 P, C.c_size_t, P, P]
+    lib.splat_lod_plan.argtypes = [C.c_uint64, C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC),
+                                   C.POINTER(C.c_size_t)]
+    lib.splat_render_lod.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, C.POINTER(CameraC),
+                                     C.POINTER(SplatParamsC), P, C.c_size_t, P, P]
+    lib.splat_render_backward.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(CameraC),
+                                          C.POINTER(SplatParamsC), P, P, P, P, P, P]
+    lib.lod_workspace_view.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_uint32,
+                                       C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]
+    lib.lod_status_string.argtypes = [st]
+    lib.lod_status_string.restype = C.c_char_p
+    lib.lod_version.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("lod_status_string", "lod_version"):
+            getattr(lib, name).restype = st
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().lod_status_string(int(code)).decode()
+
+
+def _check(code, where):
+    if code != LOD_OK:
+        raise LodError(code, where)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# value types
+
+@dataclass
+class BuildParams:
+    n: int
+    max_depth: int
+    density_level: int | None = None
+    alpha: int = 1
+    seed: int = 0
+    mode: int = 1
+    select_threads: int = 0
+
+    def c(self) -> Params:
+        L = self.max_depth if self.density_level is None else self.density_level
+        return Params(self.n, self.max_depth, L, self.alpha, self.seed & ((1 << 64) - 1), self.mode,
+                      self.select_threads)
+
+
+@dataclass
+class Camera:
+    projection: int
+    W: int
+    H: int
+    pos: tuple = (0.0, 0.0, 0.0)
+    right: tuple = (1.0, 0.0, 0.0)
+    up: tuple = (0.0, 1.0, 0.0)
+    fwd: tuple = (0.0, 0.0, 1.0)
+    F: float = 1.0
+    near: float = 1e-3
+
+    def c(self) -> CameraC:
+        f3 = C.c_float * 3
+        return CameraC(self.projection, self.W, self.H, f3(*self.pos), f3(*self.right), f3(*self.up),
+                       f3(*self.fwd), self.F, self.near)
+
+    @staticmethod
+    def ortho(W: int, H: int) -> "Camera":
+        return Camera(0, W, H)
+
+    @staticmethod
+    def look_at(pos, target, W: int, H: int, fov_deg: float = 60.0, up_hint=(0.0, 1.0, 0.0),
+                near: float = 1e-3) -> "Camera":
+        """Perspective camera; the basis is computed in float64 and cast to float32."""
+        f = [t - p for t, p in zip(target, pos)]
+        fn = math.sqrt(sum(a * a for a in f))
+        f = [a / fn for a in f]
+        u0 = list(up_hint)
+        r = [u0[1] * f[2] - u0[2] * f[1], u0[2] * f[0] - u0[0] * f[2], u0[0] * f[1] - u0[1] * f[0]]
+        rn = math.sqrt(sum(a * a for a in r))
+        if rn < 1e-12:
+            u0 = [1.0, 0.0, 0.0]
+            r = [u0[1] * f[2] - u0[2] * f[1], u0[2] * f[0] - u0[0] * f[2], u0[0] * f[1] - u0[1] * f[0]]
+            rn = math.sqrt(sum(a * a for a in r))
+        r = [a / rn for a in r]
+        up = [f[1] * r[2] - f[2] * r[1], f[2] * r[0] - f[0] * r[2], f[0] * r[1] - f[1] * r[0]]
+        F = (W / 2.0) / math.tan(math.radians(fov_deg) / 2.0)
+        return Camera(1, W, H, tuple(pos), tuple(r), tuple(up), tuple(f), F, near)
+
+
+@dataclass
+class Tree:
+    """Device arrays of a built tree (capacity-sized) plus the counts word."""
+    arrays: dict
+    counts: object            # torch uint64 [3] on the device
+    node_capacity: int
+    point_capacity: int
+    _c: TreeC = field(default=None, repr=False)
+
+    def c(self) -> TreeC:
+        if self._c is None:
+            a = self.arrays
+            self._c = TreeC(*[_ptr(a[k]) for k in (
+                "prefix", "depth", "parent", "first_child", "child_mask", "part_begin", "part_count",
+                "pt_begin", "pt_count", "node_mass", "pt_id", "qx", "qy", "qz", "pt_mass")],
+                self.node_capacity, self.point_capacity, _ptr(self.counts))
+        return self._c
+
+    def host(self) -> dict:
+        """Copy the used parts to host numpy arrays (synchronises)."""
+        import numpy as np
+        cnt = self.counts.cpu().numpy().view(np.uint64)
+        nn, npt, status = int(cnt[0]), int(cnt[1]), int(cnt[2])
+        out = {"n_nodes": nn, "n_points": npt, "status": status}
+        for k in ("prefix", "depth", "parent", "first_child", "child_mask", "part_begin", "part_count",
+                  "pt_begin", "pt_count", "node_mass"):
+            out[k] = _to_numpy(self.arrays[k][:nn])
+        for k in ("pt_id", "qx", "qy", "qz", "pt_mass"):
+            out[k] = _to_numpy(self.arrays[k][:npt])
+        return out
+
+
+def _to_numpy(t):
+    import numpy as np
+    import torch
+    conv = {torch.uint64: np.uint64, torch.uint32: np.uint32, torch.uint16: np.uint16}
+    if t.dtype in conv:
+        # torch lacks some unsigned ops; reinterpret through the signed type
+        signed = {torch.uint64: torch.int64, torch.uint32: torch.int32, torch.uint16: torch.int16}[t.dtype]
+        return t.view(signed).cpu().numpy().view(conv[t.dtype])
+    return t.cpu().numpy()
+
+
+def _empty(n, dtype, device):
+    import torch
+    return torch.empty(max(int(n), 1), dtype=dtype, device=device)
+
+
+# ---------------------------------------------------------------------------
+# build
+
+def _input(x, y, z, m, snap_offsets):
+    N = int(x.numel())
+    if snap_offsets is None:
+        return Input(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.c_void_p(0), 1)
+    return Input(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, _ptr(snap_offsets), int(snap_offsets.numel()) - 1)
+
+
+def build_plan(N: int, params: BuildParams, n_snapshots: int = 1):
+    lib = load()
+    inp = Input(None, None, None, None, N, C.c_void_p(1 if n_snapshots > 1 else 0), n_snapshots)
+    ws, nc, pc = C.c_size_t(), C.c_uint64(), C.c_uint64()
+    p = params.c()
+    _check(lib.lod_build_plan(C.byref(inp), C.byref(p), C.byref(ws), C.byref(nc), C.byref(pc)), "lod_build_plan")
+    return int(ws.value), int(nc.value), int(pc.value)
+
+
+def alloc_tree(node_cap: int, point_cap: int, device) -> Tree:
+    import torch
+    a = {
+        "prefix": _empty(node_cap, torch.uint64, device),
+        "depth": _empty(node_cap, torch.uint8, device),
+        "parent": _empty(node_cap, torch.uint32, device),
+        "first_child": _empty(node_cap, torch.uint32, device),
+        "child_mask": _empty(node_cap, torch.uint8, device),
+        "part_begin": _empty(node_cap, torch.uint64, device),
+        "part_count": _empty(node_cap, torch.uint64, device),
+        "pt_begin": _empty(node_cap, torch.uint64, device),
+        "pt_count": _empty(node_cap, torch.uint32, device),
+        "node_mass": _empty(node_cap, torch.float64, device),
+        "pt_id": _empty(point_cap, torch.uint32, device),
+        "qx": _empty(point_cap, torch.uint16, device),
+        "qy": _empty(point_cap, torch.uint16, device),
+        "qz": _empty(point_cap, torch.uint16, device),
+        "pt_mass": _empty(point_cap, torch.float32, device),
+    }
+    counts = torch.zeros(3, dtype=torch.uint64, device=device)
+    return Tree(a, counts, max(int(node_cap), 1), max(int(point_cap), 1))
+
+
+class Builder:
+    """Plans once, keeps the workspace and output tree, rebuilds on demand."""
+
+    def __init__(self, N: int, params: BuildParams, device="cuda", n_snapshots: int = 1):
+        import torch
+        self.N = N
+        self.params = params
+        self.n_snapshots = n_snapshots
+        ws, nc, pc = build_plan(N, params, n_snapshots)
+        self.ws_bytes = ws
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        self.tree = alloc_tree(nc, pc, device)
+
+    def build(self, x, y, z, m, snap_offsets=None, stream=None):
+        lib = load()
+        if int(x.numel()) != self.N:
+            raise ValueError("particle count differs from the plan")
+        for t in (x, y, z, m):
+            if t.dtype.itemsize != 4 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("x, y, z, mass must be contiguous float32 device tensors")
+        inp = _input(x, y, z, m, snap_offsets)
+        p = self.params.c()
+        code = lib.lod_build(C.byref(inp), C.byref(p), _ptr(self.workspace), self.ws_bytes,
+                             C.byref(self.tree.c()), stream if stream is not None else _stream())
+        _check(code, "lod_build")
+        self._inp = inp
+        return self.tree
+
+    def view(self, which: int, dtype):
+        """Intermediate arrays (0 keys, 1 ids, 2 w, 3 K, 4 witness) as a torch view."""
+        import torch
+        lib = load()
+        ptr, cnt = C.c_void_p(), C.c_uint64()
+        p = self.params.c()
+        _check(lib.lod_workspace_view(C.byref(self._inp), C.byref(p), _ptr(self.workspace), which,
+                                      C.byref(ptr), C.byref(cnt)), "lod_workspace_view")
+        base = self.workspace.data_ptr()
+        off = ptr.value - base
+        size = torch.tensor([], dtype=dtype).element_size()
+        return self.workspace[off:off + int(cnt.value) * size].view(dtype)
+
+
+def build(x, y, z, m, params: BuildParams, snap_offsets=None) -> Tree:
+    nsnap = 1 if snap_offsets is None else int(snap_offsets.numel()) - 1
+    b = Builder(int(x.numel()), params, x.device, nsnap)
+    return b.build(x, y, z, m, snap_offsets)
+
+
+# ---------------------------------------------------------------------------
+# cut and splat
+
+def select_nodes(tree: Tree, cam: Camera, tau_px: float, n: int, cap: int | None = None, workspace=None):
+    """Returns (node_ids device uint32 [cap], n_selected device uint64 [1])."""
+    import torch
+    lib = load()
+    dev = tree.counts.device
+    cap = tree.node_capacity if cap is None else cap
+    ws = C.c_size_t()
+    _check(lib.lod_select_plan(tree.node_capacity, C.byref(ws)), "lod_select_plan")
+    if workspace is None or workspace.numel() < ws.value:
+        workspace = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=dev)
+    ids = torch.empty(max(cap, 1), dtype=torch.uint32, device=dev)
+    nsel = torch.zeros(1, dtype=torch.uint64, device=dev)
+    camc = cam.c()
+    _check(lib.lod_select(C.byref(tree.c()), C.byref(camc), float(tau_px), int(n), _ptr(ids), cap,
+                          _ptr(nsel), _ptr(workspace), ws.value, _stream()), "lod_select")
+    return ids, nsel
+
+
+def splat_workspace_bytes(max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0) -> int:
+    lib = load()
+    ws = C.c_size_t()
+    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    _check(lib.splat_plan(int(max_points), C.byref(camc), C.byref(sp), C.byref(ws)), "splat_plan")
+    return int(ws.value)
+
+
+def splat(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, workspace=None, out=None):
+    import torch
+    lib = load()
+    dev = x.device
+    N = int(x.numel())
+    ws = splat_workspace_bytes(N, cam, sigma, radius_sigmas)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    _check(lib.splat_render(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp),
+                            _ptr(workspace), workspace.numel(), _ptr(img), _stream()), "splat_render")
+    return img
+
+
+def splat_lod_workspace_bytes(node_capacity: int, max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0):
+    lib = load()
+    ws = C.c_size_t()
+    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    _check(lib.splat_lod_plan(int(node_capacity), int(max_points), C.byref(camc), C.byref(sp), C.byref(ws)),
+           "splat_lod_plan")
+    return int(ws.value)
+
+
+def splat_lod(tree: Tree, node_ids, n_ids, max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0,
+              workspace=None, out=None):
+    import torch
+    lib = load()
+    dev = tree.counts.device
+    ws = splat_lod_workspace_bytes(tree.node_capacity, max_points, cam, sigma, radius_sigmas)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    _check(lib.splat_render_lod(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points), C.byref(camc),
+                                C.byref(sp), _ptr(workspace), workspace.numel(), _ptr(img), _stream()),
+           "splat_render_lod")
+    return img
+
+
+def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas=3.0):
+    import torch
+    lib = load()
+    N = int(x.numel())
+    gm = torch.empty(N, dtype=torch.float32, device=x.device)
+    gx = torch.empty(N, dtype=torch.float32, device=x.device)
+    gy = torch.empty(N, dtype=torch.float32, device=x.device)
+    gz = torch.empty(N, dtype=torch.float32, device=x.device)
+    g = grad_image.contiguous()
+    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    _check(lib.splat_render_backward(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp), _ptr(g),
+                                     _ptr(gm), _ptr(gx), _ptr(gy), _ptr(gz), _stream()), "splat_render_backward")
+    return gm, gx, gy, gz

@@ -1,0 +1,147 @@
+"""HIP LOD build vs the CPU oracle, through the C ABI.
+
+Node tables, stored ids and 16-bit codes must be bit-exact; float64 node
+masses within 1e-12 relative (summation order); float32 stored masses within
+1 ulp (the float64 renormalisation sum is order dependent).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lod as olod
+from paper_0811_2055_amd import lib
+
+from gpu_util import compare_tree, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _face_set(N, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.random(N).astype(np.float32)
+    y = rng.random(N).astype(np.float32)
+    z = rng.random(N).astype(np.float32)
+    k = N // 8
+    x[:k] = (rng.integers(0, 33, k) / 32.0).astype(np.float32)
+    y[k:2 * k] = np.float32(1.0)
+    z[2 * k:3 * k] = np.float32(0.0)
+    m = rng.uniform(0.1, 5.0, N).astype(np.float32)
+    return synth.Snapshot(x, y, z, m)
+
+
+def _dup_set(N, seed):
+    s = synth.small_clustered(N, seed)
+    k = N // 3
+    s.x[:k] = np.float32(0.3); s.y[:k] = np.float32(0.71); s.z[:k] = np.float32(0.123)
+    return s
+
+
+CASES = [
+    # name, generator, n, D, alpha, seed, L_rho
+    ("one", lambda: synth.uniform(1, 1), 4, 3, 1, 0, None),
+    ("two_same", lambda: synth.Snapshot(np.full(2, 0.5, np.float32), np.full(2, 0.5, np.float32),
+                                        np.full(2, 0.5, np.float32), np.ones(2, np.float32)), 1, 2, 1, 0, None),
+    ("ragged", lambda: synth.small_clustered(5000, 1), 37, 5, 1, 3, None),
+    ("faces", lambda: _face_set(9000, 2), 20, 4, 1, 4, None),
+    ("dups_overfull", lambda: _dup_set(6000, 3), 50, 3, 1, 5, None),
+    ("alpha0", lambda: synth.small_clustered(12000, 4), 64, 5, 0, 6, None),
+    ("alpha_neg", lambda: synth.small_clustered(12000, 5), 64, 5, -1, 7, None),
+    ("lrho", lambda: synth.small_clustered(12000, 6), 100, 6, 1, 8, 3),
+    ("depth0", lambda: synth.small_clustered(3000, 7), 100, 0, 1, 9, None),
+    ("n1", lambda: synth.small_clustered(2000, 8), 1, 4, 1, 10, None),
+    ("nbig", lambda: synth.small_clustered(2000, 9), 5000, 4, 1, 11, None),
+    ("deep", lambda: synth.small_clustered(100000, 10), 512, 7, 1, 12, None),
+    ("d10", lambda: synth.small_clustered(30000, 11), 40, 10, 1, 13, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_build_matches_oracle(case):
+    name, gen, n, D, alpha, seed, L = case
+    s = gen()
+    print(f"[build parity] {name} N={s.n} n={n} D={D} alpha={alpha}", flush=True)
+    ref = olod.lod_build(s.x, s.y, s.z, s.m, n=n, D=D, L_rho=L, alpha=alpha, seed=seed)
+    b = lib.Builder(s.n, lib.BuildParams(n=n, max_depth=D, density_level=L, alpha=alpha, seed=seed))
+    tree = b.build(*to_dev(s))
+    h = tree.host()
+    compare_tree(h, ref, name)
+    # intermediates
+    import torch
+    keys = lib._to_numpy(b.view(0, torch.uint32)).astype(np.uint64)
+    ids = lib._to_numpy(b.view(1, torch.uint32)).astype(np.int64)
+    w = lib._to_numpy(b.view(2, torch.uint32)).astype(np.uint64)
+    K = lib._to_numpy(b.view(3, torch.uint64))
+    wit = lib._to_numpy(b.view(4, torch.uint32)).astype(np.int64)[:ref.n_nodes]
+    assert np.array_equal(keys, ref.skey)
+    assert np.array_equal(ids, ref.order)
+    assert np.array_equal(w, ref.w)
+    assert np.array_equal(K, ref.K)
+    sel = ref.witness >= 0
+    assert np.array_equal(wit[sel], ref.witness[sel])
+
+
+def test_empty_input():
+    import torch
+    e = torch.zeros(0, dtype=torch.float32, device="cuda")
+    tree = lib.build(e, e, e, e, lib.BuildParams(n=4, max_depth=3))
+    h = tree.host()
+    assert h["n_nodes"] == 0 and h["n_points"] == 0 and h["status"] == 0
+
+
+def test_config1_full_size():
+    s = synth.config1()
+    print(f"[build parity] config1 N={s.n}", flush=True)
+    ref = olod.lod_build(s.x, s.y, s.z, s.m, n=4096, D=4, alpha=1, seed=0)
+    tree = lib.build(*to_dev(s), lib.BuildParams(n=4096, max_depth=4, alpha=1, seed=0))
+    compare_tree(tree.host(), ref, "config1")
+
+
+def test_schedules_identical():
+    """Per-node launches, level launches and every block size give identical bytes."""
+    s = synth.small_clustered(60000, 21)
+    outs = []
+    for mode, thr in ((1, 0), (0, 0), (1, 64), (1, 1024), (1, 512)):
+        tree = lib.build(*to_dev(s), lib.BuildParams(n=300, max_depth=6, seed=2, mode=mode, select_threads=thr))
+        outs.append(tree.host())
+    for h in outs[1:]:
+        for k, v in outs[0].items():
+            if isinstance(v, np.ndarray):
+                assert np.array_equal(v, h[k]), k
+            else:
+                assert v == h[k], k
+
+
+def test_repeat_runs_identical():
+    s = synth.small_clustered(50000, 22)
+    b = lib.Builder(s.n, lib.BuildParams(n=200, max_depth=6, seed=4))
+    d = to_dev(s)
+    h1 = b.build(*d).host()
+    h2 = b.build(*d).host()
+    for k, v in h1.items():
+        if isinstance(v, np.ndarray):
+            assert np.array_equal(v, h2[k]), k
+
+
+def test_batch_matches_oracle():
+    import torch
+    parts = [synth.small_clustered(3000, 31), synth.uniform(0, 1), synth.small_clustered(5000, 32),
+             synth.uniform(700, 33)]
+    x = np.concatenate([p.x for p in parts]); y = np.concatenate([p.y for p in parts])
+    z = np.concatenate([p.z for p in parts]); m = np.concatenate([p.m for p in parts])
+    off = np.concatenate([[0], np.cumsum([p.n for p in parts])]).astype(np.int64)
+    ref = olod.lod_build(x, y, z, m, n=40, D=5, seed=9, snap_offsets=off)
+    s = synth.Snapshot(x, y, z, m)
+    offs = torch.from_numpy(off.astype(np.int64)).cuda().view(torch.uint64)
+    tree = lib.build(*to_dev(s), lib.BuildParams(n=40, max_depth=5, seed=9), snap_offsets=offs)
+    compare_tree(tree.host(), ref, "batch")
+
+
+def test_domain_error_is_flagged():
+    s = synth.small_clustered(1000, 40)
+    s.x[17] = np.float32(np.nan)
+    tree = lib.build(*to_dev(s), lib.BuildParams(n=16, max_depth=3))
+    assert tree.host()["status"] & lib.STATUS_DOMAIN
+    s = synth.small_clustered(1000, 41)
+    s.m[3] = np.float32(-1.0)
+    tree = lib.build(*to_dev(s), lib.BuildParams(n=16, max_depth=3))
+    assert tree.host()["status"] & lib.STATUS_DOMAIN
