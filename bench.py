@@ -1,0 +1,270 @@
+"""Benchmark: one step = LOD build of a particle snapshot + view-dependent cut
++ additive splat of the cut, all on one MI355X.
+
+Default workload: 150,000,000 Soneira-Peebles particles (8 levels, eta 4,
+lambda 1.9, seed 3), n = 16000, max depth 8, alpha = +1, orthographic
+1024x1024 Gaussian splat (sigma 1 px, truncated at 3 sigma), cut at 1 px
+point spacing.  Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line (rank 0) with throughput, the roofline of the
+dominant kernel (HIP-event timed inside the run), the CPU oracle timed on a
+bounded sample, and the LOD-vs-full image error.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "LOD build Mparticles/s + %HBM roofline; splat Mpts/s; LOD-vs-full image err"
+
+# Algorithmic bytes per unit for each kernel (unit: particle for the build
+# kernels, point for the splat binning, (point, tile) pair for accumulation).
+KERNEL_BYTES = {
+    "k_keygen": 28.0,            # read x,y,z,m (16) write key, 48-bit fraction (12)
+    "k_scatter<true>": 36.0,     # read key, fraction, mass (16) write key,id,fraction,mass (20)
+    "k_scatter<false>": 40.0,    # read 20 write 20
+    "k_upsweep": 4.0,            # read key
+    "k_density": 20.0,           # read key, id (8) write w, K (12)
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name: str, count: int | None):
+    import synth
+    if name == "c3":
+        N = count or 150_000_000
+        return synth.config3(N), dict(n=16000, D=8, W=1024, H=1024, label=(
+            f"Soneira-Peebles {N} particles (8 levels, eta 4, lambda 1.9, seed 3), n=16000, D=8, "
+            f"alpha=+1, ortho 1024x1024 splat sigma 1px, cut tau 1px"))
+    if name == "c2":
+        s = synth.config2()
+        return s, dict(n=16000, D=8, W=1024, H=1024, label=(
+            "NFW 16,777,216 particles (500 haloes + 20% uniform, seed 2), n=16000, D=8, alpha=+1, "
+            "ortho 1024x1024 splat sigma 1px, cut tau 1px"))
+    if name == "c1":
+        s = synth.config1()
+        return s, dict(n=4096, D=4, W=256, H=256, label=(
+            "Plummer mix 262,144 particles (seed 0), n=4096, D=4, alpha=+1, ortho 256x256 splat, cut tau 1px"))
+    raise SystemExit(f"unknown workload {name}")
+
+
+def image_errors(lod_img, full_img):
+    """E_log, E_tone, E_L1 between a LOD render and the full render (torch, on the GPU)."""
+    import torch
+    lod = lod_img.double(); full = full_img.double()
+    mean = full.mean()
+    if float(mean) <= 0:
+        return dict(E_log=0.0, E_tone=0.0, E_L1=0.0)
+    a = torch.log1p(lod / mean); b = torch.log1p(full / mean)
+    e_log = float(torch.sqrt(torch.mean((a - b) ** 2)))
+    top = torch.log1p(full.max() / mean)
+    ta = torch.floor(255.0 * a / top); tb = torch.floor(255.0 * b / top)
+    e_tone = float(((ta - tb).abs() > 1).double().mean())
+    e_l1 = float((lod - full).abs().sum() / full.sum())
+    return dict(E_log=e_log, E_tone=e_tone, E_L1=e_l1)
+
+
+def cpu_baseline(snap, cfg, sample: int):
+    """Time the CPU oracle (build + cut + LOD render) on the first `sample` particles."""
+    from oracle import cut as ocut
+    from oracle import lod as olod
+    from oracle import splat as osplat
+    sub = snap.subset(min(sample, snap.n))
+    t0 = time.perf_counter()
+    tr = olod.lod_build(sub.x, sub.y, sub.z, sub.m, n=cfg["n"], D=cfg["D"], alpha=1, seed=0)
+    cam = osplat.Camera(0, cfg["W"], cfg["H"])
+    c = ocut.select(tr, cam, 1.0, cfg["n"])
+    px, py, pz, pm = olod.decoded_points(tr, c)
+    osplat.render(cam, px, py, pz, pm)
+    dt = time.perf_counter() - t0
+    return {"value": sub.n / dt / 1e6, "unit": "Mparticles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {sub.n:,} particles of the same (shuffled) snapshot, same n and D; "
+                       f"numpy oracle build + cut + LOD render, single thread, {dt:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--count", type=int, default=None, help="override the particle count (c3)")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-render", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for counter calibration)")
+    ap.add_argument("--profile-steps", type=int, default=None,
+                    help="only run this many plain steps (for profilers) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        sys.exit("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+                 "(the sharding design is described in DESIGN.md); use --gpus 1")
+
+    import numpy as np
+    import torch
+    from paper_0811_2055_amd import lib
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    snap, cfg = workload(args.workload, args.count)
+    log(f"[bench] workload generated: {snap.n} particles in {time.perf_counter() - t0:.1f} s")
+    x, y, z, m = (torch.from_numpy(a).to(dev) for a in (snap.x, snap.y, snap.z, snap.m))
+    N = snap.n
+    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=1)
+    builder = lib.Builder(N, params, dev)
+    cam = lib.Camera.ortho(cfg["W"], cfg["H"])
+    tree = builder.tree
+    sel_ws_bytes = lib.C.c_size_t()
+    lib.load().lod_select_plan(tree.node_capacity, lib.C.byref(sel_ws_bytes))
+    sel_ws = torch.empty(max(sel_ws_bytes.value, 256), dtype=torch.uint8, device=dev)
+    max_draw = N          # a cut never draws more points than particles
+    lod_ws = torch.empty(lib.splat_lod_workspace_bytes(tree.node_capacity, max_draw, cam), dtype=torch.uint8,
+                         device=dev)
+    lod_img = torch.empty((cfg["H"], cfg["W"]), dtype=torch.float32, device=dev)
+    log(f"[bench] workspace {builder.ws_bytes / 1e9:.2f} GB, tree caps {tree.node_capacity} nodes "
+        f"{tree.point_capacity} points, splat ws {lod_ws.numel() / 1e9:.2f} GB")
+
+    def step():
+        builder.build(x, y, z, m)
+        ids, nsel = lib.select_nodes(tree, cam, 1.0, cfg["n"], workspace=sel_ws)
+        lib.splat_lod(tree, ids, nsel, max_draw, cam, workspace=lod_ws, out=lod_img)
+        return ids, nsel
+
+    if args.profile_steps is not None:
+        for _ in range(args.profile_steps):
+            step()
+        torch.cuda.synchronize()
+        if args.copy_calibration:
+            a = torch.empty(256 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            log(f"[bench] copy calibration: {a.numel() * 4} bytes read and written")
+        log("[bench] profile steps done")
+        return
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h = tree.host()
+    if h["status"]:
+        raise SystemExit(f"build status word {h['status']}")
+    log(f"[bench] warmup done: {h['n_nodes']} nodes, {h['n_points']} stored points")
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step")
+
+    # per-kernel timing over a second timed region with every launch bracketed by events
+    with lib.trace() as tr:
+        for _ in range(args.steps):
+            step()
+    summ = tr.summary()
+    per_step = {k: (c / args.steps, t / args.steps) for k, (c, t) in summ.items()}
+    build_kernels = set()
+    with lib.trace() as tb:
+        builder.build(x, y, z, m)
+    for name, _ in tb.records:
+        build_kernels.add(name)
+    build_ms = sum(ms for _, ms in tb.records)
+    dom = max(per_step.items(), key=lambda kv: kv[1][1])
+    dom_name, (dom_launches, dom_ms_step) = dom
+    dom_avg = summ[dom_name][1] / summ[dom_name][0]
+    per_unit = KERNEL_BYTES.get(dom_name)
+    if per_unit is not None:
+        achieved = per_unit * N / (dom_avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "bytes_per_particle": per_unit, "avg_launch_ms": round(dom_avg, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": dom_name, "avg_launch_ms": round(dom_avg, 4)}
+    S = h["n_points"]
+    b_alg = 48.0 * N + 14.0 * S
+    build_frac = b_alg / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    ids, nsel = lib.select_nodes(tree, cam, 1.0, cfg["n"], workspace=sel_ws)
+    k = int(lib._to_numpy(nsel)[0])
+    cut_nodes = lib._to_numpy(ids[:k]).astype(np.int64)
+    drawn = int(h["pt_count"][cut_nodes].astype(np.int64).sum())
+
+    extra = {}
+    if not args.no_full_render:
+        full_ws = torch.empty(lib.splat_workspace_bytes(N, cam), dtype=torch.uint8, device=dev)
+        full = lib.splat(x, y, z, m, cam, workspace=full_ws)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        reps = 3
+        for _ in range(reps):
+            lib.splat(x, y, z, m, cam, workspace=full_ws, out=full)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        full_ms = f0.elapsed_time(f1) / reps
+        extra["splat_full_ms"] = round(full_ms, 3)
+        extra["splat_full_Mpts_s"] = round(N / full_ms / 1e3, 1)
+        step()
+        torch.cuda.synchronize()
+        extra.update({k: float(f"{v:.4g}") for k, v in image_errors(lod_img, full).items()})
+        del full_ws
+
+    splat_ms = sum(t for k, (c, t) in per_step.items() if k not in build_kernels)
+    out = {
+        "metric": METRIC,
+        "value": round(N / ms_step / 1e3, 2),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 keys, f64 masses, f32 splat",
+        "data": "synthetic",
+        "config": {"workload": cfg["label"], "particles": N, "n": cfg["n"], "max_depth": cfg["D"],
+                   "image": f"{cfg['W']}x{cfg['H']}", "parallelism": "single GPU"},
+        "roofline": roof,
+        "build_ms": round(build_ms, 4),
+        "build_Mparticles_s": round(N / build_ms / 1e3, 1),
+        "build_B_alg_GB": round(b_alg / 1e9, 3),
+        "build_frac_hbm_B_alg": round(build_frac, 4),
+        "stored_points": S,
+        "nodes": h["n_nodes"],
+        "lod_points_drawn": drawn,
+        "splat_lod_ms": round(splat_ms, 4),
+        "splat_lod_Mpts_s": round(drawn / max(splat_ms, 1e-9) / 1e3, 1),
+        "kernels_ms_per_step": {k: round(t, 4) for k, (c, t) in sorted(per_step.items(), key=lambda kv: -kv[1][1])},
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(snap, cfg, args.cpu_sample)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -238,6 +238,21 @@ lod_status splat_render_backward(const float *x, const float *y, const float *z,
 lod_status lod_workspace_view(const lod_input *in, const lod_params *p, void *workspace,
                               uint32_t which, void **device_ptr, uint64_t *count);
 
+/* Per-kernel timing for diagnostics and benchmarks.  Between
+ * lod_trace_begin() and lod_trace_end() on one host thread, every kernel an
+ * entry point enqueues is bracketed by two hipEvents recorded on its stream
+ * (this adds a few microseconds per launch).  lod_trace_end() waits for
+ * those events, writes up to `cap` records (static kernel name, elapsed
+ * milliseconds) in launch order, stores the number of launches in
+ * *n_records, and releases the events.  LOD_EINVAL if no trace is open. */
+typedef struct {
+  const char *name;
+  float ms;
+} lod_kernel_time;
+
+lod_status lod_trace_begin(void);
+lod_status lod_trace_end(lod_kernel_time *records, uint32_t cap, uint32_t *n_records);
+
 /* Static description of an error code. */
 const char *lod_status_string(lod_status s);
 

@@ -7,6 +7,7 @@
 
 #include "lod.h"
 #include "lod_internal.hpp"
+#include "lod_trace.hpp"
 
 namespace {
 
@@ -58,7 +59,42 @@ bool tree_arrays_ok(const lod_tree *t) {
 
 }  // namespace
 
+namespace lodh {
+Trace *&current_trace() {
+  static thread_local Trace *t = nullptr;
+  return t;
+}
+}  // namespace lodh
+
 extern "C" {
+
+lod_status lod_trace_begin(void) {
+  lodh::Trace *&t = lodh::current_trace();
+  if (t) return LOD_EINVAL;
+  t = new lodh::Trace();
+  return LOD_OK;
+}
+
+lod_status lod_trace_end(lod_kernel_time *records, uint32_t cap, uint32_t *n_records) {
+  lodh::Trace *&t = lodh::current_trace();
+  if (!t) return LOD_EINVAL;
+  lod_status st = LOD_OK;
+  uint32_t k = 0;
+  for (auto &r : t->recs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      st = LOD_EDEVICE;
+    if (records && k < cap) records[k] = lod_kernel_time{r.name, ms};
+    ++k;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  if (n_records) *n_records = k;
+  delete t;
+  t = nullptr;
+  return st;
+}
+
 
 lod_status lod_build_plan(const lod_input *in, const lod_params *p, size_t *workspace_bytes,
                           uint64_t *node_cap_bound, uint64_t *point_cap_bound) {

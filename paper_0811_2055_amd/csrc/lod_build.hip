@@ -957,7 +957,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   fill_u32(lvl, p.max_depth + 4, 0, st);
   if (N == 0) return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 
-  hipLaunchKernelGGL(k_check_offsets, dim3(1), dim3(256), 0, st, a);
+  LOD_LAUNCH(k_check_offsets, dim3(1), dim3(256), 0, st, a);
 
   uint32_t *keyA = (uint32_t *)(W + L.keyA), *keyB = (uint32_t *)(W + L.keyB);
   uint32_t *idxA = (uint32_t *)(W + L.idxA), *idxB = (uint32_t *)(W + L.idxB);
@@ -968,26 +968,26 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const uint64_t tiles = (N + TILE - 1) / TILE;
   const uint64_t hist_n = (uint64_t)RADIX * tiles;
 
-  hipLaunchKernelGGL(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a,
+  LOD_LAUNCH(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a,
                      keyA, loA, thist, tiles);
   const int kb = key_bits(p, n_snap);
   const int passes = std::max(1, (kb + 7) / 8);
   // pass 0: keys/fractions from keygen (A), ids implicit, masses from the input; writes B
   device_scan<uint32_t>(thist, hist_n, scan32, st);
-  hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 0, thist, tiles,
+  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 0, thist, tiles,
                      keyA, (const uint32_t *)nullptr, loA, in.mass, keyB, idxB, loB, mB);
   uint32_t *ks = keyB, *is = idxB; uint64_t *ls = loB; float *ms = mB;
   uint32_t *kd = keyA, *id = idxA; uint64_t *ld = loA; float *md = mA;
   for (int ps = 1; ps < passes; ++ps) {
-    hipLaunchKernelGGL(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
+    LOD_LAUNCH(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
     device_scan<uint32_t>(thist, hist_n, scan32, st);
-    hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 8 * ps, thist, tiles,
+    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 8 * ps, thist, tiles,
                        ks, is, ls, ms, kd, id, ld, md);
     std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(ms, md);
   }
   Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint64_t *)(W + L.K)};
 
-  hipLaunchKernelGGL(k_density, dim3((unsigned)tiles), dim3(TB), 0, st, a, ks, is,
+  LOD_LAUNCH(k_density, dim3((unsigned)tiles), dim3(TB), 0, st, a, ks, is,
                      (uint32_t *)(W + L.w), (uint64_t *)(W + L.K));
 
   TreeArgs t{};
@@ -999,21 +999,21 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   t.wit = (uint32_t *)(W + L.wit);
 
   const int D = (int)p.max_depth;
-  hipLaunchKernelGGL(k_roots, dim3(1), dim3(1024), 0, st, a, t, ks);
+  LOD_LAUNCH(k_roots, dim3(1), dim3(1024), 0, st, a, t, ks);
   const uint64_t per_level = N / ((uint64_t)p.n + 1) + n_snap;
   const unsigned oct_grid = (unsigned)std::min<uint64_t>(4096, (per_level * 8 + TB - 1) / TB + 1);
   for (int d = 0; d < D; ++d) {
-    hipLaunchKernelGGL(k_octants, dim3(oct_grid), dim3(TB), 0, st, a, t, ks, d);
-    hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, st, a, t, d);
+    LOD_LAUNCH(k_octants, dim3(oct_grid), dim3(TB), 0, st, a, t, ks, d);
+    LOD_LAUNCH(k_emit, dim3(1), dim3(1024), 0, st, a, t, d);
   }
   // level D has no children: its end was written by the last emit (or roots)
   const unsigned cap_grid = (unsigned)std::min<uint64_t>(4096, (L.node_cap + TB - 1) / TB);
-  hipLaunchKernelGGL(k_ptcount, dim3(cap_grid), dim3(TB), 0, st, a, t, D);
+  LOD_LAUNCH(k_ptcount, dim3(cap_grid), dim3(TB), 0, st, a, t, D);
   device_scan<uint64_t>(out.pt_begin, L.node_cap, (uint64_t *)(W + L.scan64), st);
-  hipLaunchKernelGGL(k_ptfinish, dim3(1), dim3(1), 0, st, a, t);
+  LOD_LAUNCH(k_ptfinish, dim3(1), dim3(1), 0, st, a, t);
 
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
-  hipLaunchKernelGGL(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
+  LOD_LAUNCH(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
 
   uint32_t *top[2] = {(uint32_t *)(W + L.top0), (uint32_t *)(W + L.top1)};
   // the per-node reference schedule needs the level sizes on the host
@@ -1034,19 +1034,19 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
   for (int d = D; d >= 0; --d) {
     if (d < D)
-      hipLaunchKernelGGL(k_internal_mass, dim3((unsigned)std::min<uint64_t>(1024, L.node_cap / TB + 1)),
+      LOD_LAUNCH(k_internal_mass, dim3((unsigned)std::min<uint64_t>(1024, L.node_cap / TB + 1)),
                          dim3(TB), 0, st, a, t, d);
     SelArgs sa{top[(d + 1) & 1], top[d & 1], (uint32_t)(N - 1)};
     if (p.mode == 0) {
       // reference schedule: one launch per selecting node of this level
       for (uint32_t v = hl[d]; v < hl[d + 1]; ++v) {
         if (hcount[v] <= p.n) continue;
-        hipLaunchKernelGGL(k_select_one, dim3(1), dim3(sel_threads), 0, st, a, t, s, sa, d, v - hl[d]);
+        LOD_LAUNCH(k_select_one, dim3(1), dim3(sel_threads), 0, st, a, t, s, sa, d, v - hl[d]);
       }
     } else {
-      hipLaunchKernelGGL(k_select_level, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
+      LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
     }
-    hipLaunchKernelGGL(k_sel_output, dim3(sel_grid), dim3(TB), 0, st, a, t, s, sa, d);
+    LOD_LAUNCH(k_sel_output, dim3(sel_grid), dim3(TB), 0, st, a, t, s, sa, d);
   }
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
@@ -1062,13 +1062,13 @@ __global__ void k_fill(T *p, uint64_t n, T v) {
 void fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st) {
   if (!n) return;
   const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
-  hipLaunchKernelGGL(k_fill<uint64_t>, dim3(g), dim3(256), 0, st, p, n, v);
+  LOD_LAUNCH(k_fill<uint64_t>, dim3(g), dim3(256), 0, st, p, n, v);
 }
 
 void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
   if (!n) return;
   const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
-  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(g), dim3(256), 0, st, p, n, v);
+  LOD_LAUNCH(k_fill<uint32_t>, dim3(g), dim3(256), 0, st, p, n, v);
 }
 
 void *workspace_view(void *ws, const BuildLayout &L, uint32_t which, uint64_t N, int passes, uint64_t *count) {

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "lod_device.hpp"
+#include "lod_trace.hpp"
 
 namespace {
 
@@ -64,13 +65,13 @@ void device_scan(T *data, uint64_t n, T *tmp, hipStream_t s) {
   if (n == 0) return;
   const uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nb == 1) {
-    hipLaunchKernelGGL(k_scan_block<T>, dim3(1), dim3(SCAN_TB), 0, s, data, n, (T *)nullptr);
+    LOD_LAUNCH(k_scan_block<T>, dim3(1), dim3(SCAN_TB), 0, s, data, n, (T *)nullptr);
     return;
   }
   T *sums = tmp;
-  hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(SCAN_TB), 0, s, data, n, sums);
+  LOD_LAUNCH(k_scan_block<T>, dim3((unsigned)nb), dim3(SCAN_TB), 0, s, data, n, sums);
   device_scan<T>(sums, nb, tmp + nb, s);
-  hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)nb), dim3(SCAN_TB), 0, s, data, n, (const T *)sums);
+  LOD_LAUNCH(k_scan_add<T>, dim3((unsigned)nb), dim3(SCAN_TB), 0, s, data, n, (const T *)sums);
 }
 
 }  // namespace

@@ -497,25 +497,25 @@ lod_status launch_splat(const float *x, const float *y, const float *z, const fl
   const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(2048, (pts + 1023) / 1024));
   const size_t lds1 = 4 * (size_t)nt, lds2 = 8 * (size_t)nt;
   if (pts) {
-    hipLaunchKernelGGL(k_bin_count, dim3(grid), dim3(PT), lds1, st, x, y, z, count, count_dev, c, tcount);
+    LOD_LAUNCH(k_bin_count, dim3(grid), dim3(PT), lds1, st, x, y, z, count, count_dev, c, tcount);
   }
   // tile offsets (exclusive), cursor copy, slices
-  hipLaunchKernelGGL(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, tcount, toff, (uint64_t)nt + 1);
+  LOD_LAUNCH(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, tcount, toff, (uint64_t)nt + 1);
   device_scan<uint32_t>(toff, nt + 1, stmp, st);
-  hipLaunchKernelGGL(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, toff, tcur, (uint64_t)nt + 1);
+  LOD_LAUNCH(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, toff, tcur, (uint64_t)nt + 1);
   if (pts) {
-    hipLaunchKernelGGL(k_bin_fill, dim3(grid), dim3(PT), lds2, st, x, y, z, m, count, count_dev, c, tcur, bu, bv,
+    LOD_LAUNCH(k_bin_fill, dim3(grid), dim3(PT), lds2, st, x, y, z, m, count, count_dev, c, tcur, bu, bv,
                        bm, L.max_pairs, status);
   }
-  hipLaunchKernelGGL(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
+  LOD_LAUNCH(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
   fill_u32(soff + nt, 1, 0, st);
   device_scan<uint32_t>(soff, nt + 1, stmp, st);
   const unsigned agrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, L.max_slices));
   if (pts) {
-    hipLaunchKernelGGL(k_accumulate, dim3(agrid), dim3(PT), 0, st, toff, tcount, soff, nt, bu, bv, bm, c, partial,
+    LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, toff, tcount, soff, nt, bu, bv, bm, c, partial,
                        L.max_slices, L.max_pairs);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial, c, image,
+  LOD_LAUNCH(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial, c, image,
                      L.max_slices);
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
@@ -526,7 +526,7 @@ lod_status launch_splat_backward(const float *x, const float *y, const float *z,
   if (!count) return LOD_OK;
   Cam c = make_cam(cam, sp, nullptr);
   const unsigned grid = (unsigned)std::min<uint64_t>(65535, (count + PT - 1) / PT);
-  hipLaunchKernelGGL(k_backward, dim3(grid), dim3(PT), 0, st, x, y, z, m, count, c, grad, gm, gx, gy, gz);
+  LOD_LAUNCH(k_backward, dim3(grid), dim3(PT), 0, st, x, y, z, m, count, c, grad, gm, gx, gy, gz);
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
 
@@ -553,11 +553,11 @@ lod_status launch_lod_gather(const lod_tree &tree, const uint32_t *node_ids, con
   uint64_t *offs = (uint64_t *)(W + L.offs);
   uint64_t *cnt = (uint64_t *)(W + L.count);
   const unsigned g = (unsigned)std::min<uint64_t>(4096, (L.max_ids + 255) / 256);
-  hipLaunchKernelGGL(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, L.max_ids, offs);
+  LOD_LAUNCH(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, L.max_ids, offs);
   device_scan<uint64_t>(offs, L.max_ids + 1, (uint64_t *)(W + L.scan_tmp), st);
-  hipLaunchKernelGGL(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, L.max_ids, L.max_points, cnt);
+  LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, L.max_ids, L.max_points, cnt);
   const unsigned dg = (unsigned)std::min<uint64_t>(16384, L.max_ids);
-  hipLaunchKernelGGL(k_lod_decode, dim3(dg), dim3(PT), 0, st, tree, node_ids, n_ids, L.max_ids, offs, L.max_points,
+  LOD_LAUNCH(k_lod_decode, dim3(dg), dim3(PT), 0, st, tree, node_ids, n_ids, L.max_ids, offs, L.max_points,
                      (float *)(W + L.x), (float *)(W + L.y), (float *)(W + L.z), (float *)(W + L.m));
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
@@ -580,10 +580,10 @@ lod_status launch_cut(const lod_tree &tree, const lod_camera &cam, float tau_px,
   c.F = (double)cam.F;
   c.tau_cbrt = (double)tau_px * std::cbrt((double)n);
   const unsigned g = (unsigned)std::min<uint64_t>(4096, (nc + 256) / 256);
-  hipLaunchKernelGGL(k_cut_flags, dim3(g), dim3(256), 0, st, tree, c, nc, keep);
-  hipLaunchKernelGGL(k_copy_u32, dim3(g), dim3(256), 0, st, keep, scan, nc + 1);
+  LOD_LAUNCH(k_cut_flags, dim3(g), dim3(256), 0, st, tree, c, nc, keep);
+  LOD_LAUNCH(k_copy_u32, dim3(g), dim3(256), 0, st, keep, scan, nc + 1);
   device_scan<uint32_t>(scan, nc + 1, tmp, st);
-  hipLaunchKernelGGL(k_cut_write, dim3(g), dim3(256), 0, st, tree, nc, keep, scan, node_ids, cap, n_selected);
+  LOD_LAUNCH(k_cut_write, dim3(g), dim3(256), 0, st, tree, nc, keep, scan, node_ids, cap, n_selected);
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
 

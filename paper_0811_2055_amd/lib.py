@@ -22,7 +22,7 @@ NONE = 0xFFFFFFFF
 EXPORTS = [
     "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
     "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
-    "lod_workspace_view", "lod_status_string", "lod_version",
+    "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
 
@@ -54,6 +54,10 @@ class CameraC(C.Structure):
     _fields_ = [("projection", C.c_uint32), ("W", C.c_uint32), ("H", C.c_uint32),
                 ("pos", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3),
                 ("fwd", C.c_float * 3), ("F", C.c_float), ("near_z", C.c_float)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("ms", C.c_float)]
 
 
 class SplatParamsC(C.Structure):
@@ -90,6 +94,8 @@ def load():
                                           C.POINTER(SplatParamsC), P, P, P, P, P, P]
     lib.lod_workspace_view.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_uint32,
                                        C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]
+    lib.lod_trace_begin.argtypes = []
+    lib.lod_trace_end.argtypes = [C.POINTER(KernelTime), C.c_uint32, C.POINTER(C.c_uint32)]
     lib.lod_status_string.argtypes = [st]
     lib.lod_status_string.restype = C.c_char_p
     lib.lod_version.restype = C.c_char_p
@@ -314,6 +320,32 @@ def build(x, y, z, m, params: BuildParams, snap_offsets=None) -> Tree:
     nsnap = 1 if snap_offsets is None else int(snap_offsets.numel()) - 1
     b = Builder(int(x.numel()), params, x.device, nsnap)
     return b.build(x, y, z, m, snap_offsets)
+
+
+class trace:
+    """Context manager collecting (kernel name, ms) for every launch inside it."""
+
+    def __enter__(self):
+        _check(load().lod_trace_begin(), "lod_trace_begin")
+        self.records = []
+        return self
+
+    def __exit__(self, *exc):
+        lib = load()
+        cap = 1 << 16
+        buf = (KernelTime * cap)()
+        n = C.c_uint32()
+        _check(lib.lod_trace_end(buf, cap, C.byref(n)), "lod_trace_end")
+        self.records = [(buf[i].name.decode(), float(buf[i].ms)) for i in range(min(n.value, cap))]
+        return False
+
+    def summary(self):
+        """{kernel: (launches, total ms)}"""
+        out = {}
+        for name, ms in self.records:
+            c, t = out.get(name, (0, 0.0))
+            out[name] = (c + 1, t + ms)
+        return out
 
 
 # ---------------------------------------------------------------------------
