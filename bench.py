@@ -256,6 +256,7 @@ def main():
         "splat_lod_ms": round(splat_ms, 4),
         "splat_lod_Mpts_s": round(drawn / max(splat_ms, 1e-9) / 1e3, 1),
         "kernels_ms_per_step": {k: round(t, 4) for k, (c, t) in sorted(per_step.items(), key=lambda kv: -kv[1][1])},
+        "select_ms_by_level": [round(ms, 4) for name, ms in tb.records if name.startswith("k_select")],
     }
     out.update(extra)
     if not args.no_cpu_baseline:

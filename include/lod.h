@@ -71,7 +71,7 @@ typedef struct {
   int32_t alpha;
   uint64_t seed;
   uint32_t mode;
-  uint32_t select_threads;   /* 0 = tuned default; else 64..1024, multiple of 64 */
+  uint32_t select_threads;   /* 0 = default (1024); else a power of two in 64..1024 */
 } lod_params;
 
 /* Particle input, structure of arrays, all device float32 [n_particles].

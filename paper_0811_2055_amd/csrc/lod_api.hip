@@ -18,7 +18,8 @@ lod_status check_params(const lod_input *in, const lod_params *p) {
   if (p->density_level > p->max_depth) return LOD_EINVAL;
   if (p->alpha < -1 || p->alpha > 1) return LOD_EINVAL;
   if (p->mode > 1) return LOD_EINVAL;
-  if (p->select_threads && (p->select_threads % 64 || p->select_threads < 64 || p->select_threads > 1024))
+  if (p->select_threads &&
+      ((p->select_threads & (p->select_threads - 1)) || p->select_threads < 64 || p->select_threads > 1024))
     return LOD_EINVAL;
   const uint32_t ns = in->snap_offsets ? in->n_snapshots : 1;
   if (in->snap_offsets && in->n_snapshots < 1) return LOD_EINVAL;

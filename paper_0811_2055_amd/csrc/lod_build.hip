@@ -332,26 +332,43 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   const bool has_prev = base > 0;
   const bool has_next = base + tile_n < N;
   if (threadIdx.x == 0) {
+    // runs crossing the tile edges: galloping search outward from the edge
     uint64_t s0 = base;
     if (has_prev && cell[0] == cell[1]) {
       const uint32_t c = cell[1];
-      uint64_t lo = 0, hi = base;
-      while (lo < hi) {
-        const uint64_t mid = lo + ((hi - lo) >> 1);
-        if ((skey[mid] >> sh) < c) lo = mid + 1; else hi = mid;
+      uint64_t right = base, step = 1, lo = 0;
+      while (true) {
+        if (right < step) { lo = 0; break; }
+        const uint64_t probe = right - step;
+        if ((skey[probe] >> sh) < c) { lo = probe + 1; break; }
+        right = probe;
+        step <<= 1;
       }
-      s0 = lo;
+      uint64_t l = lo, h = right;
+      while (l < h) {
+        const uint64_t mid = l + ((h - l) >> 1);
+        if ((skey[mid] >> sh) < c) l = mid + 1; else h = mid;
+      }
+      s0 = l;
     }
     first_start = s0;
     uint64_t e0 = base + tile_n;
     if (has_next && cell[tile_n] == cell[tile_n + 1]) {
       const uint32_t c = cell[tile_n];
-      uint64_t lo = base + tile_n, hi = N;
-      while (lo < hi) {
-        const uint64_t mid = lo + ((hi - lo) >> 1);
-        if ((skey[mid] >> sh) <= c) lo = mid + 1; else hi = mid;
+      uint64_t known = base + tile_n - 1, step = 1, hi = N;
+      while (true) {
+        const uint64_t probe = known + step;
+        if (probe >= N) { hi = N; break; }
+        if ((skey[probe] >> sh) > c) { hi = probe; break; }
+        known = probe;
+        step <<= 1;
       }
-      e0 = lo;
+      uint64_t l = known + 1, h = hi;
+      while (l < h) {
+        const uint64_t mid = l + ((h - l) >> 1);
+        if ((skey[mid] >> sh) <= c) l = mid + 1; else h = mid;
+      }
+      e0 = l;
     }
     last_end = e0;
   }
@@ -648,6 +665,7 @@ __global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, i
 // selection: per node holding > n particles, the n+1 smallest (K, id)
 
 constexpr int SMALL = 512;
+constexpr int KBINS = 4096;
 
 struct SelArgs {
   const uint32_t *top_prev;   // children's lists (level d+1)
@@ -673,12 +691,11 @@ __device__ __forceinline__ uint32_t seg_pos(const Segs &g, const SelArgs &sa, in
 __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
                             uint32_t v, int d) {
   __shared__ Segs g;
-  __shared__ uint32_t hist[RADIX];
+  __shared__ uint32_t hist[KBINS];
   __shared__ uint64_t ck[SMALL];
   __shared__ uint32_t cidx[SMALL];
   __shared__ uint32_t cpos[SMALL];
   __shared__ uint32_t ccount;
-  __shared__ uint64_t red64[1024 / WAVE + 1];
   __shared__ uint32_t red32[1024 / WAVE + 1];
   __shared__ uint64_t sh_kt;
   __shared__ uint32_t sh_it, sh_pt;
@@ -707,34 +724,50 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __syncthreads();
   const int nseg = (int)g.nseg;
 
-  // pass 0: largest K among the candidates
-  uint64_t mx = 0;
-  for (int k = 0; k < nseg; ++k)
-    for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) mx = max(mx, s.K[seg_pos(g, sa, k, j)]);
+  // round 0: 4096-bin log-scale histogram of K over all candidates
+  for (int i = threadIdx.x; i < KBINS; i += BS) hist[i] = 0;
+  if (threadIdx.x == 0) { sh_b = 0; sh_below = 0; sh_cnt = 0; }
+  __syncthreads();
+  uint32_t inplay = 0;
+  for (int k = 0; k < nseg; ++k) {
+    inplay += g.len[k];
+    for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) atomicAdd(&hist[kbin(s.K[seg_pos(g, sa, k, j)])], 1u);
+  }
+  __syncthreads();
+  uint32_t r = n;                            // 0-based rank of the witness among in-play
   {
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) mx = max(mx, (uint64_t)__shfl_xor(mx, o, WAVE));
-    if (lane == 0) red64[wid] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t r = 0;
-      for (int ww = 0; ww < BS / WAVE; ++ww) r = max(r, red64[ww]);
-      red64[0] = r;
+    const int per = KBINS / BS;
+    uint32_t loc = 0;
+    for (int i = 0; i < per; ++i) loc += hist[threadIdx.x * per + i];
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t>(loc, red32, tot);
+    if (r >= ex && r < ex + loc) {
+      uint32_t below = ex;
+      for (int i = 0; i < per; ++i) {
+        const uint32_t h = hist[threadIdx.x * per + i];
+        if (r < below + h) { sh_b = threadIdx.x * per + i; sh_below = below; sh_cnt = h; break; }
+        below += h;
+      }
     }
     __syncthreads();
-    mx = red64[0];
-    __syncthreads();
   }
-  // radix select over K, then over id among equal K
-  int kshift = mx ? 64 - __clzll(mx) : 0;   // K >> kshift == kp for all candidates
-  uint64_t kp = 0;
+  r -= sh_below;
+  inplay = sh_cnt;
+  int kshift;                                // K >> kshift == kp for the in-play candidates
+  uint64_t kp;
+  {
+    const uint32_t b0 = sh_b;
+    if (b0 < 128) { kp = b0; kshift = 0; }
+    else {
+      const int e = 7 + (int)((b0 - 128) / 64);
+      kp = 64 + (b0 - 128) % 64;
+      kshift = e - 6;
+    }
+  }
   int phase = 0;                             // 0: K bits, 1: id bits
   int ishift = 32;
   uint32_t ip = 0;
-  uint32_t r = n;                            // 0-based rank of the witness among in-play
-  uint32_t inplay = 0;
-  for (int k = 0; k < nseg; ++k) inplay += g.len[k];
+  __syncthreads();
   while (inplay > SMALL && !(phase == 1 && ishift == 0)) {
     if (phase == 0 && kshift == 0) { phase = 1; continue; }
     const int wb = phase == 0 ? min(8, kshift) : min(8, ishift);
@@ -1030,7 +1063,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
          hipStreamSynchronize(st) != hipSuccess))
       return LOD_EDEVICE;
   }
-  const unsigned sel_threads = p.select_threads ? p.select_threads : 256;
+  const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
   const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
   for (int d = D; d >= 0; --d) {
     if (d < D)

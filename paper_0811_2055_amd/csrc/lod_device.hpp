@@ -36,11 +36,35 @@ __device__ __forceinline__ uint64_t particle_U(uint64_t id, uint32_t snap, uint6
                                 (uint32_t)seed, (uint32_t)(seed >> 32)) + 1ull;
 }
 
+// floor(U 2^31 / w) for U <= 2^32, 1 <= w < 2^31, without a 64-bit divide:
+// 2^31 = a w + b, so the quotient is U a + floor(U b / w); the float64
+// estimates are off by at most one unit and the remainder corrects them.
+__device__ __forceinline__ uint64_t div_u2p31(uint64_t U, uint32_t w) {
+  uint32_t a = (uint32_t)(2147483648.0 / (double)w);
+  if ((uint64_t)a * w > 2147483648ull) --a;
+  const uint32_t b = (uint32_t)(2147483648ull - (uint64_t)a * w);
+  const uint64_t x = U * (uint64_t)b;
+  uint64_t q = (uint64_t)((double)x / (double)w);
+  int64_t r = (int64_t)(x - q * (uint64_t)w);
+  while (r < 0) { --q; r += w; }
+  while (r >= (int64_t)w) { ++q; r -= w; }
+  return U * (uint64_t)a + q;
+}
+
 // Integer selection key; smaller is kept first.
 __device__ __forceinline__ uint64_t selection_key(uint64_t U, uint32_t w, int alpha) {
-  if (alpha > 0) return (U << 31) / (uint64_t)w;
+  if (alpha > 0) return div_u2p31(U, w);
   if (alpha == 0) return U << 31;
   return U * (uint64_t)w;
+}
+
+// Monotone 12-bit log-scale bin of a 64-bit key: K < 128 maps to itself,
+// larger keys to 128 + 64 (e - 7) + the 6 bits after the leading one (e =
+// index of the leading one).  K1 < K2 implies kbin(K1) <= kbin(K2).
+__device__ __forceinline__ uint32_t kbin(uint64_t K) {
+  if (K < 128) return (uint32_t)K;
+  const int e = 63 - __clzll(K);
+  return 128u + (uint32_t)(e - 7) * 64u + (uint32_t)((K >> (e - 6)) & 63u);
 }
 
 // w^alpha as float64 (alpha in {-1,0,1}).

@@ -192,7 +192,27 @@ __device__ __forceinline__ void neumaier(float &s, float &c, float x) {
 
 // --- accumulation --------------------------------------------------------------
 
+// First and last index in [lo_clip, hi_clip] whose float32 offset
+// fl(t - (i + 1/2)) lies in [-R, R].  The offset is non-increasing in i, so
+// the set is an interval; a float estimate is corrected by exact tests.
+__device__ __forceinline__ bool clip_range(float t, float R, int lo_clip, int hi_clip, int &lo, int &hi) {
+  auto inside_hi = [&](int i) { return t - ((float)i + 0.5f) >= -R; };   // offset not below -R
+  auto inside_lo = [&](int i) { return t - ((float)i + 0.5f) <= R; };    // offset not above R
+  int a = (int)floorf(t - 0.5f - R);
+  while (!inside_lo(a)) ++a;
+  while (inside_lo(a - 1)) --a;
+  int b = (int)floorf(t - 0.5f + R);
+  while (!inside_hi(b)) --b;
+  while (inside_hi(b + 1)) ++b;
+  lo = max(a, lo_clip);
+  hi = min(b, hi_clip);
+  return lo <= hi;
+}
+
 // One block per slice; thread t owns pixel (t % 16, t / 16) of the tile.
+// Per chunk of 32 points, 8 threads serve one point: they find its pixel
+// range inside the tile, write its separable weights (at most 16 per axis)
+// to LDS, then add the rows sub, sub+8 of its footprint into the LDS tile.
 __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ tile_off,
                                                    const uint32_t *__restrict__ tile_count,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
@@ -201,11 +221,13 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
                                                    float *__restrict__ partial, uint64_t max_slices,
                                                    uint64_t max_pairs) {
   __shared__ float acc[TS * TS];
+  __shared__ float gxs[CHUNK][TS];
+  __shared__ float gys[CHUNK][TS];
+  __shared__ int rng[CHUNK][4];
   const uint32_t total_slices = slice_off[nt];
   const int lane_pt = threadIdx.x / PER_POINT;     // point within chunk
-  const int sub = threadIdx.x % PER_POINT;         // row group of that point
+  const int sub = threadIdx.x % PER_POINT;         // helper index for that point
   for (uint32_t sl = blockIdx.x; sl < total_slices && sl < max_slices; sl += gridDim.x) {
-    // tile of this slice: last t with slice_off[t] <= sl
     uint32_t lo = 0, hi = nt;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -216,28 +238,36 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
     const uint64_t pb = (uint64_t)tile_off[t] + (uint64_t)k * lodh::SPLAT_SLICE;
     const uint64_t pe = min(min((uint64_t)tile_off[t] + tile_count[t], pb + lodh::SPLAT_SLICE), max_pairs);
     const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
+    const int txe = min(tx0 + TS, (int)c.W) - 1, tye = min(ty0 + TS, (int)c.H) - 1;
     acc[threadIdx.x] = 0.0f;
     float s = 0.0f, cc = 0.0f;
     __syncthreads();
     for (uint64_t c0 = pb; c0 < pe; c0 += CHUNK) {
       const uint64_t q = c0 + lane_pt;
+      int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
+      float w = 0.0f;
       if (q < pe) {
         const float u = bu[q], v = bv[q];
-        const float w = bm[q] * c.norm;
-        int i0, i1, j0, j1;
-        if (axis_range(c, u, c.W, i0, i1) && axis_range(c, v, c.H, j0, j1)) {
-          i0 = max(i0, tx0); i1 = min(i1, tx0 + TS - 1);
-          j0 = max(j0, ty0); j1 = min(j1, ty0 + TS - 1);
-          for (int j = j0 + sub; j <= j1; j += PER_POINT) {
-            const float oy = v - ((float)j + 0.5f);
-            const float gy = w * expf(-(oy * oy) * c.inv2s2);
-            float *row = acc + (j - ty0) * TS - tx0;
-            for (int i = i0; i <= i1; ++i) {
-              const float ox = u - ((float)i + 0.5f);
-              atomicAdd(&row[i], gy * expf(-(ox * ox) * c.inv2s2));
-            }
+        w = bm[q] * c.norm;
+        if (clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
+          for (int e = sub; e <= i1 - i0; e += PER_POINT) {
+            const float ox = u - ((float)(i0 + e) + 0.5f);
+            gxs[lane_pt][e] = expf(-(ox * ox) * c.inv2s2);
           }
+          for (int e = sub; e <= j1 - j0; e += PER_POINT) {
+            const float oy = v - ((float)(j0 + e) + 0.5f);
+            gys[lane_pt][e] = w * expf(-(oy * oy) * c.inv2s2);
+          }
+        } else {
+          i1 = -1; j1 = -1;
         }
+      }
+      __syncthreads();
+      for (int j = j0 + sub; j <= j1; j += PER_POINT) {
+        const float gy = gys[lane_pt][j - j0];
+        float *row = acc + (j - ty0) * TS - tx0;
+        const float *gx = gxs[lane_pt] - i0;
+        for (int i = i0; i <= i1; ++i) atomicAdd(&row[i], gy * gx[i]);
       }
       __syncthreads();
       const float vsum = acc[threadIdx.x];
@@ -248,6 +278,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
     __syncthreads();
   }
+  (void)rng;
 }
 
 // Sum each tile's slice partials in slice order and write the image.
