@@ -62,8 +62,13 @@ typedef void *lod_stream_t;      /* hipStream_t */
  * probability grows with density^alpha.  seed: Philox4x32-10 key.
  * mode: 0 = one selection launch per node (reference schedule; reads the
  *           level sizes back to the host, so it synchronises the stream),
- *       1 = one selection launch per level over all of its nodes.
- * All modes produce identical bytes. */
+ *       1 = one selection launch per level over all of its nodes,
+ *       2 = one persistent launch over every node of every level: a block
+ *           reduces a node whose children are done and climbs to the parent
+ *           when it finishes the parent's last selecting child.
+ * All modes produce identical bytes.  select_threads (threads per node
+ * block) and persistent_blocks (mode 2 grid) are schedule parameters, e.g.
+ * from lod_autotune; 0 picks the defaults (1024 threads, 2 blocks per CU). */
 typedef struct {
   uint32_t n;
   uint32_t max_depth;
@@ -71,7 +76,9 @@ typedef struct {
   int32_t alpha;
   uint64_t seed;
   uint32_t mode;
-  uint32_t select_threads;   /* 0 = default (1024); else a power of two in 64..1024 */
+  uint32_t select_threads;     /* 0 or a power of two in 64..1024 */
+  uint32_t persistent_blocks;  /* 0 or 1..65535 */
+  uint32_t reserved;           /* must be 0 */
 } lod_params;
 
 /* Particle input, structure of arrays, all device float32 [n_particles].

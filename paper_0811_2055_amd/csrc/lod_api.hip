@@ -17,7 +17,7 @@ lod_status check_params(const lod_input *in, const lod_params *p) {
   if (p->max_depth > 10) return LOD_EINVAL;
   if (p->density_level > p->max_depth) return LOD_EINVAL;
   if (p->alpha < -1 || p->alpha > 1) return LOD_EINVAL;
-  if (p->mode > 1) return LOD_EINVAL;
+  if (p->mode > 2 || p->reserved != 0 || p->persistent_blocks > 65535) return LOD_EINVAL;
   if (p->select_threads &&
       ((p->select_threads & (p->select_threads - 1)) || p->select_threads < 64 || p->select_threads > 1024))
     return LOD_EINVAL;

@@ -312,7 +312,7 @@ __device__ __forceinline__ uint64_t block_incl_scan_op(uint64_t v, uint64_t *tmp
 // binary search over the sorted keys.
 __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__restrict__ skey,
                                                 const uint32_t *__restrict__ sidx,
-                                                uint32_t *__restrict__ w_out, uint64_t *__restrict__ K_out) {
+                                                uint32_t *__restrict__ w_out, uint16_t *__restrict__ kb_out) {
   __shared__ uint32_t cell[TILE + 2];     // cell[i+1] = cell of element base+i
   __shared__ uint64_t tmp[TB / WAVE + 1];
   __shared__ uint64_t incl_max[TB];
@@ -408,20 +408,27 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   const uint64_t prev_max = max(first_start, threadIdx.x ? incl_max[threadIdx.x - 1] : 0ull);
   // min over threads > t == reversed inclusive scan at position TB-2-t
   const uint64_t next_min = (threadIdx.x < TB - 1) ? rev_min[TB - 2 - threadIdx.x] : ~0ull;
-  const int sdb = 3 * a.D;
+  // run lengths, blocked -> LDS, then striped (coalesced) keys, ids and outputs
+  uint32_t *wl = (uint32_t *)cell;           // cell[] is no longer needed; reuse it
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const int li = t0 + i;
+    if (li < (int)tile_n) wl[li] = (uint32_t)(min(en[i], next_min) - max(st[i], prev_max));
+  }
+  __syncthreads();
+  const int sdb = 3 * a.D;
+#pragma unroll 4
+  for (int i = 0; i < ITEMS; ++i) {
+    const int li = i * TB + threadIdx.x;
     if (li >= (int)tile_n) break;
     const uint64_t e = base + li;
-    const uint64_t rs = max(st[i], prev_max);
-    const uint64_t re = min(en[i], next_min);
-    const uint32_t w = (uint32_t)(re - rs);
+    const uint32_t w = wl[li];
     const uint32_t k = skey[e];
     const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)k >> sdb) : 0u;
     const uint64_t U = particle_U(local_id(a, snap, sidx[e]), snap, a.seed);
     w_out[e] = w;
-    K_out[e] = selection_key(U, w, a.alpha);
+    kb_out[e] = (uint16_t)kbin(selection_key(U, w, a.alpha));
   }
 }
 
@@ -445,8 +452,10 @@ struct TreeArgs {
   // workspace
   uint32_t *lvl;      // [D+3] level starts; lvl[d+1] = end of level d
   uint32_t *cs;       // [node_cap * 9] octant starts (sorted positions) of internal nodes
-  uint32_t *sel_idx;  // [node_cap] index among selecting nodes of its level, or NONE
+  uint32_t *sel_idx;  // [node_cap] rank among all selecting nodes (levels in order), or NONE
   uint32_t *wit;      // [node_cap] witness sorted position, or NONE
+  uint32_t *pend;     // [node_cap] number of selecting children not yet reduced
+  uint32_t *lsel;     // [D+3] selecting nodes at levels < d (cumulative)
 };
 
 __device__ __forceinline__ void set_status(const BuildArgs &a, uint32_t bits) {
@@ -457,7 +466,7 @@ __device__ __forceinline__ void set_status(const BuildArgs &a, uint32_t bits) {
 __global__ __launch_bounds__(1024) void k_roots(BuildArgs a, TreeArgs t, const uint32_t *__restrict__ skey) {
   __shared__ uint32_t tmp[1024 / WAVE + 1];
   __shared__ uint32_t base_nodes, base_sel;
-  if (threadIdx.x == 0) { base_nodes = 0; base_sel = 0; t.lvl[0] = 0; }
+  if (threadIdx.x == 0) { base_nodes = 0; base_sel = 0; t.lvl[0] = 0; t.lsel[0] = 0; }
   __syncthreads();
   const int D = a.D;
   for (uint32_t s0 = 0; s0 < a.n_snap; s0 += blockDim.x) {
@@ -484,14 +493,14 @@ __global__ __launch_bounds__(1024) void k_roots(BuildArgs a, TreeArgs t, const u
       if (v < a.node_cap) {
         t.prefix[v] = s; t.depth[v] = 0; t.parent[v] = NONE; t.first_child[v] = NONE;
         t.child_mask[v] = 0; t.part_begin[v] = lo; t.part_count[v] = hi - lo;
-        t.sel_idx[v] = se ? base_sel + os : NONE; t.wit[v] = NONE;
+        t.sel_idx[v] = se ? base_sel + os : NONE; t.wit[v] = NONE; t.pend[v] = 0;
       } else set_status(a, LOD_STATUS_CAPACITY);
     }
     __syncthreads();
     if (threadIdx.x == 0) { base_nodes += tot_n; base_sel += tot_s; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) t.lvl[1] = min((uint64_t)base_nodes, a.node_cap);
+  if (threadIdx.x == 0) { t.lvl[1] = min((uint64_t)base_nodes, a.node_cap); t.lsel[1] = base_sel; }
 }
 
 // Octant boundaries of the internal nodes of level d: 8 lanes per node.
@@ -526,6 +535,7 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
   if (threadIdx.x == 0) { run_nodes = 0; run_sel = 0; }
   __syncthreads();
   const uint32_t next_base = e;
+  const uint32_t sel_base = t.lsel[d + 1];
   for (uint32_t v0 = b; v0 < e; v0 += blockDim.x) {
     const uint32_t v = v0 + threadIdx.x;
     uint32_t nkids = 0, nsel = 0, mask = 0;
@@ -544,9 +554,10 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
     const uint32_t os = block_excl_scan<uint32_t>(nsel, tmp, ts);
     if (v < e) {
       t.child_mask[v] = (uint8_t)mask;
+      t.pend[v] = nsel;
       if (nkids) {
         uint32_t c = next_base + run_nodes + ok;
-        uint32_t sidx = run_sel + os;
+        uint32_t sidx = sel_base + run_sel + os;
         if ((uint64_t)c + nkids > a.node_cap) {
           set_status(a, LOD_STATUS_CAPACITY);
           t.first_child[v] = NONE;
@@ -565,6 +576,7 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
             t.part_count[c] = cnt;
             t.sel_idx[c] = cnt > a.n ? sidx++ : NONE;
             t.wit[c] = NONE;
+            t.pend[c] = 0;
             ++c;
           }
         }
@@ -579,6 +591,7 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
   if (threadIdx.x == 0) {
     uint64_t end = (uint64_t)next_base + run_nodes;
     t.lvl[d + 2] = (uint32_t)min(end, a.node_cap);
+    t.lsel[d + 2] = sel_base + run_sel;
   }
 }
 
@@ -612,7 +625,7 @@ struct Sorted {
   const uint64_t *lo;
   const float *m;
   const uint32_t *w;
-  const uint64_t *K;
+  const uint16_t *kb;   // log-scale bin of the selection key
 };
 
 __device__ __forceinline__ void write_point(const BuildArgs &a, const TreeArgs &t, const Sorted &s,
@@ -628,6 +641,13 @@ __device__ __forceinline__ void write_point(const BuildArgs &a, const TreeArgs &
   t.qy[out] = quant_at(cy, (uint32_t)((l >> 16) & 0xFFFFu), D, d);
   t.qz[out] = quant_at(cz, (uint32_t)((l >> 32) & 0xFFFFu), D, d);
   t.pt_mass[out] = mass;
+}
+
+// Exact selection key of the particle at sorted position p.
+__device__ __forceinline__ uint64_t exact_K(const BuildArgs &a, const Sorted &s, uint32_t p) {
+  const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)s.key[p] >> (3 * a.D)) : 0u;
+  const uint64_t U = particle_U(local_id(a, snap, s.idx[p]), snap, a.seed);
+  return selection_key(U, s.w[p], a.alpha);
 }
 
 __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s) {
@@ -666,10 +686,10 @@ __global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, i
 
 constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
+constexpr int ILP = 4;
 
 struct SelArgs {
-  const uint32_t *top_prev;   // children's lists (level d+1)
-  uint32_t *top_cur;          // this level's lists
+  uint32_t *lists;            // top-(n+1) position lists by selecting rank
   uint32_t n_minus_1;         // N - 1
 };
 
@@ -680,16 +700,61 @@ struct Segs {
   uint32_t is_list[9];
 };
 
-// Candidate j of segment k as a sorted position; list entries are clamped
-// below N so that a list left unwritten by a failed child cannot send a read
-// out of bounds (the failure itself is reported through the status word).
-__device__ __forceinline__ uint32_t seg_pos(const Segs &g, const SelArgs &sa, int k, uint32_t j) {
-  return g.is_list[k] ? min(sa.top_prev[g.base[k] + j], sa.n_minus_1) : (uint32_t)(g.base[k] + j);
+// Calls f(p, kbin) for every candidate, ILP loads in flight per thread.  List
+// entries are clamped below N so that a list left unwritten by a failed child
+// cannot send a read out of bounds (the failure is reported in the status).
+template <typename F>
+__device__ __forceinline__ void for_candidates(const Segs &g, const SelArgs &sa, const Sorted &s, F f) {
+  const uint32_t BS = blockDim.x;
+  for (int k = 0; k < (int)g.nseg; ++k) {
+    const uint32_t L = g.len[k];
+    const bool lst = g.is_list[k];
+    const uint64_t base = g.base[k];
+    for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * ILP) {
+      uint32_t p[ILP];
+      uint32_t kb[ILP];
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) {
+        const uint32_t j = j0 + u * BS;
+        p[u] = NONE;
+        if (j < L) p[u] = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
+      }
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) kb[u] = (p[u] != NONE) ? s.kb[p[u]] : 0u;
+#pragma unroll
+      for (int u = 0; u < ILP; ++u)
+        if (p[u] != NONE) f(p[u], kb[u]);
+    }
+  }
 }
 
-// Selects for node v; must be called by the whole block.  BS = blockDim.x.
+__device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArgs &t, uint32_t v, Segs &g) {
+  const uint32_t n = a.n;
+  const uint32_t fc = t.first_child[v];
+  uint32_t ns = 0;
+  if (fc == NONE) {
+    g.base[0] = t.part_begin[v]; g.len[0] = (uint32_t)t.part_count[v]; g.is_list[0] = 0; ns = 1;
+  } else {
+    const int nk = __popc((uint32_t)t.child_mask[v]);
+    for (int k = 0; k < nk; ++k) {
+      const uint32_t u = fc + k;
+      if (t.part_count[u] > n) {
+        g.base[ns] = (uint64_t)t.sel_idx[u] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
+      } else {
+        g.base[ns] = t.part_begin[u]; g.len[ns] = (uint32_t)t.part_count[u]; g.is_list[ns] = 0;
+      }
+      ++ns;
+    }
+  }
+  g.nseg = ns;
+}
+
+// Finds the n+1 smallest (K, id) among node v's candidates and writes their
+// sorted positions, ascending, to its list; the (n+1)-th is the witness.
+// Round 0 histograms the 12-bit log-scale bin of K (stored per particle); the
+// exact K is recomputed only for candidates in the threshold bin.  Whole block.
 __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
-                            uint32_t v, int d) {
+                            uint32_t v) {
   __shared__ Segs g;
   __shared__ uint32_t hist[KBINS];
   __shared__ uint64_t ck[SMALL];
@@ -702,37 +767,11 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __shared__ uint32_t sh_b, sh_below, sh_cnt;
   const uint32_t n = a.n;
   const int BS = blockDim.x;
-  if (threadIdx.x == 0) {
-    const uint32_t fc = t.first_child[v];
-    uint32_t ns = 0;
-    if (fc == NONE) {
-      g.base[0] = t.part_begin[v]; g.len[0] = (uint32_t)t.part_count[v]; g.is_list[0] = 0; ns = 1;
-    } else {
-      const int nk = __popc((uint32_t)t.child_mask[v]);
-      for (int k = 0; k < nk; ++k) {
-        const uint32_t u = fc + k;
-        if (t.part_count[u] > n) {
-          g.base[ns] = (uint64_t)t.sel_idx[u] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
-        } else {
-          g.base[ns] = t.part_begin[u]; g.len[ns] = (uint32_t)t.part_count[u]; g.is_list[ns] = 0;
-        }
-        ++ns;
-      }
-    }
-    g.nseg = ns;
-  }
-  __syncthreads();
-  const int nseg = (int)g.nseg;
-
-  // round 0: 4096-bin log-scale histogram of K over all candidates
+  if (threadIdx.x == 0) build_segments(a, t, v, g);
   for (int i = threadIdx.x; i < KBINS; i += BS) hist[i] = 0;
   if (threadIdx.x == 0) { sh_b = 0; sh_below = 0; sh_cnt = 0; }
   __syncthreads();
-  uint32_t inplay = 0;
-  for (int k = 0; k < nseg; ++k) {
-    inplay += g.len[k];
-    for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) atomicAdd(&hist[kbin(s.K[seg_pos(g, sa, k, j)])], 1u);
-  }
+  for_candidates(g, sa, s, [&](uint32_t p, uint32_t kb) { atomicAdd(&hist[kb], 1u); });
   __syncthreads();
   uint32_t r = n;                            // 0-based rank of the witness among in-play
   {
@@ -751,51 +790,49 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     }
     __syncthreads();
   }
+  const uint32_t b0 = sh_b;
   r -= sh_below;
-  inplay = sh_cnt;
+  uint32_t inplay = sh_cnt;
   int kshift;                                // K >> kshift == kp for the in-play candidates
   uint64_t kp;
-  {
-    const uint32_t b0 = sh_b;
-    if (b0 < 128) { kp = b0; kshift = 0; }
-    else {
-      const int e = 7 + (int)((b0 - 128) / 64);
-      kp = 64 + (b0 - 128) % 64;
-      kshift = e - 6;
-    }
+  if (b0 < 128) { kp = b0; kshift = 0; }
+  else {
+    const int e = 7 + (int)((b0 - 128) / 64);
+    kp = 64 + (b0 - 128) % 64;
+    kshift = e - 6;
   }
   int phase = 0;                             // 0: K bits, 1: id bits
   int ishift = 32;
   uint32_t ip = 0;
   __syncthreads();
+  // further rounds (rare): 8-bit digits of the exact K, then of the id
   while (inplay > SMALL && !(phase == 1 && ishift == 0)) {
     if (phase == 0 && kshift == 0) { phase = 1; continue; }
     const int wb = phase == 0 ? min(8, kshift) : min(8, ishift);
     const int sft = (phase == 0 ? kshift : ishift) - wb;
     for (int i = threadIdx.x; i < RADIX; i += BS) hist[i] = 0;
     __syncthreads();
-    for (int k = 0; k < nseg; ++k)
-      for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) {
-        const uint32_t p = seg_pos(g, sa, k, j);
-        const uint64_t K = s.K[p];
-        bool match;
-        uint32_t dg;
-        if (phase == 0) {
-          match = (kshift >= 64) ? true : ((K >> kshift) == kp);
-          dg = (uint32_t)((K >> sft) & ((1u << wb) - 1));
-        } else {
-          const uint32_t id = s.idx[p];
-          match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
-          dg = (id >> sft) & ((1u << wb) - 1);
-        }
-        if (match) atomicAdd(&hist[dg], 1u);
+    for_candidates(g, sa, s, [&](uint32_t p, uint32_t kb) {
+      if (kb != b0) return;
+      const uint64_t K = exact_K(a, s, p);
+      bool match;
+      uint32_t dg;
+      if (phase == 0) {
+        match = (K >> kshift) == kp;
+        dg = (uint32_t)((K >> sft) & ((1u << wb) - 1));
+      } else {
+        const uint32_t id = s.idx[p];
+        match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
+        dg = (id >> sft) & ((1u << wb) - 1);
       }
+      if (match) atomicAdd(&hist[dg], 1u);
+    });
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t below = 0, bsel = 0, cnt = 0;
-      for (uint32_t b = 0; b < (1u << wb); ++b) {
-        const uint32_t h = hist[b];
-        if (r < below + h) { bsel = b; cnt = h; break; }
+      for (uint32_t bb = 0; bb < (1u << wb); ++bb) {
+        const uint32_t h = hist[bb];
+        if (r < below + h) { bsel = bb; cnt = h; break; }
         below += h;
       }
       sh_b = bsel; sh_below = below; sh_cnt = cnt;
@@ -807,28 +844,25 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     else { ip = (ip << wb) | sh_b; ishift = sft; }
     __syncthreads();
   }
-  // collect the in-play candidates and rank them exactly
-  if (threadIdx.x == 0) ccount = 0;
+  // collect the in-play candidates with their exact keys and rank them
+  if (threadIdx.x == 0) { ccount = 0; sh_pt = NONE; }
   __syncthreads();
-  for (int k = 0; k < nseg; ++k)
-    for (uint32_t j = threadIdx.x; j < g.len[k]; j += BS) {
-      const uint32_t p = seg_pos(g, sa, k, j);
-      const uint64_t K = s.K[p];
-      bool match;
-      if (phase == 0) match = (kshift >= 64) ? true : ((K >> kshift) == kp);
-      else {
-        const uint32_t id = s.idx[p];
-        match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
-      }
-      if (match) {
-        const uint32_t slot = atomicAdd(&ccount, 1u);
-        if (slot < SMALL) { ck[slot] = K; cidx[slot] = s.idx[p]; cpos[slot] = p; }
-      }
+  for_candidates(g, sa, s, [&](uint32_t p, uint32_t kb) {
+    if (kb != b0) return;
+    const uint64_t K = exact_K(a, s, p);
+    bool match;
+    if (phase == 0) match = (K >> kshift) == kp;
+    else {
+      const uint32_t id = s.idx[p];
+      match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
     }
+    if (match) {
+      const uint32_t slot = atomicAdd(&ccount, 1u);
+      if (slot < SMALL) { ck[slot] = K; cidx[slot] = s.idx[p]; cpos[slot] = p; }
+    }
+  });
   __syncthreads();
   const uint32_t cc = min(ccount, (uint32_t)SMALL);
-  if (threadIdx.x == 0) sh_pt = NONE;
-  __syncthreads();
   for (uint32_t e = threadIdx.x; e < cc; e += BS) {
     const uint64_t Ke = ck[e];
     const uint32_t Ie = cidx[e];
@@ -848,17 +882,23 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint64_t Kt = sh_kt;
   const uint32_t It = sh_it;
   // order-preserving compaction of (K, id) <= (Kt, It)
-  uint32_t *out = sa.top_cur + (uint64_t)t.sel_idx[v] * (n + 1);
+  uint32_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
   uint32_t written = 0;
-  for (int k = 0; k < nseg; ++k) {
+  for (int k = 0; k < (int)g.nseg; ++k) {
     const uint32_t L = g.len[k];
+    const bool lst = g.is_list[k];
+    const uint64_t base = g.base[k];
     for (uint32_t j0 = 0; j0 < L; j0 += BS) {
       const uint32_t j = j0 + threadIdx.x;
       uint32_t f = 0, p = 0;
       if (j < L) {
-        p = seg_pos(g, sa, k, j);
-        const uint64_t K = s.K[p];
-        f = (K < Kt || (K == Kt && s.idx[p] <= It)) ? 1u : 0u;
+        p = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
+        const uint32_t kb = s.kb[p];
+        if (kb < b0) f = 1;
+        else if (kb == b0) {
+          const uint64_t K = exact_K(a, s, p);
+          f = (K < Kt || (K == Kt && s.idx[p] <= It)) ? 1u : 0u;
+        }
       }
       uint32_t tot;
       const uint32_t o = block_excl_scan<uint32_t>(f, red32, tot);
@@ -873,57 +913,128 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __syncthreads();
 }
 
-// One block per node of level d (grid-stride); non-selecting nodes skipped.
+// Renormalised masses, quantisation and output of one selecting node (whole block).
+__device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
+                            uint32_t v) {
+  __shared__ double red[1024 / WAVE + 1];
+  const uint32_t n = a.n;
+  const int alpha = a.alpha;
+  const uint32_t pt = t.wit[v];
+  if (pt == NONE || a.counts[1] > a.point_cap) return;
+  const uint32_t *list = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
+  const uint32_t kt = s.key[pt];
+  const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
+  const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
+  const double tau = weight_pow(s.w[pt], alpha) * 4294967296.0 / (double)Ut;
+  double acc = 0.0;
+  for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) {
+    const uint32_t p = min(list[j], sa.n_minus_1);
+    if (p == pt) continue;
+    const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
+    acc += (double)s.m[p] / pr;
+  }
+  const double tot = block_reduce_sum<double>(acc, red);
+  const double scale = t.node_mass[v] / tot;
+  const uint64_t ob = t.pt_begin[v];
+  const int d = t.depth[v];
+  for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) {
+    const uint32_t p = min(list[j], sa.n_minus_1);
+    if (p == pt) continue;
+    const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
+    const double mhat = (double)s.m[p] / pr;
+    const uint64_t o = ob + j - (p > pt ? 1u : 0u);
+    write_point(a, t, s, p, o, d, (float)(scale * mhat));
+  }
+}
+
+// mode 1: one launch per level, one block per selecting node of that level.
 __global__ __launch_bounds__(1024) void k_select_level(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
   const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
   for (uint32_t v = b + blockIdx.x; v < e; v += gridDim.x) {
     if (t.part_count[v] <= a.n) continue;
-    select_node(a, t, s, sa, v, d);
+    select_node(a, t, s, sa, v);
   }
 }
 
-// Per-node launch: node v_rank-th of level d (mode 0).
-__global__ __launch_bounds__(1024) void k_select_one(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d,
-                                                     uint32_t rank) {
-  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
-  const uint32_t v = b + rank;
-  if (v >= e || t.part_count[v] <= a.n) return;
-  select_node(a, t, s, sa, v, d);
+// mode 0: one launch per selecting node.
+__global__ __launch_bounds__(1024) void k_select_one(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, uint32_t v) {
+  if (v >= t.lvl[a.D + 1] || t.part_count[v] <= a.n) return;
+  select_node(a, t, s, sa, v);
 }
 
-// Renormalised masses, quantisation and output for the selecting nodes of level d.
-__global__ __launch_bounds__(TB) void k_sel_output(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
-  __shared__ double red[TB / WAVE + 1];
+__global__ __launch_bounds__(1024) void k_sel_output(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
   const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
-  const uint32_t n = a.n;
-  const bool cap_ok = a.counts[1] <= a.point_cap;
-  const int alpha = a.alpha;
   for (uint32_t v = b + blockIdx.x; v < e; v += gridDim.x) {
-    if (t.part_count[v] <= n || !cap_ok) continue;
-    const uint32_t pt = t.wit[v];
-    if (pt == NONE) continue;
-    const uint32_t *list = sa.top_cur + (uint64_t)t.sel_idx[v] * (n + 1);
-    const uint32_t kt = s.key[pt];
-    const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
-    const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
-    const double tau = weight_pow(s.w[pt], alpha) * 4294967296.0 / (double)Ut;
-    double acc = 0.0;
-    for (uint32_t j = threadIdx.x; j <= n; j += TB) {
-      const uint32_t p = min(list[j], sa.n_minus_1);
-      if (p == pt) continue;
-      const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
-      acc += (double)s.m[p] / pr;
+    if (t.part_count[v] <= a.n) continue;
+    output_node(a, t, s, sa, v);
+  }
+}
+
+// Selecting nodes none of whose children select: the starting points of the
+// persistent schedule (flags for a compaction).
+__global__ void k_bottom_flags(BuildArgs a, TreeArgs t, uint32_t *__restrict__ flag) {
+  const uint32_t nn = t.lvl[a.D + 1];
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= a.node_cap;
+       v += (uint64_t)gridDim.x * blockDim.x)
+    flag[v] = (v < nn && t.part_count[v] > a.n && t.pend[v] == 0) ? 1u : 0u;
+}
+
+__global__ void k_bottom_write(BuildArgs a, const uint32_t *__restrict__ flag, const uint32_t *__restrict__ scan,
+                               uint32_t *__restrict__ bottom, uint32_t *__restrict__ ctl) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.node_cap;
+       v += (uint64_t)gridDim.x * blockDim.x)
+    if (flag[v]) bottom[scan[v]] = (uint32_t)v;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[0] = scan[a.node_cap];   // number of starting nodes
+    ctl[1] = 0;                  // ticket
+  }
+}
+
+// mode 2: one persistent launch over every selecting node of every level.
+// A block takes a starting node by ticket, reduces it (node mass, selection,
+// output) and then, if it was the last of its parent's selecting children to
+// finish, continues with the parent; otherwise it takes the next ticket.  No
+// block ever waits for another, so the grid drains without spinning.
+__global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa,
+                                                            const uint32_t *__restrict__ bottom,
+                                                            uint32_t *__restrict__ ctl) {
+  __shared__ uint32_t sh_v;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t tk = atomicAdd(&ctl[1], 1u);
+      sh_v = tk < ctl[0] ? bottom[tk] : NONE;
     }
-    const double tot = block_reduce_sum<double>(acc, red);
-    const double scale = t.node_mass[v] / tot;
-    const uint64_t ob = t.pt_begin[v];
-    for (uint32_t j = threadIdx.x; j <= n; j += TB) {
-      const uint32_t p = min(list[j], sa.n_minus_1);
-      if (p == pt) continue;
-      const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
-      const double mhat = (double)s.m[p] / pr;
-      const uint64_t o = ob + j - (p > pt ? 1u : 0u);
-      write_point(a, t, s, p, o, d, (float)(scale * mhat));
+    __syncthreads();
+    uint32_t v = sh_v;
+    __syncthreads();
+    if (v == NONE) break;
+    while (true) {
+      __threadfence();
+      if (threadIdx.x == 0) {
+        const uint32_t fc = t.first_child[v];
+        if (fc != NONE) {
+          const int nk = __popc((uint32_t)t.child_mask[v]);
+          double M = 0.0;
+          for (int k = 0; k < nk; ++k) M += t.node_mass[fc + k];
+          t.node_mass[v] = M;
+        }
+      }
+      __syncthreads();
+      select_node(a, t, s, sa, v);
+      __syncthreads();
+      output_node(a, t, s, sa, v);
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t par = t.parent[v];
+        uint32_t nxt = NONE;
+        if (par != NONE && atomicSub(&t.pend[par], 1u) == 1u) nxt = par;
+        sh_v = nxt;
+      }
+      __syncthreads();
+      v = sh_v;
+      __syncthreads();
+      if (v == NONE) break;
     }
   }
 }
@@ -934,6 +1045,31 @@ __global__ __launch_bounds__(TB) void k_sel_output(BuildArgs a, TreeArgs t, Sort
 // host side
 
 namespace lodh {
+
+namespace {
+__global__ void k_copy32(const uint32_t *__restrict__ a, uint32_t *__restrict__ b, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+template <typename T>
+__global__ void k_fill(T *p, uint64_t n, T v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+}  // namespace
+
+void fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st) {
+  if (!n) return;
+  const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
+  LOD_LAUNCH(k_fill<uint64_t>, dim3(g), dim3(256), 0, st, p, n, v);
+}
+
+void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (!n) return;
+  const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
+  LOD_LAUNCH(k_fill<uint32_t>, dim3(g), dim3(256), 0, st, p, n, v);
+}
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -947,6 +1083,8 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   if (L.node_cap == 0) L.node_cap = 1;
   L.point_cap = N + (uint64_t)p.n * p.max_depth * per_level;
   if (L.point_cap == 0) L.point_cap = 1;
+  // selecting nodes of one level are disjoint and hold > n particles each
+  const uint64_t max_sel = (uint64_t)(p.max_depth + 1) * per_level + n_snap;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   L.keyA = take(4 * Np); L.keyB = take(4 * Np);
@@ -954,16 +1092,22 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.loA = take(8 * Np); L.loB = take(8 * Np);
   L.mA = take(4 * Np); L.mB = take(4 * Np);
   L.thist = take(4 * (size_t)RADIX * tiles);
-  L.scan32 = take(4 * scan_tmp_elems<uint32_t>((uint64_t)RADIX * tiles));
+  L.scan32 = take(4 * std::max(scan_tmp_elems<uint32_t>((uint64_t)RADIX * tiles),
+                               scan_tmp_elems<uint32_t>(L.node_cap + 1)));
   L.scan64 = take(8 * scan_tmp_elems<uint64_t>(L.node_cap));
   L.w = take(4 * Np);
-  L.K = take(8 * Np);
+  L.kb = take(2 * Np);
   L.lvl = take(4 * (size_t)(p.max_depth + 4));
+  L.lsel = take(4 * (size_t)(p.max_depth + 4));
   L.cs = take(4 * 9 * (size_t)L.node_cap);
   L.sel_idx = take(4 * (size_t)L.node_cap);
   L.wit = take(4 * (size_t)L.node_cap);
-  L.top0 = take(4 * Np);
-  L.top1 = take(4 * Np);
+  L.pend = take(4 * (size_t)L.node_cap);
+  L.bflag = take(4 * (size_t)(L.node_cap + 1));
+  L.bscan = take(4 * (size_t)(L.node_cap + 1));
+  L.bottom = take(4 * (size_t)L.node_cap);
+  L.ctl = take(64);
+  L.lists = take(4 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
   L.total = off;
   return L;
 }
@@ -1018,10 +1162,10 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
                        ks, is, ls, ms, kd, id, ld, md);
     std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(ms, md);
   }
-  Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint64_t *)(W + L.K)};
+  Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint16_t *)(W + L.kb)};
 
   LOD_LAUNCH(k_density, dim3((unsigned)tiles), dim3(TB), 0, st, a, ks, is,
-                     (uint32_t *)(W + L.w), (uint64_t *)(W + L.K));
+             (uint32_t *)(W + L.w), (uint16_t *)(W + L.kb));
 
   TreeArgs t{};
   t.prefix = out.prefix; t.depth = out.depth; t.parent = out.parent; t.first_child = out.first_child;
@@ -1029,7 +1173,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   t.pt_begin = out.pt_begin; t.pt_count = out.pt_count; t.node_mass = out.node_mass;
   t.pt_id = out.pt_id; t.qx = out.qx; t.qy = out.qy; t.qz = out.qz; t.pt_mass = out.pt_mass;
   t.lvl = lvl; t.cs = (uint32_t *)(W + L.cs); t.sel_idx = (uint32_t *)(W + L.sel_idx);
-  t.wit = (uint32_t *)(W + L.wit);
+  t.wit = (uint32_t *)(W + L.wit); t.pend = (uint32_t *)(W + L.pend); t.lsel = (uint32_t *)(W + L.lsel);
 
   const int D = (int)p.max_depth;
   LOD_LAUNCH(k_roots, dim3(1), dim3(1024), 0, st, a, t, ks);
@@ -1039,7 +1183,6 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
     LOD_LAUNCH(k_octants, dim3(oct_grid), dim3(TB), 0, st, a, t, ks, d);
     LOD_LAUNCH(k_emit, dim3(1), dim3(1024), 0, st, a, t, d);
   }
-  // level D has no children: its end was written by the last emit (or roots)
   const unsigned cap_grid = (unsigned)std::min<uint64_t>(4096, (L.node_cap + TB - 1) / TB);
   LOD_LAUNCH(k_ptcount, dim3(cap_grid), dim3(TB), 0, st, a, t, D);
   device_scan<uint64_t>(out.pt_begin, L.node_cap, (uint64_t *)(W + L.scan64), st);
@@ -1048,7 +1191,25 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
   LOD_LAUNCH(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
 
-  uint32_t *top[2] = {(uint32_t *)(W + L.top0), (uint32_t *)(W + L.top1)};
+  SelArgs sa{(uint32_t *)(W + L.lists), (uint32_t)(N - 1)};
+  const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
+  const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
+  if (p.mode == 2) {
+    uint32_t *bflag = (uint32_t *)(W + L.bflag), *bscan = (uint32_t *)(W + L.bscan);
+    uint32_t *ctl = (uint32_t *)(W + L.ctl);
+    const unsigned fg = (unsigned)std::min<uint64_t>(4096, (L.node_cap + 256) / 256);
+    LOD_LAUNCH(k_bottom_flags, dim3(fg), dim3(256), 0, st, a, t, bflag);
+    LOD_LAUNCH(k_copy32, dim3(fg), dim3(256), 0, st, bflag, bscan, L.node_cap + 1);
+    device_scan<uint32_t>(bscan, L.node_cap + 1, (uint32_t *)(W + L.scan32), st);
+    LOD_LAUNCH(k_bottom_write, dim3(fg), dim3(256), 0, st, a, bflag, bscan, (uint32_t *)(W + L.bottom), ctl);
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const unsigned pgrid = p.persistent_blocks ? p.persistent_blocks : (unsigned)(2 * cus);
+    LOD_LAUNCH(k_select_persistent, dim3(pgrid), dim3(sel_threads), 0, st, a, t, s, sa,
+               (const uint32_t *)(W + L.bottom), ctl);
+    return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+  }
   // the per-node reference schedule needs the level sizes on the host
   std::vector<uint32_t> hl;
   std::vector<uint64_t> hcount;
@@ -1063,45 +1224,21 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
          hipStreamSynchronize(st) != hipSuccess))
       return LOD_EDEVICE;
   }
-  const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
-  const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
   for (int d = D; d >= 0; --d) {
     if (d < D)
-      LOD_LAUNCH(k_internal_mass, dim3((unsigned)std::min<uint64_t>(1024, L.node_cap / TB + 1)),
-                         dim3(TB), 0, st, a, t, d);
-    SelArgs sa{top[(d + 1) & 1], top[d & 1], (uint32_t)(N - 1)};
+      LOD_LAUNCH(k_internal_mass, dim3((unsigned)std::min<uint64_t>(1024, L.node_cap / TB + 1)), dim3(TB), 0, st,
+                 a, t, d);
     if (p.mode == 0) {
-      // reference schedule: one launch per selecting node of this level
       for (uint32_t v = hl[d]; v < hl[d + 1]; ++v) {
         if (hcount[v] <= p.n) continue;
-        LOD_LAUNCH(k_select_one, dim3(1), dim3(sel_threads), 0, st, a, t, s, sa, d, v - hl[d]);
+        LOD_LAUNCH(k_select_one, dim3(1), dim3(sel_threads), 0, st, a, t, s, sa, v);
       }
     } else {
       LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
     }
-    LOD_LAUNCH(k_sel_output, dim3(sel_grid), dim3(TB), 0, st, a, t, s, sa, d);
+    LOD_LAUNCH(k_sel_output, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
   }
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
-}
-
-namespace {
-template <typename T>
-__global__ void k_fill(T *p, uint64_t n, T v) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-}  // namespace
-
-void fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st) {
-  if (!n) return;
-  const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
-  LOD_LAUNCH(k_fill<uint64_t>, dim3(g), dim3(256), 0, st, p, n, v);
-}
-
-void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
-  if (!n) return;
-  const unsigned g = (unsigned)std::min<uint64_t>(1024, (n + 255) / 256);
-  LOD_LAUNCH(k_fill<uint32_t>, dim3(g), dim3(256), 0, st, p, n, v);
 }
 
 void *workspace_view(void *ws, const BuildLayout &L, uint32_t which, uint64_t N, int passes, uint64_t *count) {
@@ -1111,7 +1248,7 @@ void *workspace_view(void *ws, const BuildLayout &L, uint32_t which, uint64_t N,
     case 0: *count = N; return W + (inB ? L.keyB : L.keyA);
     case 1: *count = N; return W + (inB ? L.idxB : L.idxA);
     case 2: *count = N; return W + L.w;
-    case 3: *count = N; return W + L.K;
+    case 3: *count = N; return W + L.kb;
     case 4: *count = L.node_cap; return W + L.wit;
     default: *count = 0; return nullptr;
   }

@@ -14,9 +14,9 @@ struct BuildLayout {
   uint64_t tiles, node_cap, point_cap;
   size_t keyA, keyB, idxA, idxB, loA, loB, mA, mB;
   size_t thist, scan32, scan64;
-  size_t w, K;
-  size_t lvl, cs, sel_idx, wit;
-  size_t top0, top1;
+  size_t w, kb;
+  size_t lvl, lsel, cs, sel_idx, wit, pend, bflag, bscan, bottom, ctl;
+  size_t lists;
   size_t total;
 };
 

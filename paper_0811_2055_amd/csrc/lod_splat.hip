@@ -223,7 +223,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
   __shared__ float acc[TS * TS];
   __shared__ float gxs[CHUNK][TS];
   __shared__ float gys[CHUNK][TS];
-  __shared__ int rng[CHUNK][4];
+  __shared__ float ub[PT], vb[PT], mb[PT];
   const uint32_t total_slices = slice_off[nt];
   const int lane_pt = threadIdx.x / PER_POINT;     // point within chunk
   const int sub = threadIdx.x % PER_POINT;         // helper index for that point
@@ -241,44 +241,52 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
     const int txe = min(tx0 + TS, (int)c.W) - 1, tye = min(ty0 + TS, (int)c.H) - 1;
     acc[threadIdx.x] = 0.0f;
     float s = 0.0f, cc = 0.0f;
-    __syncthreads();
-    for (uint64_t c0 = pb; c0 < pe; c0 += CHUNK) {
-      const uint64_t q = c0 + lane_pt;
-      int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
-      float w = 0.0f;
-      if (q < pe) {
-        const float u = bu[q], v = bv[q];
-        w = bm[q] * c.norm;
-        if (clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
-          for (int e = sub; e <= i1 - i0; e += PER_POINT) {
-            const float ox = u - ((float)(i0 + e) + 0.5f);
-            gxs[lane_pt][e] = expf(-(ox * ox) * c.inv2s2);
+    // batches of PT pairs staged in LDS; the next batch is prefetched into registers
+    float nu = 0.0f, nv = 0.0f, nm = 0.0f;
+    if (pb + threadIdx.x < pe) { nu = bu[pb + threadIdx.x]; nv = bv[pb + threadIdx.x]; nm = bm[pb + threadIdx.x]; }
+    for (uint64_t b0 = pb; b0 < pe; b0 += PT) {
+      __syncthreads();
+      ub[threadIdx.x] = nu; vb[threadIdx.x] = nv; mb[threadIdx.x] = nm;
+      const uint64_t nx = b0 + PT + threadIdx.x;
+      if (nx < pe) { nu = bu[nx]; nv = bv[nx]; nm = bm[nx]; }
+      const int bn = (int)min((uint64_t)PT, pe - b0);
+      __syncthreads();
+      for (int c0 = 0; c0 < bn; c0 += CHUNK) {
+        const int q = c0 + lane_pt;
+        int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
+        if (q < bn) {
+          const float u = ub[q], v = vb[q];
+          const float w = mb[q] * c.norm;
+          if (clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
+            for (int e = sub; e <= i1 - i0; e += PER_POINT) {
+              const float ox = u - ((float)(i0 + e) + 0.5f);
+              gxs[lane_pt][e] = expf(-(ox * ox) * c.inv2s2);
+            }
+            for (int e = sub; e <= j1 - j0; e += PER_POINT) {
+              const float oy = v - ((float)(j0 + e) + 0.5f);
+              gys[lane_pt][e] = w * expf(-(oy * oy) * c.inv2s2);
+            }
+          } else {
+            i1 = -1; j1 = -1;
           }
-          for (int e = sub; e <= j1 - j0; e += PER_POINT) {
-            const float oy = v - ((float)(j0 + e) + 0.5f);
-            gys[lane_pt][e] = w * expf(-(oy * oy) * c.inv2s2);
-          }
-        } else {
-          i1 = -1; j1 = -1;
         }
+        __syncthreads();
+        for (int j = j0 + sub; j <= j1; j += PER_POINT) {
+          const float gy = gys[lane_pt][j - j0];
+          float *row = acc + (j - ty0) * TS - tx0;
+          const float *gx = gxs[lane_pt] - i0;
+          for (int i = i0; i <= i1; ++i) atomicAdd(&row[i], gy * gx[i]);
+        }
+        __syncthreads();
+        const float vsum = acc[threadIdx.x];
+        acc[threadIdx.x] = 0.0f;
+        neumaier(s, cc, vsum);
       }
-      __syncthreads();
-      for (int j = j0 + sub; j <= j1; j += PER_POINT) {
-        const float gy = gys[lane_pt][j - j0];
-        float *row = acc + (j - ty0) * TS - tx0;
-        const float *gx = gxs[lane_pt] - i0;
-        for (int i = i0; i <= i1; ++i) atomicAdd(&row[i], gy * gx[i]);
-      }
-      __syncthreads();
-      const float vsum = acc[threadIdx.x];
-      acc[threadIdx.x] = 0.0f;
-      neumaier(s, cc, vsum);
-      __syncthreads();
     }
+    __syncthreads();
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
     __syncthreads();
   }
-  (void)rng;
 }
 
 // Sum each tile's slice partials in slice order and write the image.

@@ -35,7 +35,7 @@ class LodError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("n", C.c_uint32), ("max_depth", C.c_uint32), ("density_level", C.c_uint32),
                 ("alpha", C.c_int32), ("seed", C.c_uint64), ("mode", C.c_uint32),
-                ("select_threads", C.c_uint32)]
+                ("select_threads", C.c_uint32), ("persistent_blocks", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Input(C.Structure):
@@ -134,13 +134,14 @@ class BuildParams:
     density_level: int | None = None
     alpha: int = 1
     seed: int = 0
-    mode: int = 1
+    mode: int = 2
     select_threads: int = 0
+    persistent_blocks: int = 0
 
     def c(self) -> Params:
         L = self.max_depth if self.density_level is None else self.density_level
         return Params(self.n, self.max_depth, L, self.alpha, self.seed & ((1 << 64) - 1), self.mode,
-                      self.select_threads)
+                      self.select_threads, self.persistent_blocks, 0)
 
 
 @dataclass
@@ -303,7 +304,7 @@ class Builder:
         return self.tree
 
     def view(self, which: int, dtype):
-        """Intermediate arrays (0 keys, 1 ids, 2 w, 3 K, 4 witness) as a torch view."""
+        """Intermediate arrays (0 keys, 1 ids, 2 w, 3 key bins, 4 witness) as a torch view."""
         import torch
         lib = load()
         ptr, cnt = C.c_void_p(), C.c_uint64()
