@@ -102,6 +102,10 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--count", type=int, default=None, help="override the particle count (c3)")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--mode", type=int, default=2, choices=[0, 1, 2],
+                    help="selection schedule: 0 per-node launches, 1 per-level launches, 2 one persistent launch")
+    ap.add_argument("--compare-modes", action="store_true",
+                    help="also time one build in each selection schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-render", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -124,7 +128,7 @@ def main():
     log(f"[bench] workload generated: {snap.n} particles in {time.perf_counter() - t0:.1f} s")
     x, y, z, m = (torch.from_numpy(a).to(dev) for a in (snap.x, snap.y, snap.z, snap.m))
     N = snap.n
-    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=1)
+    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=args.mode)
     builder = lib.Builder(N, params, dev)
     cam = lib.Camera.ortho(cfg["W"], cfg["H"])
     tree = builder.tree
@@ -228,6 +232,25 @@ def main():
         torch.cuda.synchronize()
         extra.update({k: float(f"{v:.4g}") for k, v in image_errors(lod_img, full).items()})
         del full_ws
+
+    if args.compare_modes:
+        by_mode = {}
+        for md in (0, 1, 2):
+            bm = lib.Builder(N, lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=md), dev)
+            bm.build(x, y, z, m)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bm.build(x, y, z, m)
+            torch.cuda.synchronize()
+            by_mode[str(md)] = round((time.perf_counter() - t0) * 1e3, 3)
+            hm = bm.tree.host()
+            for key in ("pt_id", "qx", "qy", "qz", "pt_mass", "prefix", "part_count"):
+                if not np.array_equal(hm[key], h[key]):
+                    raise SystemExit(f"schedule {md} differs from the timed schedule in {key}")
+            del bm
+            torch.cuda.empty_cache()
+        extra["build_ms_by_schedule"] = by_mode
+        log(f"[bench] build ms by schedule: {by_mode}")
 
     splat_ms = sum(t for k, (c, t) in per_step.items() if k not in build_kernels)
     out = {

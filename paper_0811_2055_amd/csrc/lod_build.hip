@@ -765,6 +765,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __shared__ uint64_t sh_kt;
   __shared__ uint32_t sh_it, sh_pt;
   __shared__ uint32_t sh_b, sh_below, sh_cnt;
+  __shared__ uint32_t stage[ILP * 1024];
   const uint32_t n = a.n;
   const int BS = blockDim.x;
   if (threadIdx.x == 0) build_segments(a, t, v, g);
@@ -881,29 +882,50 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   }
   const uint64_t Kt = sh_kt;
   const uint32_t It = sh_it;
-  // order-preserving compaction of (K, id) <= (Kt, It)
+  // order-preserving compaction of (K, id) <= (Kt, It), BS*ILP candidates at
+  // a time: striped loads into LDS, then one blocked scan
   uint32_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
   uint32_t written = 0;
   for (int k = 0; k < (int)g.nseg; ++k) {
     const uint32_t L = g.len[k];
     const bool lst = g.is_list[k];
     const uint64_t base = g.base[k];
-    for (uint32_t j0 = 0; j0 < L; j0 += BS) {
-      const uint32_t j = j0 + threadIdx.x;
-      uint32_t f = 0, p = 0;
-      if (j < L) {
-        p = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
-        const uint32_t kb = s.kb[p];
-        if (kb < b0) f = 1;
-        else if (kb == b0) {
-          const uint64_t K = exact_K(a, s, p);
-          f = (K < Kt || (K == Kt && s.idx[p] <= It)) ? 1u : 0u;
-        }
+    for (uint32_t j0 = 0; j0 < L; j0 += BS * ILP) {
+      uint32_t p[ILP];
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) {
+        const uint32_t j = j0 + u * BS + threadIdx.x;
+        p[u] = NONE;
+        if (j < L) p[u] = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
       }
+      uint32_t kb[ILP];
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) kb[u] = p[u] != NONE ? s.kb[p[u]] : 0u;
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) {
+        uint32_t keep = NONE;
+        if (p[u] != NONE) {
+          if (kb[u] < b0) keep = p[u];
+          else if (kb[u] == b0) {
+            const uint64_t K = exact_K(a, s, p[u]);
+            if (K < Kt || (K == Kt && s.idx[p[u]] <= It)) keep = p[u];
+          }
+        }
+        stage[u * BS + threadIdx.x] = keep;
+      }
+      __syncthreads();
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int i = 0; i < ILP; ++i) cnt += stage[threadIdx.x * ILP + i] != NONE ? 1u : 0u;
       uint32_t tot;
-      const uint32_t o = block_excl_scan<uint32_t>(f, red32, tot);
-      if (f && written + o <= n) out[written + o] = p;
+      uint32_t o = written + block_excl_scan<uint32_t>(cnt, red32, tot);
+#pragma unroll
+      for (int i = 0; i < ILP; ++i) {
+        const uint32_t q = stage[threadIdx.x * ILP + i];
+        if (q != NONE) { if (o <= n) out[o] = q; ++o; }
+      }
       written += tot;
+      __syncthreads();
     }
   }
   if (threadIdx.x == 0) {
@@ -927,23 +949,43 @@ __device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
   const double tau = weight_pow(s.w[pt], alpha) * 4294967296.0 / (double)Ut;
   double acc = 0.0;
-  for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) {
-    const uint32_t p = min(list[j], sa.n_minus_1);
-    if (p == pt) continue;
-    const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
-    acc += (double)s.m[p] / pr;
+  for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += blockDim.x * ILP) {
+    uint32_t p[ILP], w[ILP];
+    float mm[ILP];
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const uint32_t j = j0 + u * blockDim.x;
+      p[u] = j <= n ? min(list[j], sa.n_minus_1) : NONE;
+    }
+#pragma unroll
+    for (int u = 0; u < ILP; ++u)
+      if (p[u] != NONE) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; }
+#pragma unroll
+    for (int u = 0; u < ILP; ++u)
+      if (p[u] != NONE && p[u] != pt) acc += (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
   }
   const double tot = block_reduce_sum<double>(acc, red);
   const double scale = t.node_mass[v] / tot;
   const uint64_t ob = t.pt_begin[v];
   const int d = t.depth[v];
-  for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) {
-    const uint32_t p = min(list[j], sa.n_minus_1);
-    if (p == pt) continue;
-    const double pr = fmin(1.0, weight_pow(s.w[p], alpha) / tau);
-    const double mhat = (double)s.m[p] / pr;
-    const uint64_t o = ob + j - (p > pt ? 1u : 0u);
-    write_point(a, t, s, p, o, d, (float)(scale * mhat));
+  for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += blockDim.x * ILP) {
+    uint32_t p[ILP], w[ILP];
+    float mm[ILP];
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const uint32_t j = j0 + u * blockDim.x;
+      p[u] = j <= n ? min(list[j], sa.n_minus_1) : NONE;
+    }
+#pragma unroll
+    for (int u = 0; u < ILP; ++u)
+      if (p[u] != NONE) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; }
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      if (p[u] == NONE || p[u] == pt) continue;
+      const double mhat = (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
+      const uint32_t j = j0 + u * blockDim.x;
+      write_point(a, t, s, p[u], ob + j - (p[u] > pt ? 1u : 0u), d, (float)(scale * mhat));
+    }
   }
 }
 

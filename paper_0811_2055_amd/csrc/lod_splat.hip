@@ -224,6 +224,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
   __shared__ float gxs[CHUNK][TS];
   __shared__ float gys[CHUNK][TS];
   __shared__ float ub[PT], vb[PT], mb[PT];
+  __shared__ int rng[CHUNK][4];
   const uint32_t total_slices = slice_off[nt];
   const int lane_pt = threadIdx.x / PER_POINT;     // point within chunk
   const int sub = threadIdx.x % PER_POINT;         // helper index for that point
@@ -252,12 +253,14 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
       const int bn = (int)min((uint64_t)PT, pe - b0);
       __syncthreads();
       for (int c0 = 0; c0 < bn; c0 += CHUNK) {
+        // phase A: 8 threads per point find its pixel range in the tile and its
+        // separable weights
         const int q = c0 + lane_pt;
-        int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
         if (q < bn) {
+          int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
           const float u = ub[q], v = vb[q];
-          const float w = mb[q] * c.norm;
           if (clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
+            const float w = mb[q] * c.norm;
             for (int e = sub; e <= i1 - i0; e += PER_POINT) {
               const float ox = u - ((float)(i0 + e) + 0.5f);
               gxs[lane_pt][e] = expf(-(ox * ox) * c.inv2s2);
@@ -267,15 +270,26 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
               gys[lane_pt][e] = w * expf(-(oy * oy) * c.inv2s2);
             }
           } else {
-            i1 = -1; j1 = -1;
+            i1 = i0 - 1;
           }
+          if (sub == 0) { rng[lane_pt][0] = i0 - tx0; rng[lane_pt][1] = i1 - i0 + 1;
+                          rng[lane_pt][2] = j0 - ty0; rng[lane_pt][3] = j1 - j0 + 1; }
+        } else if (sub == 0) {
+          rng[lane_pt][1] = 0; rng[lane_pt][3] = 0;
         }
         __syncthreads();
-        for (int j = j0 + sub; j <= j1; j += PER_POINT) {
-          const float gy = gys[lane_pt][j - j0];
-          float *row = acc + (j - ty0) * TS - tx0;
-          const float *gx = gxs[lane_pt] - i0;
-          for (int i = i0; i <= i1; ++i) atomicAdd(&row[i], gy * gx[i]);
+        // phase B: each wave takes points in turn; its 64 lanes cover an 8x8
+        // pixel block of one footprint, so one LDS add never hits an address twice
+        const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+        const int dx = ln & 7, dy = ln >> 3;
+        for (int k = wv; k < CHUNK; k += PT / WAVE) {
+          const int ox0 = rng[k][0], nx = rng[k][1], oy0 = rng[k][2], ny = rng[k][3];
+          for (int by = 0; by < ny; by += 8)
+            for (int bx = 0; bx < nx; bx += 8) {
+              const int ex = bx + dx, ey = by + dy;
+              if (ex < nx && ey < ny)
+                atomicAdd(&acc[(oy0 + ey) * TS + ox0 + ex], gys[k][ey] * gxs[k][ex]);
+            }
         }
         __syncthreads();
         const float vsum = acc[threadIdx.x];
