@@ -686,7 +686,8 @@ __global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, i
 
 constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
-constexpr int ILP = 4;
+constexpr int ILP = 8;        // loads in flight per thread in the candidate passes
+constexpr int CILP = 8;       // candidates per thread per compaction step
 
 struct SelArgs {
   uint32_t *lists;            // top-(n+1) position lists by selecting rank
@@ -721,7 +722,7 @@ __device__ __forceinline__ void for_candidates(const Segs &g, const SelArgs &sa,
       }
 #pragma unroll
       for (int u = 0; u < ILP; ++u) kb[u] = (p[u] != NONE) ? s.kb[p[u]] : 0u;
-#pragma unroll
+#pragma unroll 1
       for (int u = 0; u < ILP; ++u)
         if (p[u] != NONE) f(p[u], kb[u]);
     }
@@ -765,7 +766,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __shared__ uint64_t sh_kt;
   __shared__ uint32_t sh_it, sh_pt;
   __shared__ uint32_t sh_b, sh_below, sh_cnt;
-  __shared__ uint32_t stage[ILP * 1024];
+  __shared__ uint32_t stage[CILP * 1024];
   const uint32_t n = a.n;
   const int BS = blockDim.x;
   if (threadIdx.x == 0) build_segments(a, t, v, g);
@@ -890,19 +891,19 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     const uint32_t L = g.len[k];
     const bool lst = g.is_list[k];
     const uint64_t base = g.base[k];
-    for (uint32_t j0 = 0; j0 < L; j0 += BS * ILP) {
-      uint32_t p[ILP];
+    for (uint32_t j0 = 0; j0 < L; j0 += BS * CILP) {
+      uint32_t p[CILP];
 #pragma unroll
-      for (int u = 0; u < ILP; ++u) {
+      for (int u = 0; u < CILP; ++u) {
         const uint32_t j = j0 + u * BS + threadIdx.x;
         p[u] = NONE;
         if (j < L) p[u] = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
       }
-      uint32_t kb[ILP];
+      uint32_t kb[CILP];
 #pragma unroll
-      for (int u = 0; u < ILP; ++u) kb[u] = p[u] != NONE ? s.kb[p[u]] : 0u;
+      for (int u = 0; u < CILP; ++u) kb[u] = p[u] != NONE ? s.kb[p[u]] : 0u;
 #pragma unroll
-      for (int u = 0; u < ILP; ++u) {
+      for (int u = 0; u < CILP; ++u) {
         uint32_t keep = NONE;
         if (p[u] != NONE) {
           if (kb[u] < b0) keep = p[u];
@@ -916,12 +917,12 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
       __syncthreads();
       uint32_t cnt = 0;
 #pragma unroll
-      for (int i = 0; i < ILP; ++i) cnt += stage[threadIdx.x * ILP + i] != NONE ? 1u : 0u;
+      for (int i = 0; i < CILP; ++i) cnt += stage[threadIdx.x * CILP + i] != NONE ? 1u : 0u;
       uint32_t tot;
       uint32_t o = written + block_excl_scan<uint32_t>(cnt, red32, tot);
 #pragma unroll
-      for (int i = 0; i < ILP; ++i) {
-        const uint32_t q = stage[threadIdx.x * ILP + i];
+      for (int i = 0; i < CILP; ++i) {
+        const uint32_t q = stage[threadIdx.x * CILP + i];
         if (q != NONE) { if (o <= n) out[o] = q; ++o; }
       }
       written += tot;

@@ -209,10 +209,12 @@ __device__ __forceinline__ bool clip_range(float t, float R, int lo_clip, int hi
   return lo <= hi;
 }
 
-// One block per slice; thread t owns pixel (t % 16, t / 16) of the tile.
-// Per chunk of 32 points, 8 threads serve one point: they find its pixel
-// range inside the tile, write its separable weights (at most 16 per axis)
-// to LDS, then add the rows sub, sub+8 of its footprint into the LDS tile.
+// One block per slice; thread t owns pixel (t % 16, t / 16) of the tile and
+// keeps its compensated (Neumaier) float32 sum in registers.  Per chunk of 256
+// points each thread splats one point: it finds the point's pixel range in
+// the tile, caches the column weights in LDS and adds weight products into its
+// wave's private LDS tile with ds_add_f32.  A pixel of a wave tile thus takes
+// at most 64 uncompensated adds before it is folded into the register sums.
 __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ tile_off,
                                                    const uint32_t *__restrict__ tile_count,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
@@ -220,86 +222,63 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
                                                    const float *__restrict__ bm, Cam c,
                                                    float *__restrict__ partial, uint64_t max_slices,
                                                    uint64_t max_pairs) {
-  __shared__ float acc[TS * TS];
-  __shared__ float gxs[CHUNK][TS];
-  __shared__ float gys[CHUNK][TS];
-  __shared__ float ub[PT], vb[PT], mb[PT];
-  __shared__ int rng[CHUNK][4];
+  constexpr int NW = PT / WAVE;
+  __shared__ float acc[NW][TS * TS];
+  __shared__ float gxs[TS][PT];
+  __shared__ uint32_t sh_t;
   const uint32_t total_slices = slice_off[nt];
-  const int lane_pt = threadIdx.x / PER_POINT;     // point within chunk
-  const int sub = threadIdx.x % PER_POINT;         // helper index for that point
+  const int wv = threadIdx.x / WAVE;
   for (uint32_t sl = blockIdx.x; sl < total_slices && sl < max_slices; sl += gridDim.x) {
-    uint32_t lo = 0, hi = nt;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (slice_off[mid] <= sl) lo = mid; else hi = mid;
+    if (threadIdx.x == 0) {
+      uint32_t lo = 0, hi = nt;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (slice_off[mid] <= sl) lo = mid; else hi = mid;
+      }
+      sh_t = lo;
     }
-    const uint32_t t = lo;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) acc[w][threadIdx.x] = 0.0f;
+    __syncthreads();
+    const uint32_t t = sh_t;
     const uint32_t k = sl - slice_off[t];
     const uint64_t pb = (uint64_t)tile_off[t] + (uint64_t)k * lodh::SPLAT_SLICE;
     const uint64_t pe = min(min((uint64_t)tile_off[t] + tile_count[t], pb + lodh::SPLAT_SLICE), max_pairs);
     const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
     const int txe = min(tx0 + TS, (int)c.W) - 1, tye = min(ty0 + TS, (int)c.H) - 1;
-    acc[threadIdx.x] = 0.0f;
     float s = 0.0f, cc = 0.0f;
-    // batches of PT pairs staged in LDS; the next batch is prefetched into registers
     float nu = 0.0f, nv = 0.0f, nm = 0.0f;
     if (pb + threadIdx.x < pe) { nu = bu[pb + threadIdx.x]; nv = bv[pb + threadIdx.x]; nm = bm[pb + threadIdx.x]; }
-    for (uint64_t b0 = pb; b0 < pe; b0 += PT) {
-      __syncthreads();
-      ub[threadIdx.x] = nu; vb[threadIdx.x] = nv; mb[threadIdx.x] = nm;
-      const uint64_t nx = b0 + PT + threadIdx.x;
-      if (nx < pe) { nu = bu[nx]; nv = bv[nx]; nm = bm[nx]; }
-      const int bn = (int)min((uint64_t)PT, pe - b0);
-      __syncthreads();
-      for (int c0 = 0; c0 < bn; c0 += CHUNK) {
-        // phase A: 8 threads per point find its pixel range in the tile and its
-        // separable weights
-        const int q = c0 + lane_pt;
-        if (q < bn) {
-          int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
-          const float u = ub[q], v = vb[q];
-          if (clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
-            const float w = mb[q] * c.norm;
-            for (int e = sub; e <= i1 - i0; e += PER_POINT) {
-              const float ox = u - ((float)(i0 + e) + 0.5f);
-              gxs[lane_pt][e] = expf(-(ox * ox) * c.inv2s2);
-            }
-            for (int e = sub; e <= j1 - j0; e += PER_POINT) {
-              const float oy = v - ((float)(j0 + e) + 0.5f);
-              gys[lane_pt][e] = w * expf(-(oy * oy) * c.inv2s2);
-            }
-          } else {
-            i1 = i0 - 1;
-          }
-          if (sub == 0) { rng[lane_pt][0] = i0 - tx0; rng[lane_pt][1] = i1 - i0 + 1;
-                          rng[lane_pt][2] = j0 - ty0; rng[lane_pt][3] = j1 - j0 + 1; }
-        } else if (sub == 0) {
-          rng[lane_pt][1] = 0; rng[lane_pt][3] = 0;
+    for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
+      const float u = nu, v = nv, m = nm;
+      const bool have = c0 + threadIdx.x < pe;
+      const uint64_t nx_q = c0 + PT + threadIdx.x;
+      if (nx_q < pe) { nu = bu[nx_q]; nv = bv[nx_q]; nm = bm[nx_q]; }
+      int i0, i1, j0, j1;
+      if (have && clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
+        const int nx = i1 - i0 + 1;
+        for (int e = 0; e < nx; ++e) {
+          const float ox = u - ((float)(i0 + e) + 0.5f);
+          gxs[e][threadIdx.x] = expf(-(ox * ox) * c.inv2s2);
         }
-        __syncthreads();
-        // phase B: each wave takes points in turn; its 64 lanes cover an 8x8
-        // pixel block of one footprint, so one LDS add never hits an address twice
-        const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
-        const int dx = ln & 7, dy = ln >> 3;
-        for (int k = wv; k < CHUNK; k += PT / WAVE) {
-          const int ox0 = rng[k][0], nx = rng[k][1], oy0 = rng[k][2], ny = rng[k][3];
-          for (int by = 0; by < ny; by += 8)
-            for (int bx = 0; bx < nx; bx += 8) {
-              const int ex = bx + dx, ey = by + dy;
-              if (ex < nx && ey < ny)
-                atomicAdd(&acc[(oy0 + ey) * TS + ox0 + ex], gys[k][ey] * gxs[k][ex]);
-            }
+        const float w = m * c.norm;
+        float *row = &acc[wv][(j0 - ty0) * TS + (i0 - tx0)];
+        for (int j = j0; j <= j1; ++j, row += TS) {
+          const float oy = v - ((float)j + 0.5f);
+          const float gy = w * expf(-(oy * oy) * c.inv2s2);
+          for (int e = 0; e < nx; ++e) atomicAdd(&row[e], gy * gxs[e][threadIdx.x]);
         }
-        __syncthreads();
-        const float vsum = acc[threadIdx.x];
-        acc[threadIdx.x] = 0.0f;
-        neumaier(s, cc, vsum);
       }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const float val = acc[w][threadIdx.x];
+        acc[w][threadIdx.x] = 0.0f;
+        neumaier(s, cc, val);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
-    __syncthreads();
   }
 }
 
