@@ -686,13 +686,20 @@ __global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, i
 
 constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
-constexpr int ILP = 8;        // loads in flight per thread in the candidate passes
-constexpr int CILP = 8;       // candidates per thread per compaction step
+constexpr int ILP = 8;        // list entries in flight per thread in the candidate passes
+constexpr int RILP = 16;      // key bins in flight per thread on contiguous ranges
+constexpr int CILP = 4;       // candidates per thread per compaction step
 
+// A list entry packs a sorted position (low 32 bits) and its key bin (next 16).
 struct SelArgs {
-  uint32_t *lists;            // top-(n+1) position lists by selecting rank
+  uint64_t *lists;            // top-(n+1) lists by selecting rank
   uint32_t n_minus_1;         // N - 1
 };
+
+__device__ __forceinline__ uint32_t entry_pos(uint64_t e, uint32_t n_minus_1) {
+  return min((uint32_t)e, n_minus_1);
+}
+__device__ __forceinline__ uint32_t entry_kb(uint64_t e) { return (uint32_t)(e >> 32) & 0xFFFFu; }
 
 struct Segs {
   uint32_t nseg;
@@ -701,30 +708,43 @@ struct Segs {
   uint32_t is_list[9];
 };
 
-// Calls f(p, kbin) for every candidate, ILP loads in flight per thread.  List
-// entries are clamped below N so that a list left unwritten by a failed child
-// cannot send a read out of bounds (the failure is reported in the status).
+// Calls f(p, kbin) for every candidate.  List entries carry their key bin, so
+// a list segment is one coalesced stream; a range segment streams the
+// contiguous key-bin array.  Positions from lists are clamped below N so that a
+// list left unwritten by a failed child cannot send a read out of bounds (the
+// failure itself is reported in the status word).
 template <typename F>
 __device__ __forceinline__ void for_candidates(const Segs &g, const SelArgs &sa, const Sorted &s, F f) {
   const uint32_t BS = blockDim.x;
   for (int k = 0; k < (int)g.nseg; ++k) {
     const uint32_t L = g.len[k];
-    const bool lst = g.is_list[k];
     const uint64_t base = g.base[k];
-    for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * ILP) {
-      uint32_t p[ILP];
-      uint32_t kb[ILP];
+    if (g.is_list[k]) {
+      const uint64_t *lp = sa.lists + base;
+      for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * ILP) {
+        uint64_t e[ILP];
 #pragma unroll
-      for (int u = 0; u < ILP; ++u) {
-        const uint32_t j = j0 + u * BS;
-        p[u] = NONE;
-        if (j < L) p[u] = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
-      }
-#pragma unroll
-      for (int u = 0; u < ILP; ++u) kb[u] = (p[u] != NONE) ? s.kb[p[u]] : 0u;
+        for (int u = 0; u < ILP; ++u) {
+          const uint32_t j = j0 + u * BS;
+          e[u] = j < L ? lp[j] : ~0ull;
+        }
 #pragma unroll 1
-      for (int u = 0; u < ILP; ++u)
-        if (p[u] != NONE) f(p[u], kb[u]);
+        for (int u = 0; u < ILP; ++u)
+          if (e[u] != ~0ull) f(entry_pos(e[u], sa.n_minus_1), entry_kb(e[u]));
+      }
+    } else {
+      const uint16_t *kp = s.kb + base;
+      for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * RILP) {
+        uint32_t kb[RILP];
+#pragma unroll
+        for (int u = 0; u < RILP; ++u) {
+          const uint32_t j = j0 + u * BS;
+          kb[u] = j < L ? kp[j] : 0xFFFFFFFFu;
+        }
+#pragma unroll 1
+        for (int u = 0; u < RILP; ++u)
+          if (kb[u] != 0xFFFFFFFFu) f((uint32_t)(base + j0 + u * BS), kb[u]);
+      }
     }
   }
 }
@@ -766,7 +786,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __shared__ uint64_t sh_kt;
   __shared__ uint32_t sh_it, sh_pt;
   __shared__ uint32_t sh_b, sh_below, sh_cnt;
-  __shared__ uint32_t stage[CILP * 1024];
+  __shared__ uint64_t stage[CILP * 1024];
   const uint32_t n = a.n;
   const int BS = blockDim.x;
   if (threadIdx.x == 0) build_segments(a, t, v, g);
@@ -883,47 +903,48 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   }
   const uint64_t Kt = sh_kt;
   const uint32_t It = sh_it;
-  // order-preserving compaction of (K, id) <= (Kt, It), BS*ILP candidates at
+  // order-preserving compaction of (K, id) <= (Kt, It), BS*CILP candidates at
   // a time: striped loads into LDS, then one blocked scan
-  uint32_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
+  uint64_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
   uint32_t written = 0;
   for (int k = 0; k < (int)g.nseg; ++k) {
     const uint32_t L = g.len[k];
     const bool lst = g.is_list[k];
     const uint64_t base = g.base[k];
     for (uint32_t j0 = 0; j0 < L; j0 += BS * CILP) {
-      uint32_t p[CILP];
+      uint32_t p[CILP], kb[CILP];
 #pragma unroll
       for (int u = 0; u < CILP; ++u) {
         const uint32_t j = j0 + u * BS + threadIdx.x;
-        p[u] = NONE;
-        if (j < L) p[u] = lst ? min(sa.lists[base + j], sa.n_minus_1) : (uint32_t)(base + j);
+        p[u] = NONE; kb[u] = 0;
+        if (j < L) {
+          if (lst) { const uint64_t e = sa.lists[base + j]; p[u] = entry_pos(e, sa.n_minus_1); kb[u] = entry_kb(e); }
+          else { p[u] = (uint32_t)(base + j); kb[u] = s.kb[base + j]; }
+        }
       }
-      uint32_t kb[CILP];
-#pragma unroll
-      for (int u = 0; u < CILP; ++u) kb[u] = p[u] != NONE ? s.kb[p[u]] : 0u;
-#pragma unroll
+#pragma unroll 1
       for (int u = 0; u < CILP; ++u) {
-        uint32_t keep = NONE;
+        uint64_t keep = ~0ull;
         if (p[u] != NONE) {
-          if (kb[u] < b0) keep = p[u];
-          else if (kb[u] == b0) {
+          bool take = kb[u] < b0;
+          if (kb[u] == b0) {
             const uint64_t K = exact_K(a, s, p[u]);
-            if (K < Kt || (K == Kt && s.idx[p[u]] <= It)) keep = p[u];
+            take = K < Kt || (K == Kt && s.idx[p[u]] <= It);
           }
+          if (take) keep = (uint64_t)p[u] | ((uint64_t)kb[u] << 32);
         }
         stage[u * BS + threadIdx.x] = keep;
       }
       __syncthreads();
       uint32_t cnt = 0;
 #pragma unroll
-      for (int i = 0; i < CILP; ++i) cnt += stage[threadIdx.x * CILP + i] != NONE ? 1u : 0u;
+      for (int i = 0; i < CILP; ++i) cnt += stage[threadIdx.x * CILP + i] != ~0ull ? 1u : 0u;
       uint32_t tot;
       uint32_t o = written + block_excl_scan<uint32_t>(cnt, red32, tot);
 #pragma unroll
       for (int i = 0; i < CILP; ++i) {
-        const uint32_t q = stage[threadIdx.x * CILP + i];
-        if (q != NONE) { if (o <= n) out[o] = q; ++o; }
+        const uint64_t q = stage[threadIdx.x * CILP + i];
+        if (q != ~0ull) { if (o <= n) out[o] = q; ++o; }
       }
       written += tot;
       __syncthreads();
@@ -944,7 +965,7 @@ __device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const int alpha = a.alpha;
   const uint32_t pt = t.wit[v];
   if (pt == NONE || a.counts[1] > a.point_cap) return;
-  const uint32_t *list = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
+  const uint64_t *list = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
   const uint32_t kt = s.key[pt];
   const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
   const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
@@ -956,7 +977,7 @@ __device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
       const uint32_t j = j0 + u * blockDim.x;
-      p[u] = j <= n ? min(list[j], sa.n_minus_1) : NONE;
+      p[u] = j <= n ? entry_pos(list[j], sa.n_minus_1) : NONE;
     }
 #pragma unroll
     for (int u = 0; u < ILP; ++u)
@@ -975,7 +996,7 @@ __device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
       const uint32_t j = j0 + u * blockDim.x;
-      p[u] = j <= n ? min(list[j], sa.n_minus_1) : NONE;
+      p[u] = j <= n ? entry_pos(list[j], sa.n_minus_1) : NONE;
     }
 #pragma unroll
     for (int u = 0; u < ILP; ++u)
@@ -1150,7 +1171,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.bscan = take(4 * (size_t)(L.node_cap + 1));
   L.bottom = take(4 * (size_t)L.node_cap);
   L.ctl = take(64);
-  L.lists = take(4 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
+  L.lists = take(8 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
   L.total = off;
   return L;
 }
@@ -1234,7 +1255,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
   LOD_LAUNCH(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
 
-  SelArgs sa{(uint32_t *)(W + L.lists), (uint32_t)(N - 1)};
+  SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1)};
   const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
   const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
   if (p.mode == 2) {

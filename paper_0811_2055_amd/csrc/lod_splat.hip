@@ -209,12 +209,15 @@ __device__ __forceinline__ bool clip_range(float t, float R, int lo_clip, int hi
   return lo <= hi;
 }
 
-// One block per slice; thread t owns pixel (t % 16, t / 16) of the tile and
-// keeps its compensated (Neumaier) float32 sum in registers.  Per chunk of 256
-// points each thread splats one point: it finds the point's pixel range in
-// the tile, caches the column weights in LDS and adds weight products into its
-// wave's private LDS tile with ds_add_f32.  A pixel of a wave tile thus takes
-// at most 64 uncompensated adds before it is folded into the register sums.
+// One block per slice.  The blob is separable, so a chunk of 256 points adds
+// Gy^T Gx to the 16x16 tile, with Gx[k][i] = exp(-ox^2/2s^2) and Gy[k][j] =
+// m norm exp(-oy^2/2s^2) inside point k's truncation square and 0 outside.
+// Phase A: thread k fills row k of Gx and Gy in LDS.  Phase B: thread group g
+// (64 threads) sums points 64g..64g+63 for 4 pixels of one column each, with
+// fused multiply-adds in a fixed order -- no atomics, so the image is
+// bit-reproducible.  The four group partials of a pixel (at most 64 terms
+// each) are then folded into the pixel's compensated (Neumaier) float32 sum.
+constexpr int GXS = TS + 1;          // padded row: conflict-free phase-A writes
 __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ tile_off,
                                                    const uint32_t *__restrict__ tile_count,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
@@ -222,12 +225,14 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
                                                    const float *__restrict__ bm, Cam c,
                                                    float *__restrict__ partial, uint64_t max_slices,
                                                    uint64_t max_pairs) {
-  constexpr int NW = PT / WAVE;
-  __shared__ float acc[NW][TS * TS];
-  __shared__ float gxs[TS][PT];
+  __shared__ float gx[PT][GXS];
+  __shared__ float gy[PT][GXS];
+  __shared__ float part[4][TS * TS];
   __shared__ uint32_t sh_t;
   const uint32_t total_slices = slice_off[nt];
-  const int wv = threadIdx.x / WAVE;
+  const int grp = threadIdx.x / 64;                 // point group of phase B
+  const int col = threadIdx.x % TS;                 // pixel column of phase B
+  const int row0 = ((threadIdx.x % 64) / TS) * 4;   // first of 4 pixel rows of phase B
   for (uint32_t sl = blockIdx.x; sl < total_slices && sl < max_slices; sl += gridDim.x) {
     if (threadIdx.x == 0) {
       uint32_t lo = 0, hi = nt;
@@ -237,8 +242,6 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
       }
       sh_t = lo;
     }
-#pragma unroll
-    for (int w = 0; w < NW; ++w) acc[w][threadIdx.x] = 0.0f;
     __syncthreads();
     const uint32_t t = sh_t;
     const uint32_t k = sl - slice_off[t];
@@ -252,33 +255,46 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
     for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
       const float u = nu, v = nv, m = nm;
       const bool have = c0 + threadIdx.x < pe;
-      const uint64_t nx_q = c0 + PT + threadIdx.x;
-      if (nx_q < pe) { nu = bu[nx_q]; nv = bv[nx_q]; nm = bm[nx_q]; }
-      int i0, i1, j0, j1;
-      if (have && clip_range(u, c.R, tx0, txe, i0, i1) && clip_range(v, c.R, ty0, tye, j0, j1)) {
-        const int nx = i1 - i0 + 1;
-        for (int e = 0; e < nx; ++e) {
-          const float ox = u - ((float)(i0 + e) + 0.5f);
-          gxs[e][threadIdx.x] = expf(-(ox * ox) * c.inv2s2);
-        }
-        const float w = m * c.norm;
-        float *row = &acc[wv][(j0 - ty0) * TS + (i0 - tx0)];
-        for (int j = j0; j <= j1; ++j, row += TS) {
-          const float oy = v - ((float)j + 0.5f);
-          const float gy = w * expf(-(oy * oy) * c.inv2s2);
-          for (int e = 0; e < nx; ++e) atomicAdd(&row[e], gy * gxs[e][threadIdx.x]);
-        }
+      const uint64_t nq = c0 + PT + threadIdx.x;
+      if (nq < pe) { nu = bu[nq]; nv = bv[nq]; nm = bm[nq]; }
+      // phase A
+      int i0 = 1, i1 = 0, j0 = 1, j1 = 0;
+      if (have && clip_range(u, c.R, tx0, txe, i0, i1)) {
+        if (!clip_range(v, c.R, ty0, tye, j0, j1)) { i0 = 1; i1 = 0; }
       }
+      const float w = m * c.norm;
+#pragma unroll
+      for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
+      for (int i = i0; i <= i1; ++i) {
+        const float ox = u - ((float)i + 0.5f);
+        gx[threadIdx.x][i - tx0] = expf(-(ox * ox) * c.inv2s2);
+      }
+      for (int j = j0; j <= j1; ++j) {
+        const float oy = v - ((float)j + 0.5f);
+        gy[threadIdx.x][j - ty0] = w * expf(-(oy * oy) * c.inv2s2);
+      }
+      __syncthreads();
+      // phase B
+      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+      const int kb = grp * 64;
+#pragma unroll 8
+      for (int q = 0; q < 64; ++q) {
+        const float x = gx[kb + q][col];
+        a0 = __fmaf_rn(gy[kb + q][row0 + 0], x, a0);
+        a1 = __fmaf_rn(gy[kb + q][row0 + 1], x, a1);
+        a2 = __fmaf_rn(gy[kb + q][row0 + 2], x, a2);
+        a3 = __fmaf_rn(gy[kb + q][row0 + 3], x, a3);
+      }
+      part[grp][(row0 + 0) * TS + col] = a0;
+      part[grp][(row0 + 1) * TS + col] = a1;
+      part[grp][(row0 + 2) * TS + col] = a2;
+      part[grp][(row0 + 3) * TS + col] = a3;
       __syncthreads();
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const float val = acc[w][threadIdx.x];
-        acc[w][threadIdx.x] = 0.0f;
-        neumaier(s, cc, val);
-      }
-      __syncthreads();
+      for (int g = 0; g < 4; ++g) neumaier(s, cc, part[g][threadIdx.x]);
     }
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
+    __syncthreads();
   }
 }
 
