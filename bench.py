@@ -243,6 +243,11 @@ def main():
             bm.build(x, y, z, m)
             torch.cuda.synchronize()
             by_mode[str(md)] = round((time.perf_counter() - t0) * 1e3, 3)
+            if md == 1:
+                with lib.trace() as tl:
+                    bm.build(x, y, z, m)
+                extra["select_ms_by_level_per_level_schedule"] = [
+                    round(ms, 4) for name, ms in tl.records if name in ("k_select_level", "k_sel_output")]
             hm = bm.tree.host()
             for key in ("pt_id", "qx", "qy", "qz", "pt_mass", "prefix", "part_count"):
                 if not np.array_equal(hm[key], h[key]):

@@ -224,6 +224,21 @@ lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids,
                             void *workspace, size_t workspace_bytes, float *image,
                             lod_stream_t stream);
 
+/* Workspace bytes for lod_decode on a tree of node_capacity nodes. */
+lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes);
+
+/* Decode the stored points of nodes node_ids[0 .. *n_ids) (device arrays,
+ * count on the device) into caller arrays x, y, z, m (device float32, at
+ * least max_points each), node by node in the given order; each coordinate
+ * is the float32 nearest (c 2^16 + q + 1/2) 2^-(d+16) for the storing node's
+ * cell c at depth d (quantisation paragraph).  The number of points written
+ * goes to *n_points (device uint64); more than max_points sets
+ * LOD_STATUS_CAPACITY in tree->counts[2] and truncates. */
+lod_status lod_decode(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                      uint64_t max_points, float *x, float *y, float *z, float *m,
+                      uint64_t *n_points, void *workspace, size_t workspace_bytes,
+                      lod_stream_t stream);
+
 /* Adjoint of splat_render: given dL/dimage (device float32 [H*W]) write
  * dL/dm (device float32 [count]) and dL/dx, dL/dy, dL/dz (device float32
  * [count] each; any of them may be NULL to skip).  The derivative of the

@@ -193,6 +193,23 @@ lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod
   return LOD_OK;
 }
 
+lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes) {
+  if (!workspace_bytes) return LOD_EINVAL;
+  *workspace_bytes = lodh::decode_workspace(node_capacity);
+  return LOD_OK;
+}
+
+lod_status lod_decode(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
+                      float *x, float *y, float *z, float *m, uint64_t *n_points, void *workspace,
+                      size_t workspace_bytes, lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !node_ids || !n_ids || !x || !y || !z || !m || !n_points || !workspace)
+    return LOD_EINVAL;
+  if (max_points == 0) return LOD_EINVAL;
+  if (workspace_bytes < lodh::decode_workspace(tree->node_capacity)) return LOD_ENOMEM;
+  return lodh::launch_decode(*tree, node_ids, n_ids, max_points, x, y, z, m, n_points, workspace,
+                             (hipStream_t)stream);
+}
+
 lod_status splat_render_backward(const float *x, const float *y, const float *z, const float *m, uint64_t count,
                                  const lod_camera *cam, const splat_params *sp, const float *grad_image,
                                  float *grad_m, float *grad_x, float *grad_y, float *grad_z, lod_stream_t stream) {

@@ -1055,7 +1055,7 @@ __global__ void k_bottom_write(BuildArgs a, const uint32_t *__restrict__ flag, c
 }
 
 // mode 2: one persistent launch over every selecting node of every level.
-// A block takes a starting node by ticket, reduces it (node mass, selection,
+// A block takes a starting node by ticket (deepest first), reduces it (node mass, selection,
 // output) and then, if it was the last of its parent's selecting children to
 // finish, continues with the parent; otherwise it takes the next ticket.  No
 // block ever waits for another, so the grid drains without spinning.
@@ -1065,8 +1065,9 @@ __global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArg
   __shared__ uint32_t sh_v;
   while (true) {
     if (threadIdx.x == 0) {
+      // deepest starting nodes first, so that climbs overlap the remaining work
       const uint32_t tk = atomicAdd(&ctl[1], 1u);
-      sh_v = tk < ctl[0] ? bottom[tk] : NONE;
+      sh_v = tk < ctl[0] ? bottom[ctl[0] - 1 - tk] : NONE;
     }
     __syncthreads();
     uint32_t v = sh_v;

@@ -62,6 +62,9 @@ struct LodDrawLayout {
 LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points);
 lod_status launch_lod_gather(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids,
                              void *ws, const LodDrawLayout &L, hipStream_t st);
+size_t decode_workspace(uint64_t node_capacity);
+lod_status launch_decode(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
+                         float *x, float *y, float *z, float *m, uint64_t *n_points, void *ws, hipStream_t st);
 
 // View-dependent cut.
 size_t cut_workspace(uint64_t node_capacity);

@@ -610,6 +610,26 @@ lod_status launch_lod_gather(const lod_tree &tree, const uint32_t *node_ids, con
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
 
+size_t decode_workspace(uint64_t node_capacity) {
+  const uint64_t n = std::max<uint64_t>(1, node_capacity);
+  return align256(8 * (n + 1)) + align256(8 * scan_tmp_elems<uint64_t>(n + 1));
+}
+
+lod_status launch_decode(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
+                         float *x, float *y, float *z, float *m, uint64_t *n_points, void *ws, hipStream_t st) {
+  const uint64_t max_ids = std::max<uint64_t>(1, tree.node_capacity);
+  char *W = (char *)ws;
+  uint64_t *offs = (uint64_t *)W;
+  uint64_t *tmp = (uint64_t *)(W + align256(8 * (max_ids + 1)));
+  const unsigned g = (unsigned)std::min<uint64_t>(4096, (max_ids + 256) / 256);
+  LOD_LAUNCH(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, max_ids, offs);
+  device_scan<uint64_t>(offs, max_ids + 1, tmp, st);
+  LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, max_ids, max_points, n_points);
+  const unsigned dg = (unsigned)std::min<uint64_t>(16384, max_ids);
+  LOD_LAUNCH(k_lod_decode, dim3(dg), dim3(PT), 0, st, tree, node_ids, n_ids, max_ids, offs, max_points, x, y, z, m);
+  return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+}
+
 size_t cut_workspace(uint64_t node_capacity) {
   const uint64_t n = std::max<uint64_t>(1, node_capacity) + 1;
   return align256(4 * n) * 2 + align256(4 * scan_tmp_elems<uint32_t>(n));

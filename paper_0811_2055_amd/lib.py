@@ -22,6 +22,7 @@ NONE = 0xFFFFFFFF
 EXPORTS = [
     "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
     "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
+    "lod_decode_plan", "lod_decode",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -92,6 +93,8 @@ def load():
                                      C.POINTER(SplatParamsC), P, C.c_size_t, P, P]
     lib.splat_render_backward.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(CameraC),
                                           C.POINTER(SplatParamsC), P, P, P, P, P, P]
+    lib.lod_decode_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
+    lib.lod_decode.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
     lib.lod_workspace_view.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_uint32,
                                        C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]
     lib.lod_trace_begin.argtypes = []
@@ -431,3 +434,18 @@ def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas
     _check(lib.splat_render_backward(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp), _ptr(g),
                                      _ptr(gm), _ptr(gx), _ptr(gy), _ptr(gz), _stream()), "splat_render_backward")
     return gm, gx, gy, gz
+
+
+def decode_nodes(tree: Tree, node_ids, n_ids, max_points: int):
+    """Decode the stored points of the given nodes; returns (x, y, z, m, count tensor)."""
+    import torch
+    lib = load()
+    dev = tree.counts.device
+    ws = C.c_size_t()
+    _check(lib.lod_decode_plan(tree.node_capacity, C.byref(ws)), "lod_decode_plan")
+    work = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=dev)
+    out = [torch.empty(max(int(max_points), 1), dtype=torch.float32, device=dev) for _ in range(4)]
+    cnt = torch.zeros(1, dtype=torch.uint64, device=dev)
+    _check(lib.lod_decode(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points), *[_ptr(t) for t in out],
+                          _ptr(cnt), _ptr(work), ws.value, _stream()), "lod_decode")
+    return (*out, cnt)
