@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--mode", type=int, default=2, choices=[0, 1, 2],
                     help="selection schedule: 0 per-node launches, 1 per-level launches, 2 one persistent launch")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default selection schedule")
     ap.add_argument("--compare-modes", action="store_true",
                     help="also time one build in each selection schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -161,6 +162,12 @@ def main():
         log("[bench] profile steps done")
         return
 
+    tuned = None
+    if not args.no_autotune:
+        from paper_0811_2055_amd import autotune
+        rec = autotune.tune(builder, x, y, z, m, path=os.path.join(ROOT, "gpurun_out", "lod_tune.json"))
+        tuned = {k: rec[k] for k in ("mode", "select_threads", "persistent_blocks", "ms")}
+        log(f"[bench] autotuned schedule: {tuned}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -274,6 +281,8 @@ def main():
         "config": {"workload": cfg["label"], "particles": N, "n": cfg["n"], "max_depth": cfg["D"],
                    "image": f"{cfg['W']}x{cfg['H']}", "parallelism": "single GPU"},
         "roofline": roof,
+        "schedule": tuned or {"mode": builder.params.mode, "select_threads": builder.params.select_threads,
+                              "persistent_blocks": builder.params.persistent_blocks},
         "build_ms": round(build_ms, 4),
         "build_Mparticles_s": round(N / build_ms / 1e3, 1),
         "build_B_alg_GB": round(b_alg / 1e9, 3),

@@ -249,6 +249,20 @@ lod_status splat_render_backward(const float *x, const float *y, const float *z,
                                  float *grad_m, float *grad_x, float *grad_y,
                                  float *grad_z, lod_stream_t stream);
 
+/* ---- schedule autotuning ------------------------------------------------ */
+
+/* Time lod_build on this input for each candidate schedule (mode 1 and 2,
+ * select_threads in {256, 512, 1024}, mode 2 grids of 1, 2 and 4 blocks per
+ * compute unit), two timed builds each with hipEvents on `stream`, and write
+ * the fastest into p->mode, p->select_threads and p->persistent_blocks.
+ * Every schedule produces identical bytes, so the choice affects speed only.
+ * Candidates and their mean milliseconds are written to cand / ms (up to
+ * cap entries; *n_cand gets the number tried).  Synchronises the stream.
+ * Arguments as for lod_build. */
+lod_status lod_autotune(const lod_input *in, lod_params *p, void *workspace, size_t workspace_bytes,
+                        lod_tree *out, lod_params *cand, float *ms, uint32_t cap, uint32_t *n_cand,
+                        lod_stream_t stream);
+
 /* ---- introspection ----------------------------------------------------- */
 
 /* Device pointers into a lod_build workspace, valid after a build with the

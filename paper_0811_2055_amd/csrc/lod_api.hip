@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "lod.h"
 #include "lod_internal.hpp"
@@ -229,6 +230,58 @@ lod_status lod_workspace_view(const lod_input *in, const lod_params *p, void *wo
   const int kb = lodh::key_bits(*p, ns);
   const int passes = kb > 8 ? (kb + 7) / 8 : 1;
   *device_ptr = lodh::workspace_view(workspace, L, which, in->n_particles, passes, count);
+  return LOD_OK;
+}
+
+lod_status lod_autotune(const lod_input *in, lod_params *p, void *workspace, size_t workspace_bytes,
+                        lod_tree *out, lod_params *cand, float *ms, uint32_t cap, uint32_t *n_cand,
+                        lod_stream_t stream) {
+  lod_status s = check_inputs(in, p);
+  if (s != LOD_OK) return s;
+  if (!tree_arrays_ok(out) || !workspace) return LOD_EINVAL;
+  const uint32_t ns = in->snap_offsets ? in->n_snapshots : 1;
+  lodh::BuildLayout L = lodh::build_layout(in->n_particles, *p, ns);
+  if (workspace_bytes < L.total) return LOD_ENOMEM;
+  if (out->node_capacity < L.node_cap || out->point_capacity < L.point_cap) return LOD_ECAPACITY;
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess) return LOD_EDEVICE;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::vector<lod_params> cands;
+  for (uint32_t thr : {256u, 512u, 1024u}) {
+    lod_params c = *p; c.mode = 1; c.select_threads = thr; c.persistent_blocks = 0;
+    cands.push_back(c);
+    for (uint32_t per : {1u, 2u, 4u}) {
+      lod_params c2 = *p; c2.mode = 2; c2.select_threads = thr; c2.persistent_blocks = per * (uint32_t)cus;
+      cands.push_back(c2);
+    }
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LOD_EDEVICE;
+  float best = 1e30f;
+  lod_params bestp = *p;
+  uint32_t k = 0;
+  lod_status rs = LOD_OK;
+  for (const lod_params &c : cands) {
+    if ((rs = lodh::launch_build(*in, c, workspace, L, *out, st)) != LOD_OK) break;   // warm-up
+    hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && rs == LOD_OK; ++r) rs = lodh::launch_build(*in, c, workspace, L, *out, st);
+    hipEventRecord(e1, st);
+    if (rs != LOD_OK || hipEventSynchronize(e1) != hipSuccess) { rs = rs != LOD_OK ? rs : LOD_EDEVICE; break; }
+    float t = 0.0f;
+    hipEventElapsedTime(&t, e0, e1);
+    t *= 0.5f;
+    if (cand && ms && k < cap) { cand[k] = c; ms[k] = t; }
+    ++k;
+    if (t < best) { best = t; bestp = c; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (n_cand) *n_cand = k;
+  if (rs != LOD_OK) return rs;
+  p->mode = bestp.mode;
+  p->select_threads = bestp.select_threads;
+  p->persistent_blocks = bestp.persistent_blocks;
   return LOD_OK;
 }
 

@@ -22,7 +22,7 @@ NONE = 0xFFFFFFFF
 EXPORTS = [
     "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
     "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
-    "lod_decode_plan", "lod_decode",
+    "lod_decode_plan", "lod_decode", "lod_autotune",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -95,6 +95,8 @@ def load():
                                           C.POINTER(SplatParamsC), P, P, P, P, P, P]
     lib.lod_decode_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
     lib.lod_decode.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
+    lib.lod_autotune.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_size_t, C.POINTER(TreeC),
+                                 C.POINTER(Params), C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32), P]
     lib.lod_workspace_view.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_uint32,
                                        C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]
     lib.lod_trace_begin.argtypes = []
@@ -305,6 +307,28 @@ class Builder:
         _check(code, "lod_build")
         self._inp = inp
         return self.tree
+
+    def autotune(self, x, y, z, m, snap_offsets=None):
+        """Time every candidate schedule on this input; adopt and return the fastest.
+
+        Returns (best BuildParams, [(candidate BuildParams, ms), ...])."""
+        lib = load()
+        inp = _input(x, y, z, m, snap_offsets)
+        p = self.params.c()
+        cap = 64
+        cands = (Params * cap)()
+        ms = (C.c_float * cap)()
+        n = C.c_uint32()
+        _check(lib.lod_autotune(C.byref(inp), C.byref(p), _ptr(self.workspace), self.ws_bytes,
+                                C.byref(self.tree.c()), cands, ms, cap, C.byref(n), _stream()), "lod_autotune")
+        self.params.mode, self.params.select_threads, self.params.persistent_blocks = \
+            p.mode, p.select_threads, p.persistent_blocks
+        table = []
+        for i in range(min(n.value, cap)):
+            c = cands[i]
+            table.append((dict(mode=c.mode, select_threads=c.select_threads,
+                               persistent_blocks=c.persistent_blocks), float(ms[i])))
+        return self.params, table
 
     def view(self, which: int, dtype):
         """Intermediate arrays (0 keys, 1 ids, 2 w, 3 key bins, 4 witness) as a torch view."""

@@ -149,3 +149,20 @@ def test_domain_error_is_flagged():
     s.m[3] = np.float32(-1.0)
     tree = lib.build(*to_dev(s), lib.BuildParams(n=16, max_depth=3))
     assert tree.host()["status"] & lib.STATUS_DOMAIN
+
+
+def test_autotune_keeps_bytes_and_caches(tmp_path):
+    from paper_0811_2055_amd import autotune
+    s = synth.small_clustered(80000, 51)
+    d = to_dev(s)
+    b = lib.Builder(s.n, lib.BuildParams(n=400, max_depth=6, seed=3, mode=2))
+    ref = b.build(*d).host()
+    rec = autotune.tune(b, *d, path=str(tmp_path / "tune.json"), device_name="test")
+    assert rec["mode"] in (1, 2) and len(rec["candidates"]) == 12
+    got = b.build(*d).host()
+    for k, v in ref.items():
+        if isinstance(v, np.ndarray):
+            assert np.array_equal(v, got[k]), k
+    b2 = lib.Builder(s.n, lib.BuildParams(n=400, max_depth=6, seed=3, mode=2))
+    assert autotune.apply_cached(b2, "test", path=str(tmp_path / "tune.json"))
+    assert (b2.params.mode, b2.params.select_threads) == (rec["mode"], rec["select_threads"])
