@@ -212,12 +212,13 @@ __device__ __forceinline__ bool clip_range(float t, float R, int lo_clip, int hi
 // One block per slice.  The blob is separable, so a chunk of 256 points adds
 // Gy^T Gx to the 16x16 tile, with Gx[k][i] = exp(-ox^2/2s^2) and Gy[k][j] =
 // m norm exp(-oy^2/2s^2) inside point k's truncation square and 0 outside.
-// Phase A: thread k fills row k of Gx and Gy in LDS.  Phase B: thread group g
-// (64 threads) sums points 64g..64g+63 for 4 pixels of one column each, with
-// fused multiply-adds in a fixed order -- no atomics, so the image is
-// bit-reproducible.  The four group partials of a pixel (at most 64 terms
+// Phase A: thread k fills row k of Gx and Gy in LDS.  Phase B: wave g
+// contracts points 64g..64g+63 on the matrix cores (MFMA 16x16x4, float32),
+// each lane ending with 4 pixels of one column -- no atomics, so the image is
+// bit-reproducible.  The four wave partials of a pixel (at most 64 products
 // each) are then folded into the pixel's compensated (Neumaier) float32 sum.
 constexpr int GXS = TS + 1;          // padded row: conflict-free phase-A writes
+typedef float float4v __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ tile_off,
                                                    const uint32_t *__restrict__ tile_count,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
@@ -274,17 +275,18 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
         gy[threadIdx.x][j - ty0] = w * expf(-(oy * oy) * c.inv2s2);
       }
       __syncthreads();
-      // phase B
-      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+      // phase B: wave g accumulates points 64g..64g+63 with 16 MFMA steps of
+      // 16x16x4 (float32); lane l feeds A[l%16][l/16] = Gy[k][row] and
+      // B[l/16][l%16] = Gx[k][col] and receives rows 4(l/16)..+3 of column l%16
       const int kb = grp * 64;
-#pragma unroll 8
-      for (int q = 0; q < 64; ++q) {
-        const float x = gx[kb + q][col];
-        a0 = __fmaf_rn(gy[kb + q][row0 + 0], x, a0);
-        a1 = __fmaf_rn(gy[kb + q][row0 + 1], x, a1);
-        a2 = __fmaf_rn(gy[kb + q][row0 + 2], x, a2);
-        a3 = __fmaf_rn(gy[kb + q][row0 + 3], x, a3);
+      const int ln = threadIdx.x % 64;
+      float4v acc4 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const int kk = kb + st * 4 + ln / 16;
+        acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(gy[kk][ln % 16], gx[kk][ln % 16], acc4, 0, 0, 0);
       }
+      const float a0 = acc4[0], a1 = acc4[1], a2 = acc4[2], a3 = acc4[3];
       part[grp][(row0 + 0) * TS + col] = a0;
       part[grp][(row0 + 1) * TS + col] = a1;
       part[grp][(row0 + 2) * TS + col] = a2;
