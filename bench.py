@@ -37,6 +37,30 @@ KERNEL_BYTES = {
 }
 
 
+KERNEL_SOURCES = ["paper_0811_2055_amd/csrc/lod_build.hip", "paper_0811_2055_amd/csrc/lod_splat.hip",
+                  "paper_0811_2055_amd/csrc/lod_device.hpp", "paper_0811_2055_amd/csrc/lod_scan.hpp"]
+TRAFFIC_TABLE = "profiles/hbm_traffic_sp150m_step.txt"
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed PMC table, or None when
+    the table was measured on different kernel sources (or has no such kernel)."""
+    import hashlib
+    try:
+        h = hashlib.sha1(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+        lines = open(os.path.join(ROOT, TRAFFIC_TABLE)).read().splitlines()
+    except OSError:
+        return None
+    stamp = [l.split(":", 1)[1].strip() for l in lines if l.startswith("# kernel-source-sha1:")]
+    if not stamp or stamp[0] != h:
+        return None
+    for l in lines:
+        parts = l.split()
+        if parts and parts[0] == kernel and len(parts) == 5:
+            return float(parts[4]) * 1e9
+    return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -206,7 +230,7 @@ def main():
     if per_unit is not None:
         achieved = per_unit * N / (dom_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_name), "kernel": dom_name,
                 "bytes_per_particle": per_unit, "avg_launch_ms": round(dom_avg, 4)}
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
