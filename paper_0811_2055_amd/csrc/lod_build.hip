@@ -142,33 +142,53 @@ __global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key
   for (int i = threadIdx.x; i < RADIX; i += TB) thist[(uint64_t)i * n_tiles + tile] = hist[i];
 }
 
-// Stable scatter of one LSD pass.  Wave w of the block owns tile elements
-// [w*1024, (w+1)*1024); in round r lane l holds element w*1024 + r*64 + l, so
-// element order is (w, r, l).  Ranks within a wave come from 8 ballots (the
-// lanes sharing the digit) and a wave-private LDS counter per digit.
+// Stable scatter of one LSD pass over 4096-element tiles, 512 threads.  Wave
+// w of the block owns tile elements [w*512, (w+1)*512); in round r lane l holds
+// element w*512 + r*64 + l, so element order is (w, r, l).  All loads of a
+// thread's 8 elements are issued first, so their latency overlaps the ranking.
+// Ranks within a wave come from 8 ballots (the lanes sharing the digit) and a
+// wave-private LDS counter per digit; the tile is staged in LDS in digit order
+// so that the global writes of each digit run are contiguous.
+constexpr int STB = 512;                     // scatter threads per block
+constexpr int SITEMS = TILE / STB;           // 8 elements per thread
+
 template <bool FIRST>
-__global__ __launch_bounds__(TB) void k_scatter(uint64_t N, int shift, const uint32_t *__restrict__ thist,
-                                                uint64_t n_tiles,
-                                                const uint32_t *__restrict__ key_in,
-                                                const uint32_t *__restrict__ idx_in,
-                                                const uint64_t *__restrict__ lo_in,
-                                                const float *__restrict__ m_in,
-                                                uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
-                                                uint64_t *__restrict__ lo_out, float *__restrict__ m_out) {
-  constexpr int NW = TB / WAVE;               // 4 waves
-  constexpr int PER_WAVE = TILE / NW;         // 1024
-  constexpr int ROUNDS = PER_WAVE / WAVE;     // 16
+__global__ __launch_bounds__(STB) void k_scatter(uint64_t N, int shift, const uint32_t *__restrict__ thist,
+                                                 uint64_t n_tiles,
+                                                 const uint32_t *__restrict__ key_in,
+                                                 const uint32_t *__restrict__ idx_in,
+                                                 const uint64_t *__restrict__ lo_in,
+                                                 const float *__restrict__ m_in,
+                                                 uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
+                                                 uint64_t *__restrict__ lo_out, float *__restrict__ m_out) {
+  constexpr int NW = STB / WAVE;              // 8 waves
+  constexpr int PER_WAVE = TILE / NW;         // 512
+  constexpr int ROUNDS = PER_WAVE / WAVE;     // 8
   __shared__ uint32_t wcnt[NW][RADIX];
   __shared__ uint32_t bin_start[RADIX];       // tile-local start of each digit
   __shared__ uint32_t gofs[RADIX];            // global start of this tile's digit run
   __shared__ uint64_t stage[TILE];
-  __shared__ uint32_t tmp[TB / WAVE + 1];
+  __shared__ uint32_t tmp[STB / WAVE + 1];
 
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x / WAVE;
   const uint64_t tile = blockIdx.x;
   const uint64_t tbase = tile * TILE;
-  for (int i = threadIdx.x; i < NW * RADIX; i += TB) (&wcnt[0][0])[i] = 0;
+  const uint64_t ebase = tbase + (uint64_t)w * PER_WAVE + lane;
+  uint32_t kk[ROUNDS], ii[ROUNDS];
+  uint64_t ll[ROUNDS];
+  float mm[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint64_t e = ebase + (uint64_t)r * WAVE;
+    const bool valid = e < N;
+    kk[r] = valid ? key_in[e] : 0u;
+    ii[r] = FIRST ? (uint32_t)e : (valid ? idx_in[e] : 0u);
+    ll[r] = valid ? lo_in[e] : 0ull;
+    mm[r] = valid ? m_in[e] : 0.0f;
+  }
+  for (int i = threadIdx.x; i < NW * RADIX; i += STB) (&wcnt[0][0])[i] = 0;
+  if (threadIdx.x < RADIX) gofs[threadIdx.x] = thist[(uint64_t)threadIdx.x * n_tiles + tile];
   __syncthreads();
 
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
@@ -176,9 +196,8 @@ __global__ __launch_bounds__(TB) void k_scatter(uint64_t N, int shift, const uin
   uint32_t rnk[ROUNDS];
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) {
-    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
-    const bool valid = e < N;
-    const uint32_t d = valid ? ((key_in[e] >> shift) & 0xFFu) : 0u;
+    const bool valid = ebase + (uint64_t)r * WAVE < N;
+    const uint32_t d = (kk[r] >> shift) & 0xFFu;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -187,7 +206,7 @@ __global__ __launch_bounds__(TB) void k_scatter(uint64_t N, int shift, const uin
     }
     const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
     const uint32_t cnt = (uint32_t)__popcll(peers);
-    uint32_t old = valid ? wcnt[w][d] : 0u;
+    const uint32_t old = valid ? wcnt[w][d] : 0u;
     if (valid && below == 0) wcnt[w][d] = old + cnt;
     dig[r] = d;
     rnk[r] = old + below;
@@ -198,34 +217,30 @@ __global__ __launch_bounds__(TB) void k_scatter(uint64_t N, int shift, const uin
   if (threadIdx.x < RADIX) {
     const int d = threadIdx.x;
     for (int ww = 0; ww < NW; ++ww) {
-      uint32_t c = wcnt[ww][d];
+      const uint32_t c = wcnt[ww][d];
       wcnt[ww][d] = tot;
       tot += c;
     }
-    gofs[d] = thist[(uint64_t)d * n_tiles + tile];
   }
   uint32_t dummy;
-  uint32_t st = block_excl_scan<uint32_t>(threadIdx.x < RADIX ? tot : 0u, tmp, dummy);
+  const uint32_t st = block_excl_scan<uint32_t>(threadIdx.x < RADIX ? tot : 0u, tmp, dummy);
   if (threadIdx.x < RADIX) bin_start[threadIdx.x] = st;
   __syncthreads();
 
-  // tile-local slot of each element
   uint32_t slot[ROUNDS];
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) slot[r] = bin_start[dig[r]] + wcnt[w][dig[r]] + rnk[r];
   const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, N - tbase);
 
-  // stage keys; derive each output slot's global position
-  uint64_t gpos[ITEMS];
+  // keys (with their output positions), then ids, fractions, masses
+  uint64_t gpos[SITEMS];
 #pragma unroll
-  for (int r = 0; r < ROUNDS; ++r) {
-    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
-    if (e < N) stage[slot[r]] = key_in[e];
-  }
+  for (int r = 0; r < ROUNDS; ++r)
+    if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = kk[r];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+  for (int i = 0; i < SITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
     gpos[i] = ~0ull;
     if (s < tile_n) {
       const uint32_t k = (uint32_t)stage[s];
@@ -235,42 +250,33 @@ __global__ __launch_bounds__(TB) void k_scatter(uint64_t N, int shift, const uin
     }
   }
   __syncthreads();
-  // ids
 #pragma unroll
-  for (int r = 0; r < ROUNDS; ++r) {
-    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
-    if (e < N) stage[slot[r]] = FIRST ? (uint64_t)e : (uint64_t)idx_in[e];
-  }
+  for (int r = 0; r < ROUNDS; ++r)
+    if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = ii[r];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+  for (int i = 0; i < SITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
     if (s < tile_n) idx_out[gpos[i]] = (uint32_t)stage[s];
   }
   __syncthreads();
-  // fractions
 #pragma unroll
-  for (int r = 0; r < ROUNDS; ++r) {
-    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
-    if (e < N) stage[slot[r]] = lo_in[e];
-  }
+  for (int r = 0; r < ROUNDS; ++r)
+    if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = ll[r];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+  for (int i = 0; i < SITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
     if (s < tile_n) lo_out[gpos[i]] = stage[s];
   }
   __syncthreads();
-  // masses
 #pragma unroll
-  for (int r = 0; r < ROUNDS; ++r) {
-    const uint64_t e = tbase + (uint64_t)w * PER_WAVE + (uint64_t)r * WAVE + lane;
-    if (e < N) stage[slot[r]] = (uint64_t)__float_as_uint(m_in[e]);
-  }
+  for (int r = 0; r < ROUNDS; ++r)
+    if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = (uint64_t)__float_as_uint(mm[r]);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * TB + threadIdx.x;
+  for (int i = 0; i < SITEMS; ++i) {
+    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
     if (s < tile_n) m_out[gpos[i]] = __uint_as_float((uint32_t)stage[s]);
   }
 }
@@ -1216,14 +1222,14 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const int passes = std::max(1, (kb + 7) / 8);
   // pass 0: keys/fractions from keygen (A), ids implicit, masses from the input; writes B
   device_scan<uint32_t>(thist, hist_n, scan32, st);
-  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 0, thist, tiles,
+  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(STB), 0, st, N, 0, thist, tiles,
                      keyA, (const uint32_t *)nullptr, loA, in.mass, keyB, idxB, loB, mB);
   uint32_t *ks = keyB, *is = idxB; uint64_t *ls = loB; float *ms = mB;
   uint32_t *kd = keyA, *id = idxA; uint64_t *ld = loA; float *md = mA;
   for (int ps = 1; ps < passes; ++ps) {
     LOD_LAUNCH(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
     device_scan<uint32_t>(thist, hist_n, scan32, st);
-    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(TB), 0, st, N, 8 * ps, thist, tiles,
+    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(STB), 0, st, N, 8 * ps, thist, tiles,
                        ks, is, ls, ms, kd, id, ld, md);
     std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(ms, md);
   }
