@@ -33,7 +33,7 @@ KERNEL_BYTES = {
     "k_scatter<true>": 36.0,     # read key, fraction, mass (16) write key,id,fraction,mass (20)
     "k_scatter<false>": 40.0,    # read 20 write 20
     "k_upsweep": 4.0,            # read key
-    "k_density": 20.0,           # read key, id (8) write w, K (12)
+    "k_density": 14.0,           # read key, id (8) write w (4), kbin (2)
 }
 
 

@@ -350,3 +350,59 @@ def decoded_points(tree: Tree, nodes=None):
         e = np.zeros(0, np.float32)
         return e, e, e, e
     return (np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(ms))
+
+
+def node_direct(x, y, z, m, cell, d: int, n: int, D: int, L_rho: int | None = None, alpha: int = 1,
+                seed: int = 0, dens_counts=None, keys_D=None):
+    """Stored points of the single depth-d node with cell coordinates `cell`
+    (cx, cy, cz), straight from the definition over the raw particles.
+
+    Returns (ids ascending by (key, id), qx, qy, qz, masses, node mass), where the
+    ids are the stored particles in the node's output order.  dens_counts may
+    pass precomputed depth-L cell counts (see `density_counts`), keys_D the
+    depth-D Morton keys of all particles (membership is then a key prefix test).
+    """
+    if L_rho is None:
+        L_rho = D
+    if keys_D is not None:
+        want = int(interleave(np.array([cell[0]]), np.array([cell[1]]), np.array([cell[2]]), d)[0])
+        members = np.nonzero((keys_D >> np.uint64(3 * (D - d))) == np.uint64(want))[0]
+    else:
+        inside = np.ones(len(x), dtype=bool)
+        for a, c in ((x, cell[0]), (y, cell[1]), (z, cell[2])):
+            inside &= cell_coords(a, d) == c
+        members = np.nonzero(inside)[0]
+    mass_node = exact_sum(m[members])
+    keys = interleave(cell_coords(x[members], D), cell_coords(y[members], D), cell_coords(z[members], D), D)
+    order = np.lexsort((members, keys))            # sorted order: (key, id)
+    members = members[order]
+    if len(members) <= n:
+        sel = members
+        out_mass = m[sel].copy()
+    else:
+        if dens_counts is None:
+            dens_counts = density_counts(x, y, z, L_rho)
+        cl = (cell_coords(x[members], L_rho), cell_coords(y[members], L_rho), cell_coords(z[members], L_rho))
+        w = dens_counts[cl[0] + (cl[1] << L_rho) + (cl[2] << (2 * L_rho))].astype(np.uint64)
+        U = particle_uniform(members, 0, seed)
+        K = selection_keys(U, w, alpha)
+        rank = np.lexsort((members, K))
+        top = rank[:n + 1]
+        chosen = np.sort(top[:n])                   # ascending sorted position
+        t = top[n]
+        a_sel = weight_power(w[chosen], alpha)
+        a_t = float(weight_power(np.array([w[t]]), alpha)[0])
+        tau = a_t * 4294967296.0 / float(U[t])
+        p = np.minimum(1.0, a_sel / tau)
+        mhat = m[members[chosen]].astype(np.float64) / p
+        s = mass_node / exact_sum(mhat)
+        sel = members[chosen]
+        out_mass = (s * mhat).astype(np.float32)
+    q = [quantise(a[sel], c, d) for a, c in ((x, cell[0]), (y, cell[1]), (z, cell[2]))]
+    return sel.astype(np.uint32), q[0], q[1], q[2], out_mass, mass_node
+
+
+def density_counts(x, y, z, L: int) -> np.ndarray:
+    """Particle count of every depth-L cell, indexed cx + cy 2^L + cz 2^(2L)."""
+    idx = cell_coords(x, L) + (cell_coords(y, L) << L) + (cell_coords(z, L) << (2 * L))
+    return np.bincount(idx, minlength=1 << (3 * L))

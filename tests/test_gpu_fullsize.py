@@ -1,0 +1,123 @@
+"""Full-size checks at the benchmark configuration (150 M Soneira-Peebles
+particles, n = 16000, D = 8, the autotuned schedule), on outputs the oracle
+computes one by one: sampled nodes' stored points straight from the
+definition over the raw particles, properties of the sort and the tree that
+hold at any size, and sampled pixels of the full render.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lod as olod
+from oracle import splat as osplat
+from paper_0811_2055_amd import autotune, lib
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+
+def log(msg):
+    print(f"[fullsize {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import torch
+    log("generating 150M Soneira-Peebles particles")
+    s = synth.config3()
+    d = [torch.from_numpy(a).cuda() for a in (s.x, s.y, s.z, s.m)]
+    b = lib.Builder(s.n, lib.BuildParams(n=16000, max_depth=8, seed=0))
+    autotune.tune(b, *d, path="/tmp/lod_tune_test.json")
+    log(f"schedule {b.params}")
+    tree = b.build(*d)
+    h = tree.host()
+    log(f"built: {h['n_nodes']} nodes {h['n_points']} points status {h['status']}")
+    keys_D = olod.interleave(*(olod.cell_coords(a, 8) for a in (s.x, s.y, s.z)), 8)
+    log("oracle depth-8 keys")
+    return s, d, b, tree, h, keys_D
+
+
+def test_sort_and_tree_properties(c3):
+    import torch
+    s, d, b, tree, h, keys_D = c3
+    assert h["status"] == 0
+    keys = b.view(0, torch.uint32).view(torch.int32).long() & 0xFFFFFFFF
+    ids = b.view(1, torch.uint32).view(torch.int32).long()
+    N = s.n
+    # the sort: keys non-decreasing, ids ascending within equal keys, a permutation
+    assert bool((keys[1:] >= keys[:-1]).all())
+    eq = keys[1:] == keys[:-1]
+    assert bool((ids[1:][eq] > ids[:-1][eq]).all())
+    assert int(torch.bincount(ids, minlength=N).max()) == 1
+    # keys of sampled particles from their raw coordinates (oracle key function)
+    rng = np.random.default_rng(0)
+    pos = rng.integers(0, N, 20000)
+    gi = ids[torch.from_numpy(pos).cuda()].cpu().numpy()
+    assert np.array_equal(keys[torch.from_numpy(pos).cuda()].cpu().numpy().astype(np.uint64), keys_D[gi])
+    # density: the run length of equal keys at sampled positions
+    w = b.view(2, torch.uint32).view(torch.int32).long()
+    kn = keys.cpu().numpy()
+    lo = np.searchsorted(kn, kn[pos], "left"); hi = np.searchsorted(kn, kn[pos], "right")
+    assert np.array_equal(w[torch.from_numpy(pos).cuda()].cpu().numpy(), hi - lo)
+    # tree invariants
+    n, D = 16000, 8
+    internal = h["first_child"] != lib.NONE
+    assert np.array_equal(internal, (h["part_count"] > n) & (h["depth"] < D))
+    leaf = ~internal
+    lb = h["part_begin"][leaf].astype(np.int64); lc = h["part_count"][leaf].astype(np.int64)
+    o = np.argsort(lb)
+    assert lb[o][0] == 0 and np.all(lb[o][1:] == (lb[o] + lc[o])[:-1]) and (lb[o] + lc[o])[-1] == N
+    for v in np.nonzero(internal)[0]:
+        fc = int(h["first_child"][v]); k = bin(int(h["child_mask"][v])).count("1")
+        assert int(h["part_count"][fc:fc + k].sum()) == int(h["part_count"][v])
+    sh = 3 * (D - h["depth"].astype(np.int64))
+    assert np.array_equal(kn[h["part_begin"].astype(np.int64)] >> sh, h["prefix"].astype(np.int64))
+    assert np.array_equal(h["pt_count"], np.minimum(h["part_count"], n))
+    assert h["n_points"] == int(h["pt_count"].astype(np.int64).sum())
+
+
+def test_sampled_nodes_match_direct_definition(c3):
+    s, d, b, tree, h, keys_D = c3
+    n, D = 16000, 8
+    log("density counts")
+    dens = olod.density_counts(s.x, s.y, s.z, D)
+    counts = h["part_count"].astype(np.int64)
+    depth = h["depth"].astype(np.int64)
+    rng = np.random.default_rng(1)
+    picks = []
+    for dd in (1, 2, 3, 4, 5, 6, 7, 8):
+        cand = np.nonzero((depth == dd) & (counts > n) & (counts < 4_000_000))[0]
+        if len(cand):
+            picks.append(int(rng.choice(cand)))
+    small = np.nonzero(counts <= n)[0]
+    picks += [int(v) for v in rng.choice(small, 3, replace=False)]
+    for v in picks:
+        dd = int(depth[v])
+        cell = olod.deinterleave(int(h["prefix"][v]), dd)
+        t0 = time.time()
+        ids, qx, qy, qz, mass, M = olod.node_direct(s.x, s.y, s.z, s.m, cell, dd, n, D, dens_counts=dens,
+                                                      keys_D=keys_D)
+        pb, pc = int(h["pt_begin"][v]), int(h["pt_count"][v])
+        log(f"node {v} depth {dd} count {counts[v]}: oracle {time.time() - t0:.1f} s")
+        assert np.array_equal(h["pt_id"][pb:pb + pc], ids), v
+        assert np.array_equal(h["qx"][pb:pb + pc], qx) and np.array_equal(h["qy"][pb:pb + pc], qy)
+        assert np.array_equal(h["qz"][pb:pb + pc], qz)
+        ulp = np.abs(h["pt_mass"][pb:pb + pc].view(np.int32).astype(np.int64) - mass.view(np.int32))
+        assert ulp.max() <= 1, v
+        assert abs(h["node_mass"][v] - M) <= 1e-12 * M
+
+
+def test_sampled_pixels_of_full_render(c3):
+    s, d, b, tree, h, keys_D = c3
+    cam = lib.Camera.ortho(1024, 1024)
+    img = lib.splat(*d, cam).cpu().numpy()
+    rng = np.random.default_rng(2)
+    flat = np.argsort(-img.ravel())
+    pix = np.concatenate([flat[:4], rng.choice(np.nonzero(img.ravel() > 0)[0], 8, replace=False)])
+    pi, pj = pix % 1024, pix // 1024
+    log("oracle pixels")
+    want = osplat.render_pixels(osplat.Camera(0, 1024, 1024), s.x, s.y, s.z, s.m, pi, pj)
+    got = img[pj, pi].astype(np.float64)
+    assert np.all(np.abs(got - want) <= 1e-5 * want), (got, want)

@@ -571,3 +571,24 @@ def test_cut_perspective_cover_and_monotone():
             (cx, cy, cz), d = lod.node_origin(t, p)
             side = 2.0 ** -d
             assert all(cc * side <= 0.30 <= (cc + 1) * side for cc in (cx, cy, cz))
+
+
+@pytest.mark.parametrize("alpha", [-1, 0, 1])
+def test_node_direct_matches_tree_build(alpha):
+    """The one-node definition over raw particles equals the whole-tree build
+    on every node (both membership tests: cell coordinates and key prefix)."""
+    s = synth.small_clustered(20000, 91 + alpha)
+    n, D = 120, 5
+    t = lod.lod_build(s.x, s.y, s.z, s.m, n=n, D=D, seed=4, alpha=alpha)
+    keys = lod.interleave(*(lod.cell_coords(a, D) for a in (s.x, s.y, s.z)), D)
+    dens = lod.density_counts(s.x, s.y, s.z, D)
+    for v in range(t.n_nodes):
+        d = int(t.depth[v])
+        c = lod.deinterleave(int(t.prefix[v]), d)
+        kw = {"keys_D": keys} if v % 2 else {}
+        ids, qx, qy, qz, mass, M = lod.node_direct(s.x, s.y, s.z, s.m, c, d, n, D, alpha=alpha, seed=4,
+                                                    dens_counts=dens, **kw)
+        pb, pc = int(t.pt_begin[v]), int(t.pt_count[v])
+        assert np.array_equal(t.pt_id[pb:pb + pc], ids)
+        assert np.array_equal(t.qx[pb:pb + pc], qx) and np.array_equal(t.qz[pb:pb + pc], qz)
+        assert np.array_equal(t.pt_mass[pb:pb + pc], mass) and M == t.node_mass[v]
