@@ -2,8 +2,9 @@
 // paragraphs of arXiv:0811.2055; readings fixed in the oracle's docstrings).
 //
 // Data path (all device-resident, one stream, no host synchronisation):
-//   keygen     x,y,z -> sort key (snapshot | 3D-bit Morton), 48-bit fraction,
-//              domain check, digit-0 tile histograms
+//   keygen     domain check and digit-0 tile histograms of the sort key
+//              (snapshot | 3D-bit Morton); the first scatter pass recomputes
+//              the key and the 48-bit fraction from x, y, z
 //   radix sort stable LSD, 8-bit digits, reduce-then-scan: per-tile digit
 //              histograms, one device scan, scatter with wave-ballot ranks and
 //              LDS-staged coalesced writes; payload (id, fraction, mass) rides
@@ -85,39 +86,49 @@ __global__ void k_check_offsets(BuildArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// keygen: key, 48-bit fraction, domain check, digit-0 tile histogram
+// sort key and 48-bit fraction of particle e.  Both the keygen histogram and
+// the first scatter pass call this, so their digits agree bit for bit (NaN and
+// out-of-range coordinates map to 0 and are reported by keygen's check).
 
+struct PKey {
+  uint32_t key;
+  uint64_t lo;
+  bool ok;
+};
+
+__device__ __forceinline__ PKey particle_key(const BuildArgs &a, float xe, float ye, float ze, float me,
+                                             uint64_t e) {
+  uint32_t X, Y, Z;
+  bool ok = fixed_coord(xe, a.D, X);
+  ok &= fixed_coord(ye, a.D, Y);
+  ok &= fixed_coord(ze, a.D, Z);
+  ok &= (me >= 0.0f) && (me <= 3.4028235e38f);
+  const uint32_t cmask = (1u << a.D) - 1u;
+  const uint32_t cx = (X >> 16) & cmask, cy = (Y >> 16) & cmask, cz = (Z >> 16) & cmask;
+  uint32_t k = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+  if (a.n_snap > 1) k |= (uint32_t)(((uint64_t)snapshot_of(a, e) << (3 * a.D)) & 0xFFFFFFFFull);
+  const uint64_t lo = (uint64_t)(X & 0xFFFFu) | ((uint64_t)(Y & 0xFFFFu) << 16) | ((uint64_t)(Z & 0xFFFFu) << 32);
+  return PKey{k, lo, ok};
+}
+
+// keygen: domain check and digit-0 tile histograms (reads the input only; the
+// first scatter pass recomputes the keys instead of reading them back)
 __global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, const float *__restrict__ y,
                                                const float *__restrict__ z, const float *__restrict__ m,
-                                               BuildArgs a, uint32_t *__restrict__ key,
-                                               uint64_t *__restrict__ lo, uint32_t *__restrict__ thist,
-                                               uint64_t n_tiles) {
+                                               BuildArgs a, uint32_t *__restrict__ thist, uint64_t n_tiles) {
   __shared__ uint32_t hist[RADIX];
   __shared__ int bad;
   for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   const uint64_t tile = blockIdx.x;
-  const int D = a.D;
-  const uint32_t cmask = (1u << D) - 1u;
   bool my_bad = false;
   for (int i = 0; i < ITEMS; ++i) {
     const uint64_t e = tile * TILE + (uint64_t)i * TB + threadIdx.x;
     if (e >= a.N) break;
-    uint32_t X, Y, Z;
-    bool ok = fixed_coord(x[e], D, X);
-    ok &= fixed_coord(y[e], D, Y);
-    ok &= fixed_coord(z[e], D, Z);
-    const float me = m[e];
-    ok &= (me >= 0.0f) && (me <= 3.4028235e38f);
-    my_bad |= !ok;
-    const uint32_t cx = (X >> 16) & cmask, cy = (Y >> 16) & cmask, cz = (Z >> 16) & cmask;
-    uint32_t k = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
-    const uint32_t snap = snapshot_of(a, e);
-    if (a.n_snap > 1) k |= (uint32_t)(((uint64_t)snap << (3 * D)) & 0xFFFFFFFFull);
-    key[e] = k;
-    lo[e] = (uint64_t)(X & 0xFFFFu) | ((uint64_t)(Y & 0xFFFFu) << 16) | ((uint64_t)(Z & 0xFFFFu) << 32);
-    atomicAdd(&hist[k & 0xFFu], 1u);
+    const PKey pk = particle_key(a, x[e], y[e], z[e], m[e], e);
+    my_bad |= !pk.ok;
+    atomicAdd(&hist[pk.key & 0xFFu], 1u);
   }
   if (my_bad) bad = 1;
   __syncthreads();
@@ -152,15 +163,21 @@ __global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key
 constexpr int STB = 512;                     // scatter threads per block
 constexpr int SITEMS = TILE / STB;           // 8 elements per thread
 
+// FIRST: the input is the particles themselves (x, y, z, m with ids implicit);
+// keys and fractions come from particle_key.  Otherwise (key, id, fraction,
+// mass) arrays of the previous pass.
+struct ScatterIn {
+  const uint32_t *key, *idx;
+  const uint64_t *lo;
+  const float *x, *y, *z, *m;
+};
+
 template <bool FIRST>
-__global__ __launch_bounds__(STB) void k_scatter(uint64_t N, int shift, const uint32_t *__restrict__ thist,
-                                                 uint64_t n_tiles,
-                                                 const uint32_t *__restrict__ key_in,
-                                                 const uint32_t *__restrict__ idx_in,
-                                                 const uint64_t *__restrict__ lo_in,
-                                                 const float *__restrict__ m_in,
+__global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const uint32_t *__restrict__ thist,
+                                                 uint64_t n_tiles, ScatterIn in,
                                                  uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
                                                  uint64_t *__restrict__ lo_out, float *__restrict__ m_out) {
+  const uint64_t N = a.N;
   constexpr int NW = STB / WAVE;              // 8 waves
   constexpr int PER_WAVE = TILE / NW;         // 512
   constexpr int ROUNDS = PER_WAVE / WAVE;     // 8
@@ -182,10 +199,19 @@ __global__ __launch_bounds__(STB) void k_scatter(uint64_t N, int shift, const ui
   for (int r = 0; r < ROUNDS; ++r) {
     const uint64_t e = ebase + (uint64_t)r * WAVE;
     const bool valid = e < N;
-    kk[r] = valid ? key_in[e] : 0u;
-    ii[r] = FIRST ? (uint32_t)e : (valid ? idx_in[e] : 0u);
-    ll[r] = valid ? lo_in[e] : 0ull;
-    mm[r] = valid ? m_in[e] : 0.0f;
+    if (FIRST) {
+      const float xe = valid ? in.x[e] : 0.0f, ye = valid ? in.y[e] : 0.0f, ze = valid ? in.z[e] : 0.0f;
+      mm[r] = valid ? in.m[e] : 0.0f;
+      const PKey pk = particle_key(a, xe, ye, ze, mm[r], e);
+      kk[r] = pk.key;
+      ll[r] = pk.lo;
+      ii[r] = (uint32_t)e;
+    } else {
+      kk[r] = valid ? in.key[e] : 0u;
+      ii[r] = valid ? in.idx[e] : 0u;
+      ll[r] = valid ? in.lo[e] : 0ull;
+      mm[r] = valid ? in.m[e] : 0.0f;
+    }
   }
   for (int i = threadIdx.x; i < NW * RADIX; i += STB) (&wcnt[0][0])[i] = 0;
   if (threadIdx.x < RADIX) gofs[threadIdx.x] = thist[(uint64_t)threadIdx.x * n_tiles + tile];
@@ -1216,21 +1242,20 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const uint64_t tiles = (N + TILE - 1) / TILE;
   const uint64_t hist_n = (uint64_t)RADIX * tiles;
 
-  LOD_LAUNCH(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a,
-                     keyA, loA, thist, tiles);
+  LOD_LAUNCH(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a, thist, tiles);
   const int kb = key_bits(p, n_snap);
   const int passes = std::max(1, (kb + 7) / 8);
-  // pass 0: keys/fractions from keygen (A), ids implicit, masses from the input; writes B
+  // pass 0 reads the particles (keys recomputed, ids implicit) and writes B
   device_scan<uint32_t>(thist, hist_n, scan32, st);
-  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(STB), 0, st, N, 0, thist, tiles,
-                     keyA, (const uint32_t *)nullptr, loA, in.mass, keyB, idxB, loB, mB);
+  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 0, thist, tiles,
+             ScatterIn{nullptr, nullptr, nullptr, in.x, in.y, in.z, in.mass}, keyB, idxB, loB, mB);
   uint32_t *ks = keyB, *is = idxB; uint64_t *ls = loB; float *ms = mB;
   uint32_t *kd = keyA, *id = idxA; uint64_t *ld = loA; float *md = mA;
   for (int ps = 1; ps < passes; ++ps) {
     LOD_LAUNCH(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
     device_scan<uint32_t>(thist, hist_n, scan32, st);
-    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(STB), 0, st, N, 8 * ps, thist, tiles,
-                       ks, is, ls, ms, kd, id, ld, md);
+    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 8 * ps, thist, tiles,
+               ScatterIn{ks, is, ls, nullptr, nullptr, nullptr, ms}, kd, id, ld, md);
     std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(ms, md);
   }
   Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint16_t *)(W + L.kb)};
