@@ -160,8 +160,7 @@ lod_status splat_render(const float *x, const float *y, const float *z, const fl
   lod_status s = lodh::splat_layout(count, *cam, *sp, L);
   if (s != LOD_OK) return s;
   if (workspace_bytes < L.total) return LOD_ENOMEM;
-  return lodh::launch_splat(x, y, z, m, count, nullptr, *cam, *sp, workspace, L, image, nullptr,
-                            (hipStream_t)stream);
+  return lodh::launch_splat(x, y, z, m, count, *cam, *sp, workspace, L, image, (hipStream_t)stream);
 }
 
 lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
@@ -175,12 +174,7 @@ lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, cons
   lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L);
   if (s != LOD_OK) return s;
   if (workspace_bytes < D.total + L.total) return LOD_ENOMEM;
-  s = lodh::launch_lod_gather(*tree, node_ids, n_ids, workspace, D, (hipStream_t)stream);
-  if (s != LOD_OK) return s;
-  char *W = (char *)workspace;
-  return lodh::launch_splat((const float *)(W + D.x), (const float *)(W + D.y), (const float *)(W + D.z),
-                            (const float *)(W + D.m), D.max_points, (const uint64_t *)(W + D.count), *cam, *sp,
-                            W + D.total, L, image, tree->counts + 2, (hipStream_t)stream);
+  return lodh::launch_splat_lod(*tree, node_ids, n_ids, workspace, D, *cam, *sp, L, image, (hipStream_t)stream);
 }
 
 lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,

@@ -123,12 +123,21 @@ __global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, cons
   __syncthreads();
   const uint64_t tile = blockIdx.x;
   bool my_bad = false;
+  // all loads first (clamped indices: a predicated load is waited for alone)
+  float xs[ITEMS], ys[ITEMS], zs[ITEMS], ms[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint64_t e = min(tile * TILE + (uint64_t)i * TB + threadIdx.x, a.N - 1);
+    xs[i] = x[e]; ys[i] = y[e]; zs[i] = z[e]; ms[i] = m[e];
+  }
+#pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint64_t e = tile * TILE + (uint64_t)i * TB + threadIdx.x;
-    if (e >= a.N) break;
-    const PKey pk = particle_key(a, x[e], y[e], z[e], m[e], e);
-    my_bad |= !pk.ok;
-    atomicAdd(&hist[pk.key & 0xFFu], 1u);
+    if (e < a.N) {
+      const PKey pk = particle_key(a, xs[i], ys[i], zs[i], ms[i], e);
+      my_bad |= !pk.ok;
+      atomicAdd(&hist[pk.key & 0xFFu], 1u);
+    }
   }
   if (my_bad) bad = 1;
   __syncthreads();
@@ -144,11 +153,12 @@ __global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key
   for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
   __syncthreads();
   const uint64_t tile = blockIdx.x;
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint64_t e = tile * TILE + (uint64_t)i * TB + threadIdx.x;
-    if (e >= N) break;
-    atomicAdd(&hist[(key[e] >> shift) & 0xFFu], 1u);
-  }
+  uint32_t ks[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) ks[i] = key[min(tile * TILE + (uint64_t)i * TB + threadIdx.x, N - 1)];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (tile * TILE + (uint64_t)i * TB + threadIdx.x < N) atomicAdd(&hist[(ks[i] >> shift) & 0xFFu], 1u);
   __syncthreads();
   for (int i = threadIdx.x; i < RADIX; i += TB) thist[(uint64_t)i * n_tiles + tile] = hist[i];
 }
@@ -197,20 +207,20 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
   float mm[ROUNDS];
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) {
-    const uint64_t e = ebase + (uint64_t)r * WAVE;
-    const bool valid = e < N;
+    // clamped, unconditional loads; lanes past N are masked out below
+    const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
     if (FIRST) {
-      const float xe = valid ? in.x[e] : 0.0f, ye = valid ? in.y[e] : 0.0f, ze = valid ? in.z[e] : 0.0f;
-      mm[r] = valid ? in.m[e] : 0.0f;
+      const float xe = in.x[e], ye = in.y[e], ze = in.z[e];
+      mm[r] = in.m[e];
       const PKey pk = particle_key(a, xe, ye, ze, mm[r], e);
       kk[r] = pk.key;
       ll[r] = pk.lo;
-      ii[r] = (uint32_t)e;
+      ii[r] = (uint32_t)(ebase + (uint64_t)r * WAVE);
     } else {
-      kk[r] = valid ? in.key[e] : 0u;
-      ii[r] = valid ? in.idx[e] : 0u;
-      ll[r] = valid ? in.lo[e] : 0ull;
-      mm[r] = valid ? in.m[e] : 0.0f;
+      kk[r] = in.key[e];
+      ii[r] = in.idx[e];
+      ll[r] = in.lo[e];
+      mm[r] = in.m[e];
     }
   }
   for (int i = threadIdx.x; i < NW * RADIX; i += STB) (&wcnt[0][0])[i] = 0;
@@ -354,11 +364,22 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   const uint64_t base = (uint64_t)blockIdx.x * TILE;
   const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, N - base);
   const int sh = a.shift_rho;
-  for (int i = threadIdx.x; i < TILE + 2; i += TB) {
-    const int64_t e = (int64_t)base + i - 1;
-    uint32_t c = 0xFFFFFFFFu;
-    if (e >= 0 && (uint64_t)e < N && i <= (int)tile_n + 1) c = skey[e] >> sh;
-    cell[i] = c;
+  {
+    // clamped, unconditional loads first, then the selects
+    constexpr int CI = (TILE + 2 + TB - 1) / TB;
+    uint32_t kc[CI];
+#pragma unroll
+    for (int j = 0; j < CI; ++j) {
+      const int64_t e = (int64_t)base + j * TB + (int)threadIdx.x - 1;
+      kc[j] = skey[(uint64_t)min(max(e, (int64_t)0), (int64_t)N - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < CI; ++j) {
+      const int i = j * TB + (int)threadIdx.x;
+      const int64_t e = (int64_t)base + i - 1;
+      if (i < TILE + 2)
+        cell[i] = (e >= 0 && (uint64_t)e < N && i <= (int)tile_n + 1) ? (kc[j] >> sh) : 0xFFFFFFFFu;
+    }
   }
   __syncthreads();
   const bool has_prev = base > 0;
@@ -450,17 +471,27 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   }
   __syncthreads();
   const int sdb = 3 * a.D;
-#pragma unroll 4
+  uint32_t ids[ITEMS], snaps[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    ids[i] = sidx[min(base + (uint64_t)(i * TB + threadIdx.x), N - 1)];
+    snaps[i] = 0u;
+  }
+  if (a.n_snap > 1) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+      snaps[i] = (uint32_t)((uint64_t)skey[min(base + (uint64_t)(i * TB + threadIdx.x), N - 1)] >> sdb);
+  }
+#pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const int li = i * TB + threadIdx.x;
-    if (li >= (int)tile_n) break;
-    const uint64_t e = base + li;
-    const uint32_t w = wl[li];
-    const uint32_t k = skey[e];
-    const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)k >> sdb) : 0u;
-    const uint64_t U = particle_U(local_id(a, snap, sidx[e]), snap, a.seed);
-    w_out[e] = w;
-    kb_out[e] = (uint16_t)kbin(selection_key(U, w, a.alpha));
+    if (li < (int)tile_n) {
+      const uint64_t e = base + li;
+      const uint32_t w = wl[li];
+      const uint64_t U = particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed);
+      w_out[e] = w;
+      kb_out[e] = (uint16_t)kbin(selection_key(U, w, a.alpha));
+    }
   }
 }
 

@@ -30,8 +30,9 @@ void *workspace_view(void *ws, const BuildLayout &L, uint32_t which, uint64_t N,
 // Splat workspace layout.
 struct SplatLayout {
   uint32_t tiles_x, tiles_y, n_tiles;
+  uint32_t units, chunks;            // binning units (waves), 64 per chunk
   uint64_t max_points, max_pairs, max_slices;
-  size_t tile_count, tile_off, tile_cursor, slice_off, scan_tmp, counters;
+  size_t tile_count, tile_off, ucount, pchunk, slice_off, scan_tmp, counters;
   size_t bu, bv, bm, partial;
   size_t total;
 };
@@ -39,29 +40,28 @@ struct SplatLayout {
 constexpr int SPLAT_TS = 16;           // tile edge in pixels
 constexpr uint32_t SPLAT_MAX_TILES = 8192;
 constexpr uint32_t SPLAT_SLICE = 2048; // points per accumulation slice
+constexpr uint32_t SPLAT_MAX_CHUNKS = 32;
 
 lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_params &sp,
                         SplatLayout &L);
-// count_dev: if non-null the point count is read on the device and `count`
-// is only an upper bound.
 lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, uint64_t count,
-                        const uint64_t *count_dev, const lod_camera &cam, const splat_params &sp,
-                        void *ws, const SplatLayout &L, float *image, uint64_t *status_word,
+                        const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L, float *image,
                         hipStream_t st);
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m,
                                  uint64_t count, const lod_camera &cam, const splat_params &sp,
                                  const float *grad, float *gm, float *gx, float *gy, float *gz,
                                  hipStream_t st);
 
-// LOD render: decode the chosen nodes' points into workspace arrays.
+// LOD render: the chosen nodes' stored points, decoded inside the binning.
 struct LodDrawLayout {
   uint64_t max_ids, max_points;
-  size_t offs, scan_tmp, x, y, z, m, count;
+  size_t offs, scan_tmp, count;
   size_t total;
 };
 LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points);
-lod_status launch_lod_gather(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids,
-                             void *ws, const LodDrawLayout &L, hipStream_t st);
+lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
+                            const LodDrawLayout &D, const lod_camera &cam, const splat_params &sp,
+                            const SplatLayout &L, float *image, hipStream_t st);
 size_t decode_workspace(uint64_t node_capacity);
 lod_status launch_decode(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
                          float *x, float *y, float *z, float *m, uint64_t *n_points, void *ws, hipStream_t st);

@@ -2,15 +2,16 @@
 // gfx950 (rendering paragraph of arXiv:0811.2055: every point drawn as a
 // blob evaluated for each pixel it covers).
 //
-// Forward: points are binned to 16x16 pixel tiles (per-block LDS counts, one
-// global reservation per block and tile), each tile's list is cut into
-// slices of at most 2048 points, and one 256-thread block per slice
-// accumulates the blobs in an LDS tile with ds_add_f32 in chunks of 32
-// points; after each chunk every thread folds its pixel into a compensated
-// (Neumaier) float32 register sum.  A final pass adds a tile's slice
-// partials in slice order, again compensated.  Worst-case relative error per
-// pixel: 31 ulp from a chunk's atomic adds plus a few ulp from exp and the
-// products -- below 1e-5.
+// Forward: points are binned to 16x16 pixel tiles by a stable counting sort
+// (per-wave units, a count pass and a fill pass, ballot ranks inside the
+// wave), so a tile's pair list depends on the input alone.  Each list is cut
+// into slices of at most 2048 points; one 256-thread block per slice adds the
+// separable blobs to its 16x16 tile as rank-64 products on the matrix cores
+// (MFMA 16x16x4, float32) and folds the four wave partials of a pixel into a
+// compensated (Neumaier) float32 sum.  A final pass adds a tile's slice
+// partials in slice order, again compensated.  No floating-point atomics:
+// the image is bit-reproducible.  The LOD render feeds the binning straight
+// from the tree's 16-bit node-relative points, decoding them in registers.
 //
 // The screen position and pixel offsets follow a fixed float32 sequence with
 // no contraction (this file is compiled with -ffp-contract=off) so that the
@@ -31,8 +32,6 @@ namespace {
 
 constexpr int TS = lodh::SPLAT_TS;
 constexpr int PT = 256;            // threads per block
-constexpr int CHUNK = 32;          // points per LDS accumulation chunk
-constexpr int PER_POINT = PT / CHUNK;
 
 struct Cam {
   uint32_t proj, W, H;
@@ -83,115 +82,6 @@ __device__ __forceinline__ bool project(const Cam &c, float x, float y, float z,
   return true;
 }
 
-// Inclusive range [lo, hi] of pixel indices along one axis whose float32
-// offset fl(t - (i + 1/2)) lies within [-R, R], clipped to [0, size).  Every
-// candidate in the window is tested, as the definition states.
-__device__ __forceinline__ bool axis_range(const Cam &c, float t, uint32_t size, int &lo, int &hi) {
-  const float lim = c.R + 4.0f;
-  if (!(t > -lim && t < (float)size + lim)) return false;
-  const int f = (int)floorf(t);
-  lo = 1 << 30; hi = -(1 << 30);
-  for (int i = f - c.win; i <= f + c.win; ++i) {
-    if (i < 0 || i >= (int)size) continue;
-    const float o = t - ((float)i + 0.5f);
-    if (fabsf(o) <= c.R) { lo = min(lo, i); hi = max(hi, i); }
-  }
-  return lo <= hi;
-}
-
-__device__ __forceinline__ uint64_t load_count(uint64_t count, const uint64_t *count_dev) {
-  return count_dev ? min(count, *count_dev) : count;
-}
-
-// --- binning -----------------------------------------------------------------
-
-// Pass 1: per-tile pair counts.  Each block owns a contiguous chunk of points.
-__global__ __launch_bounds__(PT) void k_bin_count(const float *__restrict__ x, const float *__restrict__ y,
-                                                  const float *__restrict__ z, uint64_t count,
-                                                  const uint64_t *count_dev, Cam c,
-                                                  uint32_t *__restrict__ tile_count) {
-  extern __shared__ uint32_t lcount[];
-  const uint32_t nt = c.tiles_x * c.tiles_y;
-  for (uint32_t i = threadIdx.x; i < nt; i += PT) lcount[i] = 0;
-  __syncthreads();
-  const uint64_t n = load_count(count, count_dev);
-  const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const uint64_t b = (uint64_t)blockIdx.x * per, e = min(n, b + per);
-  for (uint64_t k = b + threadIdx.x; k < e; k += PT) {
-    float u, v, xc, yc, zc;
-    if (!project(c, x[k], y[k], z[k], u, v, xc, yc, zc)) continue;
-    int i0, i1, j0, j1;
-    if (!axis_range(c, u, c.W, i0, i1) || !axis_range(c, v, c.H, j0, j1)) continue;
-    for (int tj = j0 / TS; tj <= j1 / TS; ++tj)
-      for (int ti = i0 / TS; ti <= i1 / TS; ++ti) atomicAdd(&lcount[tj * c.tiles_x + ti], 1u);
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nt; i += PT)
-    if (lcount[i]) atomicAdd(&tile_count[i], lcount[i]);
-}
-
-// Pass 2: write (u, v, m) records into the tile lists.
-__global__ __launch_bounds__(PT) void k_bin_fill(const float *__restrict__ x, const float *__restrict__ y,
-                                                 const float *__restrict__ z, const float *__restrict__ m,
-                                                 uint64_t count, const uint64_t *count_dev, Cam c,
-                                                 uint32_t *__restrict__ tile_cursor,
-                                                 float *__restrict__ bu, float *__restrict__ bv,
-                                                 float *__restrict__ bm, uint64_t max_pairs,
-                                                 uint64_t *status) {
-  extern __shared__ uint32_t lds[];
-  const uint32_t nt = c.tiles_x * c.tiles_y;
-  uint32_t *lcount = lds;          // then: base of this block's reservation
-  uint32_t *lcur = lds + nt;
-  for (uint32_t i = threadIdx.x; i < nt; i += PT) { lcount[i] = 0; lcur[i] = 0; }
-  __syncthreads();
-  const uint64_t n = load_count(count, count_dev);
-  const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const uint64_t b = (uint64_t)blockIdx.x * per, e = min(n, b + per);
-  for (uint64_t k = b + threadIdx.x; k < e; k += PT) {
-    float u, v, xc, yc, zc;
-    if (!project(c, x[k], y[k], z[k], u, v, xc, yc, zc)) continue;
-    int i0, i1, j0, j1;
-    if (!axis_range(c, u, c.W, i0, i1) || !axis_range(c, v, c.H, j0, j1)) continue;
-    for (int tj = j0 / TS; tj <= j1 / TS; ++tj)
-      for (int ti = i0 / TS; ti <= i1 / TS; ++ti) atomicAdd(&lcount[tj * c.tiles_x + ti], 1u);
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nt; i += PT) {
-    const uint32_t cnt = lcount[i];
-    lcount[i] = cnt ? atomicAdd(&tile_cursor[i], cnt) : 0u;
-  }
-  __syncthreads();
-  for (uint64_t k = b + threadIdx.x; k < e; k += PT) {
-    float u, v, xc, yc, zc;
-    if (!project(c, x[k], y[k], z[k], u, v, xc, yc, zc)) continue;
-    int i0, i1, j0, j1;
-    if (!axis_range(c, u, c.W, i0, i1) || !axis_range(c, v, c.H, j0, j1)) continue;
-    const float mk = m[k];
-    for (int tj = j0 / TS; tj <= j1 / TS; ++tj)
-      for (int ti = i0 / TS; ti <= i1 / TS; ++ti) {
-        const uint32_t t = tj * c.tiles_x + ti;
-        const uint64_t slot = (uint64_t)lcount[t] + atomicAdd(&lcur[t], 1u);
-        if (slot < max_pairs) { bu[slot] = u; bv[slot] = v; bm[slot] = mk; }
-        else atomicOr((unsigned long long *)status, (unsigned long long)LOD_STATUS_CAPACITY);
-      }
-  }
-}
-
-// slices per tile
-__global__ void k_slice_count(const uint32_t *__restrict__ tile_count, uint32_t nt, uint32_t *__restrict__ ns) {
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x)
-    ns[t] = (tile_count[t] + lodh::SPLAT_SLICE - 1) / lodh::SPLAT_SLICE;
-}
-
-__device__ __forceinline__ void neumaier(float &s, float &c, float x) {
-  const float t = s + x;
-  if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
-  else c += (x - t) + s;
-  s = t;
-}
-
-// --- accumulation --------------------------------------------------------------
-
 // First and last index in [lo_clip, hi_clip] whose float32 offset
 // fl(t - (i + 1/2)) lies in [-R, R].  The offset is non-increasing in i, so
 // the set is an interval; a float estimate is corrected by exact tests.
@@ -208,6 +98,322 @@ __device__ __forceinline__ bool clip_range(float t, float R, int lo_clip, int hi
   hi = min(b, hi_clip);
   return lo <= hi;
 }
+
+// Inclusive range [lo, hi] of pixel indices along one axis whose float32
+// offset fl(t - (i + 1/2)) lies within [-R, R], clipped to [0, size).
+__device__ __forceinline__ bool axis_range(const Cam &c, float t, uint32_t size, int &lo, int &hi) {
+  const float lim = c.R + 4.0f;
+  if (!(t > -lim && t < (float)size + lim)) return false;
+  return clip_range(t, c.R, 0, (int)size - 1, lo, hi);
+}
+
+__device__ __forceinline__ uint64_t load_count(uint64_t count, const uint64_t *count_dev) {
+  return count_dev ? min(count, *count_dev) : count;
+}
+
+// --- binning -----------------------------------------------------------------
+//
+// Points are binned to 16x16 pixel tiles by a stable counting sort, so that
+// every tile's pair list -- and with it the image -- is a function of the
+// input alone.  The points are cut into U = 64 C contiguous ranges ("units"),
+// one wave each.  Pass 1 counts each unit's pairs per tile into row u of a
+// [U][tiles] table; two column scans (within chunks of 64 units, then over the
+// C chunks) and a scan over tiles give every (tile, unit) its slot range.
+// Pass 2 re-derives the pairs in the same order (64-point rounds, then a
+// point's tiles row by row, then lane) and ranks equal tiles inside the wave
+// with ballots, so the list of a tile is ordered by (unit, round, tile index
+// within the point, lane).
+
+constexpr int BW = 64;              // binning block: one wave, one unit
+constexpr int BR = 8;               // rounds of 64 points loaded together
+
+// decoded float32 coordinate of a stored point (cell coordinate c at depth d,
+// 16-bit offset q): centre of the quantisation cell, exact in float32
+__device__ __forceinline__ float decode_coord(uint32_t c, uint32_t q, int d) {
+  return (float)(2u * ((c << 16) + q) + 1u) * ldexpf(1.0f, -(d + 17));
+}
+
+// Point sources.  A wave first resolves the addresses of its next BR rounds of
+// points (resolve + end_round, in round order), then issues all their loads
+// at once (fetch), so one memory latency covers BR rounds.
+
+// raw float32 arrays
+struct RawSrc {
+  const float *x, *y, *z, *m;
+  uint64_t n;
+  struct Addr {
+    uint64_t k;
+  };
+  struct Cursor {
+    uint64_t last;      // a valid index: loads are unconditional (a predicated
+                        // load would be waited for on its own)
+    __device__ void begin(const RawSrc &, uint64_t b, uint64_t e) { last = e - 1; }
+    __device__ __forceinline__ Addr resolve(const RawSrc &, uint64_t k, bool valid) {
+      return Addr{valid ? k : last};
+    }
+    __device__ void end_round(const RawSrc &) {}
+    __device__ __forceinline__ void fetch(const RawSrc &s, const Addr &a, bool, float &px, float &py,
+                                          float &pz, float &pm) const {
+      px = s.x[a.k]; py = s.y[a.k]; pz = s.z[a.k]; pm = s.m[a.k];
+    }
+  };
+  __device__ uint64_t count() const { return n; }
+};
+
+// The stored points of a list of tree nodes, decoded on the fly.  offs is the
+// exclusive scan of the nodes' point counts; the wave keeps the node holding
+// its current point in registers and walks offs per lane when a round crosses
+// into later nodes.
+struct TreeSrc {
+  lod_tree t;
+  const uint32_t *ids;
+  const uint64_t *offs;
+  const uint64_t *n_ids;
+  uint64_t max_ids;
+  const uint64_t *total;     // points to draw (device)
+  struct Addr {
+    uint64_t sidx;
+    uint32_t cx, cy, cz;
+    int d;
+  };
+  struct Cursor {
+    uint64_t c, ob, oe, pb, far_c;
+    uint32_t cx, cy, cz;
+    int d;
+    __device__ __forceinline__ void set(const TreeSrc &s, uint64_t cc) {
+      c = cc;
+      const uint32_t v = s.ids[cc];
+      ob = s.offs[cc]; oe = s.offs[cc + 1];
+      d = s.t.depth[v];
+      const uint64_t pfx = s.t.prefix[v];
+      const uint32_t cell = d ? (uint32_t)(pfx & ((1ull << (3 * d)) - 1)) : 0u;
+      cx = compact3(cell); cy = compact3(cell >> 1); cz = compact3(cell >> 2);
+      pb = s.t.pt_begin[v];
+      far_c = cc;
+    }
+    __device__ void begin(const TreeSrc &s, uint64_t b, uint64_t) {
+      // the last node whose offset is <= b; it holds point b (b < total)
+      uint64_t lo = 0, hi = min(*s.n_ids, s.max_ids);
+      while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (s.offs[mid] <= b) lo = mid; else hi = mid;
+      }
+      set(s, lo);
+    }
+    __device__ __forceinline__ Addr resolve(const TreeSrc &s, uint64_t k, bool valid) {
+      // invalid lanes load the cached node's first point (in bounds, unused)
+      Addr a{pb, cx, cy, cz, d};
+      if (!valid) return a;
+      if (k < oe) {
+        a.sidx = pb + (k - ob);
+        return a;
+      }
+      uint64_t cl = c + 1;
+      while (s.offs[cl + 1] <= k) ++cl;
+      far_c = max(far_c, cl);
+      const uint32_t v = s.ids[cl];
+      a.d = s.t.depth[v];
+      const uint64_t pfx = s.t.prefix[v];
+      const uint32_t cell = a.d ? (uint32_t)(pfx & ((1ull << (3 * a.d)) - 1)) : 0u;
+      a.cx = compact3(cell); a.cy = compact3(cell >> 1); a.cz = compact3(cell >> 2);
+      a.sidx = s.t.pt_begin[v] + (k - s.offs[cl]);
+      return a;
+    }
+    // move the cached node to the furthest node any lane reached
+    __device__ void end_round(const TreeSrc &s) {
+      if (!__ballot(far_c != c)) return;      // every lane stayed in the cached node
+      uint64_t f = far_c;
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) f = max(f, (uint64_t)__shfl_xor(f, o, WAVE));
+      if (f != c) set(s, f);
+    }
+    __device__ __forceinline__ void fetch(const TreeSrc &s, const Addr &a, bool, float &px, float &py,
+                                          float &pz, float &pm) const {
+      const uint32_t qx = s.t.qx[a.sidx], qy = s.t.qy[a.sidx], qz = s.t.qz[a.sidx];
+      pm = s.t.pt_mass[a.sidx];
+      px = decode_coord(a.cx, qx, a.d);
+      py = decode_coord(a.cy, qy, a.d);
+      pz = decode_coord(a.cz, qz, a.d);
+    }
+  };
+  __device__ uint64_t count() const { return *total; }
+};
+
+// One point's screen position and tile rectangle (ntx = nty = 0: not drawn).
+struct Blob {
+  float u, v, m;
+  int tx0, ty0, ntx, nty;
+};
+
+__device__ __forceinline__ Blob make_blob(const Cam &c, bool valid, float px, float py, float pz, float pm) {
+  Blob b{0.0f, 0.0f, pm, 0, 0, 0, 0};
+  if (!valid) return b;
+  float xc, yc, zc;
+  if (!project(c, px, py, pz, b.u, b.v, xc, yc, zc)) return b;
+  int i0, i1, j0, j1;
+  if (!axis_range(c, b.u, c.W, i0, i1) || !axis_range(c, b.v, c.H, j0, j1)) return b;
+  b.tx0 = i0 / TS; b.ty0 = j0 / TS;
+  b.ntx = i1 / TS - b.tx0 + 1;
+  b.nty = j1 / TS - b.ty0 + 1;
+  return b;
+}
+
+// Lanes of the wave holding the same tile t as this lane (among lanes with
+// `has`).  Spatially coherent points share few tiles, so groups are peeled
+// off by their lowest lane first; after four groups the rest is matched bit
+// by bit.  The grouping, not the method, decides the ranks.
+__device__ __forceinline__ uint64_t group_of(uint32_t t, bool has, int nbits) {
+  uint64_t pending = __ballot(has);
+  uint64_t mine = 0;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    if (!pending) return mine;
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t tl = __builtin_amdgcn_readlane(t, leader);
+    const uint64_t grp = __ballot(has && t == tl);
+    if (has && t == tl) mine = grp;
+    pending &= ~grp;
+  }
+  if (!pending) return mine;
+  const bool rest = ((pending >> (threadIdx.x & (WAVE - 1))) & 1ull) != 0;
+  uint64_t peers = pending;
+  for (int b = 0; b < nbits; ++b) {
+    const uint64_t bal = __ballot((t >> b) & 1u);
+    peers &= ((t >> b) & 1u) ? bal : ~bal;
+  }
+  return rest ? peers : mine;
+}
+
+template <class Src, bool FILL>
+__device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, int nbits,
+                                         uint32_t *lc, float *__restrict__ bu, float *__restrict__ bv,
+                                         float *__restrict__ bm, uint64_t max_pairs, uint64_t *status) {
+  const int lane = threadIdx.x;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+  const uint64_t n = src.count();
+  const uint64_t per = (n + units - 1) / units;
+  const uint64_t b = (uint64_t)blockIdx.x * per, e = min(n, b + per);
+  if (b >= e) return;
+  typename Src::Cursor cur;
+  cur.begin(src, b, e);
+  for (uint64_t k0 = b; k0 < e; k0 += (uint64_t)BR * WAVE) {
+    typename Src::Addr ad[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const uint64_t k = k0 + (uint64_t)r * WAVE + lane;
+      ad[r] = cur.resolve(src, k, k < e);
+      cur.end_round(src);
+    }
+    float px[BR], py[BR], pz[BR], pm[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const uint64_t k = k0 + (uint64_t)r * WAVE + lane;
+      cur.fetch(src, ad[r], k < e, px[r], py[r], pz[r], pm[r]);
+    }
+    Blob blobs[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+      blobs[r] = make_blob(c, k0 + (uint64_t)r * WAVE + lane < e, px[r], py[r], pz[r], pm[r]);
+    // pairs in the order (round, tile row, tile column, lane)
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const Blob &bl = blobs[r];
+      for (int dy = 0; __ballot(dy < bl.nty); ++dy) {
+        for (int dx = 0; __ballot(dy < bl.nty && dx < bl.ntx); ++dx) {
+          const bool has = dy < bl.nty && dx < bl.ntx;
+          const uint32_t t = has ? (uint32_t)((bl.ty0 + dy) * (int)c.tiles_x + bl.tx0 + dx) : 0u;
+          const uint64_t peers = group_of(t, has, nbits);
+          const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+          const uint32_t cnt = (uint32_t)__popcll(peers);
+          const uint32_t old = has ? lc[t] : 0u;
+          if (has && below == 0) lc[t] = old + cnt;
+          if (FILL && has) {
+            const uint64_t slot = (uint64_t)old + below;
+            if (slot < max_pairs) { bu[slot] = bl.u; bv[slot] = bl.v; bm[slot] = bl.m; }
+            else atomicOr((unsigned long long *)status, (unsigned long long)LOD_STATUS_CAPACITY);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Pass 1: row u of the [U][tiles] count table.
+template <class Src>
+__global__ __launch_bounds__(BW) void k_bin_count(Src src, Cam c, uint32_t units, int nbits,
+                                                  uint32_t *__restrict__ ucount) {
+  extern __shared__ uint32_t lc[];
+  const uint32_t nt = c.tiles_x * c.tiles_y;
+  for (uint32_t i = threadIdx.x; i < nt; i += BW) lc[i] = 0;
+  __syncthreads();
+  bin_unit<Src, false>(src, c, units, nbits, lc, nullptr, nullptr, nullptr, 0, nullptr);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nt; i += BW) ucount[(uint64_t)blockIdx.x * nt + i] = lc[i];
+}
+
+// Column scans of the count table: exclusive prefix over the 64 units of each
+// chunk (in place) and the chunk totals.
+__global__ void k_bin_colscan(uint32_t *__restrict__ ucount, uint32_t nt, uint32_t *__restrict__ pchunk) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t ch = blockIdx.y;
+  if (t >= nt) return;
+  uint32_t run = 0;
+  for (uint32_t u = ch * 64; u < ch * 64 + 64; ++u) {
+    const uint64_t i = (uint64_t)u * nt + t;
+    const uint32_t v = ucount[i];
+    ucount[i] = run;
+    run += v;
+  }
+  pchunk[(uint64_t)ch * nt + t] = run;
+}
+
+// exclusive prefix over chunks (in place) and the tile totals
+__global__ void k_bin_chunkscan(uint32_t *__restrict__ pchunk, uint32_t nt, uint32_t chunks,
+                                uint32_t *__restrict__ tile_count) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  uint32_t run = 0;
+  for (uint32_t ch = 0; ch < chunks; ++ch) {
+    const uint64_t i = (uint64_t)ch * nt + t;
+    const uint32_t v = pchunk[i];
+    pchunk[i] = run;
+    run += v;
+  }
+  tile_count[t] = run;
+}
+
+// Pass 2: write the (u, v, m) records; the unit's cursor for tile t starts at
+// tile_off[t] + (pairs of earlier chunks) + (pairs of earlier units in its chunk).
+template <class Src>
+__global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units, int nbits,
+                                                 const uint32_t *__restrict__ ucount,
+                                                 const uint32_t *__restrict__ pchunk,
+                                                 const uint32_t *__restrict__ tile_off,
+                                                 float *__restrict__ bu, float *__restrict__ bv,
+                                                 float *__restrict__ bm, uint64_t max_pairs, uint64_t *status) {
+  extern __shared__ uint32_t lc[];
+  const uint32_t nt = c.tiles_x * c.tiles_y;
+  const uint32_t ch = blockIdx.x / 64;
+  for (uint32_t i = threadIdx.x; i < nt; i += BW)
+    lc[i] = tile_off[i] + pchunk[(uint64_t)ch * nt + i] + ucount[(uint64_t)blockIdx.x * nt + i];
+  __syncthreads();
+  bin_unit<Src, true>(src, c, units, nbits, lc, bu, bv, bm, max_pairs, status);
+}
+
+// slices per tile
+__global__ void k_slice_count(const uint32_t *__restrict__ tile_count, uint32_t nt, uint32_t *__restrict__ ns) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x)
+    ns[t] = (tile_count[t] + lodh::SPLAT_SLICE - 1) / lodh::SPLAT_SLICE;
+}
+
+__device__ __forceinline__ void neumaier(float &s, float &c, float x) {
+  const float t = s + x;
+  if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+// --- accumulation --------------------------------------------------------------
 
 // One block per slice.  The blob is separable, so a chunk of 256 points adds
 // Gy^T Gx to the 16x16 tile, with Gx[k][i] = exp(-ox^2/2s^2) and Gy[k][j] =
@@ -407,14 +613,13 @@ __global__ __launch_bounds__(PT) void k_lod_decode(const lod_tree t, const uint3
     const uint64_t pb = t.pt_begin[v];
     const uint32_t pc = t.pt_count[v];
     const uint64_t ob = offs[k];
-    const float scale = ldexpf(1.0f, -(d + 17));
     for (uint32_t j = threadIdx.x; j < pc; j += PT) {
       const uint64_t o = ob + j;
       if (o >= max_points) break;
       const uint64_t s = pb + j;
-      x[o] = (float)(2u * ((cx << 16) + t.qx[s]) + 1u) * scale;
-      y[o] = (float)(2u * ((cy << 16) + t.qy[s]) + 1u) * scale;
-      z[o] = (float)(2u * ((cz << 16) + t.qz[s]) + 1u) * scale;
+      x[o] = decode_coord(cx, t.qx[s], d);
+      y[o] = decode_coord(cy, t.qy[s], d);
+      z[o] = decode_coord(cz, t.qz[s], d);
       m[o] = t.pt_mass[s];
     }
   }
@@ -512,9 +717,13 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   L.max_slices = nt + L.max_pairs / SPLAT_SLICE + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  // units: 64 per chunk, one chunk per 2^18 points, at most 32 chunks
+  L.chunks = (uint32_t)std::min<uint64_t>(SPLAT_MAX_CHUNKS, std::max<uint64_t>(1, (max_points + (1u << 18) - 1) >> 18));
+  L.units = 64 * L.chunks;
   L.tile_count = take(4 * (nt + 1));
   L.tile_off = take(4 * (nt + 1));
-  L.tile_cursor = take(4 * (nt + 1));
+  L.ucount = take(4 * (size_t)L.units * nt);
+  L.pchunk = take(4 * (size_t)L.chunks * nt);
   L.slice_off = take(4 * (nt + 1));
   L.scan_tmp = take(4 * scan_tmp_elems<uint32_t>(nt + 1));
   L.counters = take(64);
@@ -526,48 +735,56 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   return LOD_OK;
 }
 
-lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, uint64_t count,
-                        const uint64_t *count_dev, const lod_camera &cam, const splat_params &sp, void *ws,
-                        const SplatLayout &L, float *image, uint64_t *status_word, hipStream_t st) {
+template <class Src>
+static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &cam, const splat_params &sp, void *ws,
+                                   const SplatLayout &L, float *image, uint64_t *status_word, hipStream_t st) {
   char *W = (char *)ws;
   Cam c = make_cam(cam, sp, &L);
   const uint32_t nt = L.n_tiles;
   uint32_t *tcount = (uint32_t *)(W + L.tile_count);
   uint32_t *toff = (uint32_t *)(W + L.tile_off);
-  uint32_t *tcur = (uint32_t *)(W + L.tile_cursor);
+  uint32_t *ucount = (uint32_t *)(W + L.ucount);
+  uint32_t *pchunk = (uint32_t *)(W + L.pchunk);
   uint32_t *soff = (uint32_t *)(W + L.slice_off);
   uint32_t *stmp = (uint32_t *)(W + L.scan_tmp);
   uint64_t *ctr = (uint64_t *)(W + L.counters);
   uint64_t *status = status_word ? status_word : ctr;
   float *bu = (float *)(W + L.bu), *bv = (float *)(W + L.bv), *bm = (float *)(W + L.bm);
   float *partial = (float *)(W + L.partial);
+  int nbits = 0;
+  while ((1u << nbits) < nt) ++nbits;
   fill_u32(tcount, nt + 1, 0, st);
   if (!status_word) fill_u64(ctr, 1, 0, st);
-  const uint64_t pts = count;
-  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(2048, (pts + 1023) / 1024));
-  const size_t lds1 = 4 * (size_t)nt, lds2 = 8 * (size_t)nt;
-  if (pts) {
-    LOD_LAUNCH(k_bin_count, dim3(grid), dim3(PT), lds1, st, x, y, z, count, count_dev, c, tcount);
+  const size_t lds = 4 * (size_t)nt;
+  if (any) {
+    LOD_LAUNCH(k_bin_count<Src>, dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount);
+    LOD_LAUNCH(k_bin_colscan, dim3((nt + 255) / 256, L.chunks), dim3(256), 0, st, ucount, nt, pchunk);
+    LOD_LAUNCH(k_bin_chunkscan, dim3((nt + 255) / 256), dim3(256), 0, st, pchunk, nt, L.chunks, tcount);
   }
-  // tile offsets (exclusive), cursor copy, slices
+  // tile offsets (exclusive; toff[nt] = pairs), slices
   LOD_LAUNCH(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, tcount, toff, (uint64_t)nt + 1);
   device_scan<uint32_t>(toff, nt + 1, stmp, st);
-  LOD_LAUNCH(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, toff, tcur, (uint64_t)nt + 1);
-  if (pts) {
-    LOD_LAUNCH(k_bin_fill, dim3(grid), dim3(PT), lds2, st, x, y, z, m, count, count_dev, c, tcur, bu, bv,
-                       bm, L.max_pairs, status);
+  if (any) {
+    LOD_LAUNCH(k_bin_fill<Src>, dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount, pchunk, toff,
+               bu, bv, bm, L.max_pairs, status);
   }
   LOD_LAUNCH(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
   fill_u32(soff + nt, 1, 0, st);
   device_scan<uint32_t>(soff, nt + 1, stmp, st);
   const unsigned agrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, L.max_slices));
-  if (pts) {
+  if (any) {
     LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, toff, tcount, soff, nt, bu, bv, bm, c, partial,
-                       L.max_slices, L.max_pairs);
+               L.max_slices, L.max_pairs);
   }
   LOD_LAUNCH(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial, c, image,
-                     L.max_slices);
+             L.max_slices);
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+}
+
+lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, uint64_t count,
+                        const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L, float *image,
+                        hipStream_t st) {
+  return launch_splat_src(RawSrc{x, y, z, m, count}, count > 0, cam, sp, ws, L, image, nullptr, st);
 }
 
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m, uint64_t count,
@@ -588,28 +805,23 @@ LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points) {
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   L.offs = take(8 * (L.max_ids + 1));
   L.scan_tmp = take(8 * scan_tmp_elems<uint64_t>(L.max_ids + 1));
-  L.x = take(4 * L.max_points);
-  L.y = take(4 * L.max_points);
-  L.z = take(4 * L.max_points);
-  L.m = take(4 * L.max_points);
   L.count = take(64);
   L.total = off;
   return L;
 }
 
-lod_status launch_lod_gather(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
-                             const LodDrawLayout &L, hipStream_t st) {
+lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
+                            const LodDrawLayout &D, const lod_camera &cam, const splat_params &sp,
+                            const SplatLayout &L, float *image, hipStream_t st) {
   char *W = (char *)ws;
-  uint64_t *offs = (uint64_t *)(W + L.offs);
-  uint64_t *cnt = (uint64_t *)(W + L.count);
-  const unsigned g = (unsigned)std::min<uint64_t>(4096, (L.max_ids + 255) / 256);
-  LOD_LAUNCH(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, L.max_ids, offs);
-  device_scan<uint64_t>(offs, L.max_ids + 1, (uint64_t *)(W + L.scan_tmp), st);
-  LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, L.max_ids, L.max_points, cnt);
-  const unsigned dg = (unsigned)std::min<uint64_t>(16384, L.max_ids);
-  LOD_LAUNCH(k_lod_decode, dim3(dg), dim3(PT), 0, st, tree, node_ids, n_ids, L.max_ids, offs, L.max_points,
-                     (float *)(W + L.x), (float *)(W + L.y), (float *)(W + L.z), (float *)(W + L.m));
-  return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+  uint64_t *offs = (uint64_t *)(W + D.offs);
+  uint64_t *cnt = (uint64_t *)(W + D.count);
+  const unsigned g = (unsigned)std::min<uint64_t>(4096, (D.max_ids + 256) / 256);
+  LOD_LAUNCH(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, D.max_ids, offs);
+  device_scan<uint64_t>(offs, D.max_ids + 1, (uint64_t *)(W + D.scan_tmp), st);
+  LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, D.max_ids, D.max_points, cnt);
+  const TreeSrc src{tree, node_ids, offs, n_ids, D.max_ids, cnt};
+  return launch_splat_src(src, true, cam, sp, W + D.total, L, image, tree.counts + 2, st);
 }
 
 size_t decode_workspace(uint64_t node_capacity) {

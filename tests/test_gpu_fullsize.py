@@ -87,7 +87,9 @@ def test_sampled_nodes_match_direct_definition(c3):
     depth = h["depth"].astype(np.int64)
     rng = np.random.default_rng(1)
     picks = []
-    for dd in (1, 2, 3, 4, 5, 6, 7, 8):
+    d1 = np.nonzero((depth == 1) & (counts > n))[0]
+    picks.append(int(d1[np.argmin(counts[d1])]))       # the smallest depth-1 internal node
+    for dd in (2, 3, 4, 5, 6, 7, 8):
         cand = np.nonzero((depth == dd) & (counts > n) & (counts < 4_000_000))[0]
         if len(cand):
             picks.append(int(rng.choice(cand)))

@@ -123,3 +123,54 @@ def test_lod_render_matches_oracle():
         refimg = osplat.render(ocam, px, py, pz, pm)
         err, zeros_ok = image_rel_err(img, refimg)
         assert zeros_ok and err <= TOL, (name, err)
+
+
+def test_splat_bit_reproducible():
+    """Pair lists are built by a stable counting sort, so repeated renders
+    (with different workspace contents) give identical bits."""
+    import torch
+    s = synth.small_clustered(600000, 72)
+    d = to_dev(s)
+    for cam in (lib.Camera.ortho(512, 384), lib.Camera.look_at((0.5, 0.45, -0.6), (0.5, 0.5, 0.5), 300, 200)):
+        ws = lib.splat_workspace_bytes(s.n, cam)
+        w1 = torch.zeros(ws, dtype=torch.uint8, device="cuda")
+        w2 = torch.full((ws,), 0xA5, dtype=torch.uint8, device="cuda")
+        a = lib.splat(*d, cam, workspace=w1).cpu().numpy()
+        b = lib.splat(*d, cam, workspace=w2).cpu().numpy()
+        c = lib.splat(*d, cam, workspace=w1).cpu().numpy()
+        assert np.array_equal(a.view(np.int32), b.view(np.int32))
+        assert np.array_equal(a.view(np.int32), c.view(np.int32))
+
+
+@pytest.mark.parametrize("n", [16, 64, 700])
+def test_lod_render_equals_render_of_decoded_points(n):
+    """The LOD render decodes the stored points inside the binning; it must
+    equal, bit for bit, the plain render of the decoded points (same point
+    sequence, same units), also with invalid ids in the list and when
+    max_points truncates the sequence."""
+    import torch
+    s = synth.small_clustered(120000, 73)
+    tree = lib.build(*to_dev(s), lib.BuildParams(n=n, max_depth=6, seed=1))
+    h = tree.host()
+    cam = lib.Camera.look_at((0.52, 0.47, -0.5), (0.5, 0.5, 0.5), 256, 192, fov_deg=55.0)
+    ids, nsel = lib.select_nodes(tree, cam, 1.0, n)
+    k = int(lib._to_numpy(nsel)[0])
+    chosen = lib._to_numpy(ids[:k]).astype(np.int64)
+    # interleave invalid ids (beyond the node count)
+    mixed = []
+    for i, v in enumerate(chosen):
+        mixed.append(v)
+        if i % 5 == 0:
+            mixed.append(h["n_nodes"] + 3 + i)
+    mixed = np.array(mixed, dtype=np.int64)
+    total = int(h["pt_count"][chosen].astype(np.int64).sum())
+    for lst in (chosen, mixed):
+        idt = torch.from_numpy(lst.astype(np.int32)).cuda().view(torch.uint32)
+        nid = torch.tensor([len(lst)], dtype=torch.int64).cuda().view(torch.uint64)
+        for cap in (total, total // 3 + 1):
+            img = lib.splat_lod(tree, idt, nid, cap, cam).cpu().numpy()
+            x, y, z, m, cnt = lib.decode_nodes(tree, idt, nid, cap)
+            c = int(lib._to_numpy(cnt)[0])
+            assert c == min(cap, total)
+            ref = lib.splat(x[:c], y[:c], z[:c], m[:c], cam).cpu().numpy()
+            assert np.array_equal(img.view(np.int32), ref.view(np.int32)), (n, len(lst), cap)
