@@ -36,7 +36,16 @@ namespace {
 
 constexpr int TB = 256;          // threads per block for streaming kernels
 constexpr int ITEMS = 16;        // elements per thread
-constexpr int TILE = TB * ITEMS; // elements per tile (4096)
+constexpr int TILE = TB * ITEMS; // elements per density tile (4096)
+
+// radix sort tiles: scatter blocks of STB threads x SITEMS elements; the
+// histogram kernels (TB threads) cover the same STILE elements per block
+constexpr int STB = 1024;                    // scatter threads per block
+constexpr int SITEMS = 8;                    // elements per scatter thread
+constexpr int STILE = STB * SITEMS;          // elements per sort tile
+constexpr int HITEMS = STILE / TB;           // elements per histogram thread
+constexpr int HCHUNK = 8;                    // loads issued together in keygen (twice that in upsweep)
+static_assert(HITEMS % (2 * HCHUNK) == 0, "histogram chunks must divide the tile");
 constexpr int RADIX = 256;
 constexpr uint32_t STATUS_INTERNAL = 8u;
 
@@ -124,19 +133,21 @@ __global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, cons
   const uint64_t tile = blockIdx.x;
   bool my_bad = false;
   // all loads first (clamped indices: a predicated load is waited for alone)
-  float xs[ITEMS], ys[ITEMS], zs[ITEMS], ms[ITEMS];
+  for (int c = 0; c < HITEMS; c += HCHUNK) {
+    float xs[HCHUNK], ys[HCHUNK], zs[HCHUNK], ms[HCHUNK];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint64_t e = min(tile * TILE + (uint64_t)i * TB + threadIdx.x, a.N - 1);
-    xs[i] = x[e]; ys[i] = y[e]; zs[i] = z[e]; ms[i] = m[e];
-  }
+    for (int i = 0; i < HCHUNK; ++i) {
+      const uint64_t e = min(tile * STILE + (uint64_t)(c + i) * TB + threadIdx.x, a.N - 1);
+      xs[i] = x[e]; ys[i] = y[e]; zs[i] = z[e]; ms[i] = m[e];
+    }
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint64_t e = tile * TILE + (uint64_t)i * TB + threadIdx.x;
-    if (e < a.N) {
-      const PKey pk = particle_key(a, xs[i], ys[i], zs[i], ms[i], e);
-      my_bad |= !pk.ok;
-      atomicAdd(&hist[pk.key & 0xFFu], 1u);
+    for (int i = 0; i < HCHUNK; ++i) {
+      const uint64_t e = tile * STILE + (uint64_t)(c + i) * TB + threadIdx.x;
+      if (e < a.N) {
+        const PKey pk = particle_key(a, xs[i], ys[i], zs[i], ms[i], e);
+        my_bad |= !pk.ok;
+        atomicAdd(&hist[pk.key & 0xFFu], 1u);
+      }
     }
   }
   if (my_bad) bad = 1;
@@ -153,25 +164,27 @@ __global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key
   for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
   __syncthreads();
   const uint64_t tile = blockIdx.x;
-  uint32_t ks[ITEMS];
+  for (int c = 0; c < HITEMS; c += 2 * HCHUNK) {
+    uint32_t ks[2 * HCHUNK];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) ks[i] = key[min(tile * TILE + (uint64_t)i * TB + threadIdx.x, N - 1)];
+    for (int i = 0; i < 2 * HCHUNK; ++i)
+      ks[i] = key[min(tile * STILE + (uint64_t)(c + i) * TB + threadIdx.x, N - 1)];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i)
-    if (tile * TILE + (uint64_t)i * TB + threadIdx.x < N) atomicAdd(&hist[(ks[i] >> shift) & 0xFFu], 1u);
+    for (int i = 0; i < 2 * HCHUNK; ++i)
+      if (tile * STILE + (uint64_t)(c + i) * TB + threadIdx.x < N) atomicAdd(&hist[(ks[i] >> shift) & 0xFFu], 1u);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < RADIX; i += TB) thist[(uint64_t)i * n_tiles + tile] = hist[i];
 }
 
-// Stable scatter of one LSD pass over 4096-element tiles, 512 threads.  Wave
-// w of the block owns tile elements [w*512, (w+1)*512); in round r lane l holds
-// element w*512 + r*64 + l, so element order is (w, r, l).  All loads of a
-// thread's 8 elements are issued first, so their latency overlaps the ranking.
+// Stable scatter of one LSD pass over STILE-element tiles, STB threads.  Wave
+// w of the block owns tile elements [w*P, (w+1)*P) with P = STILE / waves; in
+// round r lane l holds element w*P + r*64 + l, so element order is (w, r, l).
+// All loads of a thread's SITEMS elements are issued first, so their latency
+// overlaps the ranking.
 // Ranks within a wave come from 8 ballots (the lanes sharing the digit) and a
 // wave-private LDS counter per digit; the tile is staged in LDS in digit order
 // so that the global writes of each digit run are contiguous.
-constexpr int STB = 512;                     // scatter threads per block
-constexpr int SITEMS = TILE / STB;           // 8 elements per thread
 
 // FIRST: the input is the particles themselves (x, y, z, m with ids implicit);
 // keys and fractions come from particle_key.  Otherwise (key, id, fraction,
@@ -188,19 +201,19 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
                                                  uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
                                                  uint64_t *__restrict__ lo_out, float *__restrict__ m_out) {
   const uint64_t N = a.N;
-  constexpr int NW = STB / WAVE;              // 8 waves
-  constexpr int PER_WAVE = TILE / NW;         // 512
+  constexpr int NW = STB / WAVE;              // waves per block
+  constexpr int PER_WAVE = STILE / NW;
   constexpr int ROUNDS = PER_WAVE / WAVE;     // 8
   __shared__ uint32_t wcnt[NW][RADIX];
   __shared__ uint32_t bin_start[RADIX];       // tile-local start of each digit
   __shared__ uint32_t gofs[RADIX];            // global start of this tile's digit run
-  __shared__ uint64_t stage[TILE];
+  __shared__ uint64_t stage[STILE];
   __shared__ uint32_t tmp[STB / WAVE + 1];
 
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x / WAVE;
   const uint64_t tile = blockIdx.x;
-  const uint64_t tbase = tile * TILE;
+  const uint64_t tbase = tile * STILE;
   const uint64_t ebase = tbase + (uint64_t)w * PER_WAVE + lane;
   uint32_t kk[ROUNDS], ii[ROUNDS];
   uint64_t ll[ROUNDS];
@@ -266,7 +279,7 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
   uint32_t slot[ROUNDS];
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) slot[r] = bin_start[dig[r]] + wcnt[w][dig[r]] + rnk[r];
-  const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, N - tbase);
+  const uint32_t tile_n = (uint32_t)min((uint64_t)STILE, N - tbase);
 
   // keys (with their output positions), then ids, fractions, masses
   uint64_t gpos[SITEMS];
@@ -691,18 +704,27 @@ struct Sorted {
   const uint16_t *kb;   // log-scale bin of the selection key
 };
 
-__device__ __forceinline__ void write_point(const BuildArgs &a, const TreeArgs &t, const Sorted &s,
-                                            uint64_t pos, uint64_t out, int d, float mass) {
-  const uint32_t k = s.key[pos];
+// A stored point's fields read from the sorted arrays (loads are issued for
+// every lane; the stores are predicated by the caller).
+struct PointIn {
+  uint32_t k, id;
+  uint64_t l;
+};
+
+__device__ __forceinline__ PointIn read_point(const Sorted &s, uint64_t pos) {
+  return PointIn{s.key[pos], s.idx[pos], s.lo[pos]};
+}
+
+__device__ __forceinline__ void store_point(const BuildArgs &a, const TreeArgs &t, const PointIn &q, uint64_t out,
+                                            int d, float mass) {
   const int D = a.D;
-  const uint32_t kk = D ? (k & (uint32_t)((1ull << (3 * D)) - 1)) : 0u;
+  const uint32_t kk = D ? (q.k & (uint32_t)((1ull << (3 * D)) - 1)) : 0u;
   const uint32_t cx = compact3(kk), cy = compact3(kk >> 1), cz = compact3(kk >> 2);
-  const uint64_t l = s.lo[pos];
-  const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)k >> (3 * D)) : 0u;
-  t.pt_id[out] = (uint32_t)local_id(a, snap, s.idx[pos]);
-  t.qx[out] = quant_at(cx, (uint32_t)(l & 0xFFFFu), D, d);
-  t.qy[out] = quant_at(cy, (uint32_t)((l >> 16) & 0xFFFFu), D, d);
-  t.qz[out] = quant_at(cz, (uint32_t)((l >> 32) & 0xFFFFu), D, d);
+  const uint32_t snap = (a.n_snap > 1) ? (uint32_t)((uint64_t)q.k >> (3 * D)) : 0u;
+  t.pt_id[out] = (uint32_t)local_id(a, snap, q.id);
+  t.qx[out] = quant_at(cx, (uint32_t)(q.l & 0xFFFFu), D, d);
+  t.qy[out] = quant_at(cy, (uint32_t)((q.l >> 16) & 0xFFFFu), D, d);
+  t.qz[out] = quant_at(cz, (uint32_t)((q.l >> 32) & 0xFFFFu), D, d);
   t.pt_mass[out] = mass;
 }
 
@@ -713,6 +735,8 @@ __device__ __forceinline__ uint64_t exact_K(const BuildArgs &a, const Sorted &s,
   return selection_key(U, s.w[p], a.alpha);
 }
 
+constexpr int LILP = 4;       // particles per thread per step in k_leaves
+
 __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s) {
   __shared__ double red[TB / WAVE + 1];
   const uint32_t nn = t.lvl[a.D + 1];
@@ -720,15 +744,30 @@ __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s
   for (uint32_t v = blockIdx.x; v < nn; v += gridDim.x) {
     if (t.first_child[v] != NONE) continue;
     const uint64_t b = t.part_begin[v], c = t.part_count[v];
+    const bool copy = c <= a.n && cap_ok;
+    const uint64_t ob = t.pt_begin[v];
+    const int d = t.depth[v];
     double acc = 0.0;
-    for (uint64_t i = threadIdx.x; i < c; i += TB) acc += (double)s.m[b + i];
+    for (uint64_t i0 = threadIdx.x; i0 < c; i0 += TB * LILP) {
+      float mm[LILP];
+      PointIn q[LILP];
+#pragma unroll
+      for (int u = 0; u < LILP; ++u) {
+        const uint64_t pos = b + min(i0 + (uint64_t)u * TB, c - 1);
+        mm[u] = s.m[pos];
+        if (copy) q[u] = read_point(s, pos);
+      }
+#pragma unroll
+      for (int u = 0; u < LILP; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * TB;
+        if (i < c) {
+          acc += (double)mm[u];
+          if (copy) store_point(a, t, q[u], ob + i, d, mm[u]);
+        }
+      }
+    }
     const double M = block_reduce_sum<double>(acc, red);
     if (threadIdx.x == 0) t.node_mass[v] = M;
-    if (c <= a.n && cap_ok) {
-      const uint64_t ob = t.pt_begin[v];
-      const int d = t.depth[v];
-      for (uint64_t i = threadIdx.x; i < c; i += TB) write_point(a, t, s, b + i, ob + i, d, s.m[b + i]);
-    }
   }
 }
 
@@ -785,28 +824,23 @@ __device__ __forceinline__ void for_candidates(const Segs &g, const SelArgs &sa,
     if (g.is_list[k]) {
       const uint64_t *lp = sa.lists + base;
       for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * ILP) {
+        // clamped, unconditional loads (a predicated load is waited for alone)
         uint64_t e[ILP];
 #pragma unroll
-        for (int u = 0; u < ILP; ++u) {
-          const uint32_t j = j0 + u * BS;
-          e[u] = j < L ? lp[j] : ~0ull;
-        }
+        for (int u = 0; u < ILP; ++u) e[u] = lp[min(j0 + u * BS, L - 1)];
 #pragma unroll 1
         for (int u = 0; u < ILP; ++u)
-          if (e[u] != ~0ull) f(entry_pos(e[u], sa.n_minus_1), entry_kb(e[u]));
+          if (j0 + u * BS < L) f(entry_pos(e[u], sa.n_minus_1), entry_kb(e[u]));
       }
     } else {
       const uint16_t *kp = s.kb + base;
       for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * RILP) {
         uint32_t kb[RILP];
 #pragma unroll
-        for (int u = 0; u < RILP; ++u) {
-          const uint32_t j = j0 + u * BS;
-          kb[u] = j < L ? kp[j] : 0xFFFFFFFFu;
-        }
+        for (int u = 0; u < RILP; ++u) kb[u] = kp[min(j0 + u * BS, L - 1)];
 #pragma unroll 1
         for (int u = 0; u < RILP; ++u)
-          if (kb[u] != 0xFFFFFFFFu) f((uint32_t)(base + j0 + u * BS), kb[u]);
+          if (j0 + u * BS < L) f((uint32_t)(base + j0 + u * BS), kb[u]);
       }
     }
   }
@@ -976,15 +1010,22 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     const uint64_t base = g.base[k];
     for (uint32_t j0 = 0; j0 < L; j0 += BS * CILP) {
       uint32_t p[CILP], kb[CILP];
+      if (lst) {
 #pragma unroll
-      for (int u = 0; u < CILP; ++u) {
-        const uint32_t j = j0 + u * BS + threadIdx.x;
-        p[u] = NONE; kb[u] = 0;
-        if (j < L) {
-          if (lst) { const uint64_t e = sa.lists[base + j]; p[u] = entry_pos(e, sa.n_minus_1); kb[u] = entry_kb(e); }
-          else { p[u] = (uint32_t)(base + j); kb[u] = s.kb[base + j]; }
+        for (int u = 0; u < CILP; ++u) {
+          const uint64_t e = sa.lists[base + min(j0 + u * BS + threadIdx.x, L - 1)];
+          p[u] = entry_pos(e, sa.n_minus_1); kb[u] = entry_kb(e);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < CILP; ++u) {
+          const uint32_t jc = min(j0 + u * BS + threadIdx.x, L - 1);
+          p[u] = (uint32_t)(base + jc); kb[u] = s.kb[base + jc];
         }
       }
+#pragma unroll
+      for (int u = 0; u < CILP; ++u)
+        if (j0 + u * BS + threadIdx.x >= L) p[u] = NONE;
 #pragma unroll 1
       for (int u = 0; u < CILP; ++u) {
         uint64_t keep = ~0ull;
@@ -1034,20 +1075,18 @@ __device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
   const double tau = weight_pow(s.w[pt], alpha) * 4294967296.0 / (double)Ut;
   double acc = 0.0;
+  // list entries and gathers are loaded for every lane (clamped); only the
+  // arithmetic and the stores are predicated
   for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += blockDim.x * ILP) {
     uint32_t p[ILP], w[ILP];
     float mm[ILP];
 #pragma unroll
-    for (int u = 0; u < ILP; ++u) {
-      const uint32_t j = j0 + u * blockDim.x;
-      p[u] = j <= n ? entry_pos(list[j], sa.n_minus_1) : NONE;
-    }
+    for (int u = 0; u < ILP; ++u) p[u] = entry_pos(list[min(j0 + u * blockDim.x, n)], sa.n_minus_1);
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; }
 #pragma unroll
     for (int u = 0; u < ILP; ++u)
-      if (p[u] != NONE) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; }
-#pragma unroll
-    for (int u = 0; u < ILP; ++u)
-      if (p[u] != NONE && p[u] != pt) acc += (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
+      if (j0 + u * blockDim.x <= n && p[u] != pt) acc += (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
   }
   const double tot = block_reduce_sum<double>(acc, red);
   const double scale = t.node_mass[v] / tot;
@@ -1056,20 +1095,17 @@ __device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += blockDim.x * ILP) {
     uint32_t p[ILP], w[ILP];
     float mm[ILP];
+    PointIn q[ILP];
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) p[u] = entry_pos(list[min(j0 + u * blockDim.x, n)], sa.n_minus_1);
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; q[u] = read_point(s, p[u]); }
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
       const uint32_t j = j0 + u * blockDim.x;
-      p[u] = j <= n ? entry_pos(list[j], sa.n_minus_1) : NONE;
-    }
-#pragma unroll
-    for (int u = 0; u < ILP; ++u)
-      if (p[u] != NONE) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; }
-#pragma unroll
-    for (int u = 0; u < ILP; ++u) {
-      if (p[u] == NONE || p[u] == pt) continue;
+      if (j > n || p[u] == pt) continue;
       const double mhat = (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
-      const uint32_t j = j0 + u * blockDim.x;
-      write_point(a, t, s, p[u], ob + j - (p[u] > pt ? 1u : 0u), d, (float)(scale * mhat));
+      store_point(a, t, q[u], ob + j - (p[u] > pt ? 1u : 0u), d, (float)(scale * mhat));
     }
   }
 }
@@ -1204,7 +1240,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   BuildLayout L{};
   const uint64_t Np = N ? N : 1;
-  const uint64_t tiles = (Np + TILE - 1) / TILE;
+  const uint64_t tiles = (Np + STILE - 1) / STILE;
   L.tiles = tiles;
   uint64_t per_level = N / ((uint64_t)p.n + 1);
   L.node_cap = (uint64_t)n_snap + 8ull * p.max_depth * per_level;
@@ -1270,8 +1306,9 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   float *mA = (float *)(W + L.mA), *mB = (float *)(W + L.mB);
   uint32_t *thist = (uint32_t *)(W + L.thist);
   uint32_t *scan32 = (uint32_t *)(W + L.scan32);
-  const uint64_t tiles = (N + TILE - 1) / TILE;
+  const uint64_t tiles = (N + STILE - 1) / STILE;
   const uint64_t hist_n = (uint64_t)RADIX * tiles;
+  const uint64_t dtiles = (N + TILE - 1) / TILE;
 
   LOD_LAUNCH(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a, thist, tiles);
   const int kb = key_bits(p, n_snap);
@@ -1291,7 +1328,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   }
   Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint16_t *)(W + L.kb)};
 
-  LOD_LAUNCH(k_density, dim3((unsigned)tiles), dim3(TB), 0, st, a, ks, is,
+  LOD_LAUNCH(k_density, dim3((unsigned)dtiles), dim3(TB), 0, st, a, ks, is,
              (uint32_t *)(W + L.w), (uint16_t *)(W + L.kb));
 
   TreeArgs t{};
