@@ -715,8 +715,8 @@ __device__ __forceinline__ PointIn read_point(const Sorted &s, uint64_t pos) {
   return PointIn{s.key[pos], s.idx[pos], s.lo[pos]};
 }
 
-__device__ __forceinline__ void store_point(const BuildArgs &a, const TreeArgs &t, const PointIn &q, uint64_t out,
-                                            int d, float mass) {
+__device__ __forceinline__ void store_point_pos(const BuildArgs &a, const TreeArgs &t, const PointIn &q,
+                                                uint64_t out, int d) {
   const int D = a.D;
   const uint32_t kk = D ? (q.k & (uint32_t)((1ull << (3 * D)) - 1)) : 0u;
   const uint32_t cx = compact3(kk), cy = compact3(kk >> 1), cz = compact3(kk >> 2);
@@ -725,6 +725,11 @@ __device__ __forceinline__ void store_point(const BuildArgs &a, const TreeArgs &
   t.qx[out] = quant_at(cx, (uint32_t)(q.l & 0xFFFFu), D, d);
   t.qy[out] = quant_at(cy, (uint32_t)((q.l >> 16) & 0xFFFFu), D, d);
   t.qz[out] = quant_at(cz, (uint32_t)((q.l >> 32) & 0xFFFFu), D, d);
+}
+
+__device__ __forceinline__ void store_point(const BuildArgs &a, const TreeArgs &t, const PointIn &q, uint64_t out,
+                                            int d, float mass) {
+  store_point_pos(a, t, q, out, d);
   t.pt_mass[out] = mass;
 }
 
@@ -789,13 +794,14 @@ __global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, i
 constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
 constexpr int ILP = 8;        // list entries in flight per thread in the candidate passes
-constexpr int RILP = 16;      // key bins in flight per thread on contiguous ranges
-constexpr int CILP = 4;       // candidates per thread per compaction step
+constexpr int SILP = 8;       // candidates per lane per wave step
+constexpr int QCAP = 2048;    // bin-b0 candidates queued in LDS by the collect pass
 
 // A list entry packs a sorted position (low 32 bits) and its key bin (next 16).
 struct SelArgs {
   uint64_t *lists;            // top-(n+1) lists by selecting rank
   uint32_t n_minus_1;         // N - 1
+  double *mhat;               // float64 mass scratch, one row of n per block
 };
 
 __device__ __forceinline__ uint32_t entry_pos(uint64_t e, uint32_t n_minus_1) {
@@ -809,42 +815,6 @@ struct Segs {
   uint32_t len[9];
   uint32_t is_list[9];
 };
-
-// Calls f(p, kbin) for every candidate.  List entries carry their key bin, so
-// a list segment is one coalesced stream; a range segment streams the
-// contiguous key-bin array.  Positions from lists are clamped below N so that a
-// list left unwritten by a failed child cannot send a read out of bounds (the
-// failure itself is reported in the status word).
-template <typename F>
-__device__ __forceinline__ void for_candidates(const Segs &g, const SelArgs &sa, const Sorted &s, F f) {
-  const uint32_t BS = blockDim.x;
-  for (int k = 0; k < (int)g.nseg; ++k) {
-    const uint32_t L = g.len[k];
-    const uint64_t base = g.base[k];
-    if (g.is_list[k]) {
-      const uint64_t *lp = sa.lists + base;
-      for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * ILP) {
-        // clamped, unconditional loads (a predicated load is waited for alone)
-        uint64_t e[ILP];
-#pragma unroll
-        for (int u = 0; u < ILP; ++u) e[u] = lp[min(j0 + u * BS, L - 1)];
-#pragma unroll 1
-        for (int u = 0; u < ILP; ++u)
-          if (j0 + u * BS < L) f(entry_pos(e[u], sa.n_minus_1), entry_kb(e[u]));
-      }
-    } else {
-      const uint16_t *kp = s.kb + base;
-      for (uint32_t j0 = threadIdx.x; j0 < L; j0 += BS * RILP) {
-        uint32_t kb[RILP];
-#pragma unroll
-        for (int u = 0; u < RILP; ++u) kb[u] = kp[min(j0 + u * BS, L - 1)];
-#pragma unroll 1
-        for (int u = 0; u < RILP; ++u)
-          if (j0 + u * BS < L) f((uint32_t)(base + j0 + u * BS), kb[u]);
-      }
-    }
-  }
-}
 
 __device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArgs &t, uint32_t v, Segs &g) {
   const uint32_t n = a.n;
@@ -867,10 +837,122 @@ __device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArg
   g.nseg = ns;
 }
 
-// Finds the n+1 smallest (K, id) among node v's candidates and writes their
-// sorted positions, ascending, to its list; the (n+1)-th is the witness.
+// The candidates of a node are the concatenation of its segments, in sorted
+// position order.  Wave w of the block owns the w-th of W equal contiguous
+// parts of every segment, so (segment, wave) parts are in candidate order and
+// a wave streams its part in steps of 64 x SILP without block barriers.
+__device__ __forceinline__ void wave_part(uint32_t L, uint32_t w, uint32_t W, uint32_t &lo, uint32_t &hi) {
+  const uint32_t P = (L + W - 1) / W;
+  lo = min(L, w * P);
+  hi = min(L, lo + P);
+}
+
+// Loads SILP candidates (sorted position, key bin) of a wave step; indices
+// are clamped into the part, so every load is issued unconditionally.
+__device__ __forceinline__ void load_step(const Segs &g, int k, const SelArgs &sa, const Sorted &s, uint32_t j0,
+                                          uint32_t hi, uint32_t (&pos)[SILP], uint32_t (&kb)[SILP]) {
+  const uint32_t lane = threadIdx.x & (WAVE - 1);
+  const uint64_t base = g.base[k];
+  if (g.is_list[k]) {
+#pragma unroll
+    for (int u = 0; u < SILP; ++u) {
+      const uint64_t e = sa.lists[base + min(j0 + u * WAVE + lane, hi - 1)];
+      pos[u] = entry_pos(e, sa.n_minus_1);
+      kb[u] = entry_kb(e);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < SILP; ++u) {
+      const uint64_t p = base + min(j0 + u * WAVE + lane, hi - 1);
+      pos[u] = (uint32_t)p;
+      kb[u] = s.kb[p];
+    }
+  }
+}
+
+// Calls f(k, pos, kb) for every candidate of this wave's parts, in no
+// particular order (f is inlined many times: keep it small), with 16-byte loads (8 key bins or 2 list entries per
+// lane and load) so that many bytes are in flight per wave.  Reads may run up
+// to 16 bytes past a part; the key-bin and list arrays are padded for it.
+constexpr int BU = 4;         // 16-byte loads in flight per lane
+template <typename F>
+__device__ __forceinline__ void for_parts_bulk(const Segs &g, const SelArgs &sa, const Sorted &s, F f) {
+  const uint32_t W = blockDim.x / WAVE, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  for (int k = 0; k < (int)g.nseg; ++k) {
+    uint32_t lo, hi;
+    wave_part(g.len[k], w, W, lo, hi);
+    if (lo >= hi) continue;
+    const uint64_t b = g.base[k] + lo, e = g.base[k] + hi;   // element range [b, e)
+    if (g.is_list[k]) {
+      const uint64_t a0 = b & ~1ull, last = (e - 1) & ~1ull;
+      for (uint64_t q0 = a0; q0 < e; q0 += 2ull * WAVE * BU) {
+        uint64_t v0[BU], v1[BU];
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+          const uint64_t i = min(q0 + 2ull * (u * WAVE + lane), last);
+          const ulonglong2 pr = *reinterpret_cast<const ulonglong2 *>(sa.lists + i);
+          v0[u] = pr.x; v1[u] = pr.y;
+        }
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+          const uint64_t i = q0 + 2ull * (u * WAVE + lane);
+          if (i >= b && i < e) f(k, entry_pos(v0[u], sa.n_minus_1), entry_kb(v0[u]));
+          if (i + 1 >= b && i + 1 < e) f(k, entry_pos(v1[u], sa.n_minus_1), entry_kb(v1[u]));
+        }
+      }
+    } else {
+      const uint64_t a0 = b & ~7ull, last = (e - 1) & ~7ull;
+      for (uint64_t q0 = a0; q0 < e; q0 += 8ull * WAVE * BU) {
+        uint4 v[BU];
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+          const uint64_t i = min(q0 + 8ull * (u * WAVE + lane), last);
+          v[u] = *reinterpret_cast<const uint4 *>(s.kb + i);
+        }
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+          const uint64_t i = q0 + 8ull * (u * WAVE + lane);
+          const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+          for (int h = 0; h < 8; ++h) {
+            const uint64_t ih = i + h;
+            if (ih >= b && ih < e) f(k, (uint32_t)ih, (wd[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Calls f(k, pos, kb) for every candidate of this wave's parts.
+template <typename F>
+__device__ __forceinline__ void for_parts(const Segs &g, const SelArgs &sa, const Sorted &s, F f) {
+  const uint32_t W = blockDim.x / WAVE, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  for (int k = 0; k < (int)g.nseg; ++k) {
+    uint32_t lo, hi;
+    wave_part(g.len[k], w, W, lo, hi);
+    for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * SILP) {
+      uint32_t pos[SILP], kb[SILP];
+      load_step(g, k, sa, s, j0, hi, pos, kb);
+#pragma unroll 1
+      for (int u = 0; u < SILP; ++u)
+        if (j0 + u * WAVE + lane < hi) f(k, pos[u], kb[u]);
+    }
+  }
+}
+
+// One selecting node, whole block: the n+1 smallest (K, id) among its
+// candidates (children's lists or its own range) form its list, ascending by
+// sorted position; the (n+1)-th smallest is the witness.  The other n are
+// its stored points, written with their float64-renormalised masses.
+//
 // Round 0 histograms the 12-bit log-scale bin of K (stored per particle); the
-// exact K is recomputed only for candidates in the threshold bin.  Whole block.
+// exact K is recomputed only in the threshold bin (rare further rounds split
+// it by 8-bit digits of K, then of the id).  The collect pass gathers the
+// threshold bin's candidates and counts, per (segment, wave) part, the
+// candidates below it; after ranking, one scan of those counts gives every
+// part its output offset and the write pass compacts each part with wave
+// ballots.
 __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
                             uint32_t v) {
   __shared__ Segs g;
@@ -878,19 +960,26 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __shared__ uint64_t ck[SMALL];
   __shared__ uint32_t cidx[SMALL];
   __shared__ uint32_t cpos[SMALL];
-  __shared__ uint32_t ccount;
+  __shared__ uint16_t cpart[SMALL];
+  __shared__ uint32_t pcnt[9 * (1024 / WAVE)];   // per (segment, wave) part: count, then offset
+  __shared__ uint32_t ccount, sh_total, nq;
+  __shared__ uint32_t qpos[QCAP];
+  __shared__ uint16_t qpart[QCAP];
   __shared__ uint32_t red32[1024 / WAVE + 1];
+  __shared__ double red64[1024 / WAVE + 1];
   __shared__ uint64_t sh_kt;
   __shared__ uint32_t sh_it, sh_pt;
   __shared__ uint32_t sh_b, sh_below, sh_cnt;
-  __shared__ uint64_t stage[CILP * 1024];
+  __shared__ double sh_tau;
   const uint32_t n = a.n;
   const int BS = blockDim.x;
+  const uint32_t W = BS / WAVE, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
   if (threadIdx.x == 0) build_segments(a, t, v, g);
   for (int i = threadIdx.x; i < KBINS; i += BS) hist[i] = 0;
+  for (int i = threadIdx.x; i < 9 * (int)W; i += BS) pcnt[i] = 0;
   if (threadIdx.x == 0) { sh_b = 0; sh_below = 0; sh_cnt = 0; }
   __syncthreads();
-  for_candidates(g, sa, s, [&](uint32_t p, uint32_t kb) { atomicAdd(&hist[kb], 1u); });
+  for_parts_bulk(g, sa, s, [&](int, uint32_t, uint32_t kb) { atomicAdd(&hist[kb], 1u); });
   __syncthreads();
   uint32_t r = n;                            // 0-based rank of the witness among in-play
   {
@@ -912,6 +1001,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint32_t b0 = sh_b;
   r -= sh_below;
   uint32_t inplay = sh_cnt;
+  const uint32_t sh_cnt0 = sh_cnt;           // candidates in bin b0
   int kshift;                                // K >> kshift == kp for the in-play candidates
   uint64_t kp;
   if (b0 < 128) { kp = b0; kshift = 0; }
@@ -931,7 +1021,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     const int sft = (phase == 0 ? kshift : ishift) - wb;
     for (int i = threadIdx.x; i < RADIX; i += BS) hist[i] = 0;
     __syncthreads();
-    for_candidates(g, sa, s, [&](uint32_t p, uint32_t kb) {
+    for_parts(g, sa, s, [&](int, uint32_t p, uint32_t kb) {
       if (kb != b0) return;
       const uint64_t K = exact_K(a, s, p);
       bool match;
@@ -963,23 +1053,61 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     else { ip = (ip << wb) | sh_b; ishift = sft; }
     __syncthreads();
   }
-  // collect the in-play candidates with their exact keys and rank them
-  if (threadIdx.x == 0) { ccount = 0; sh_pt = NONE; }
+  // collect the in-play candidates; count, per part, the candidates of lower
+  // bins and (once ranked) the in-play ones at or below the witness
+  if (threadIdx.x == 0) { ccount = 0; sh_pt = NONE; nq = 0; }
   __syncthreads();
-  for_candidates(g, sa, s, [&](uint32_t p, uint32_t kb) {
-    if (kb != b0) return;
+  // a candidate of bin b0 with exact key K: in play (collected) or, if not,
+  // counted when it lies below the in-play digits
+  auto visit_b0 = [&](uint32_t part, uint32_t p) {
     const uint64_t K = exact_K(a, s, p);
-    bool match;
-    if (phase == 0) match = (K >> kshift) == kp;
-    else {
-      const uint32_t id = s.idx[p];
-      match = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
+    const uint32_t id = s.idx[p];
+    bool inp, lower;
+    if (phase == 0) {
+      inp = (K >> kshift) == kp;
+      lower = (K >> kshift) < kp;
+    } else {
+      inp = (K == kp) && ((ishift >= 32) ? true : ((id >> ishift) == ip));
+      lower = (K < kp) || (K == kp && ishift < 32 && (id >> ishift) < ip);
     }
-    if (match) {
+    if (inp) {
       const uint32_t slot = atomicAdd(&ccount, 1u);
-      if (slot < SMALL) { ck[slot] = K; cidx[slot] = s.idx[p]; cpos[slot] = p; }
+      if (slot < SMALL) { ck[slot] = K; cidx[slot] = id; cpos[slot] = p; cpart[slot] = (uint16_t)part; }
+    } else if (lower) {
+      atomicAdd(&pcnt[part], 1u);
     }
-  });
+  };
+  {
+    uint32_t below_cnt = 0;
+    int cur = -1;
+    if (sh_cnt0 <= QCAP) {
+      // bin-b0 candidates are queued in LDS and keyed afterwards by the whole block
+      for_parts_bulk(g, sa, s, [&](int k, uint32_t p, uint32_t kb) {
+        if (k != cur) {
+          if (cur >= 0 && below_cnt) atomicAdd(&pcnt[cur * W + w], below_cnt);
+          cur = k; below_cnt = 0;
+        }
+        if (kb < b0) ++below_cnt;
+        else if (kb == b0) {
+          const uint32_t q = atomicAdd(&nq, 1u);
+          qpos[q] = p; qpart[q] = (uint16_t)(k * W + w);
+        }
+      });
+      if (cur >= 0 && below_cnt) atomicAdd(&pcnt[cur * W + w], below_cnt);
+      __syncthreads();
+      for (uint32_t q = threadIdx.x; q < nq; q += BS) visit_b0(qpart[q], qpos[q]);
+    } else {
+      for_parts(g, sa, s, [&](int k, uint32_t p, uint32_t kb) {
+        if (k != cur) {
+          if (cur >= 0 && below_cnt) atomicAdd(&pcnt[cur * W + w], below_cnt);
+          cur = k; below_cnt = 0;
+        }
+        if (kb < b0) ++below_cnt;
+        else if (kb == b0) visit_b0(k * W + w, p);
+      });
+      if (cur >= 0 && below_cnt) atomicAdd(&pcnt[cur * W + w], below_cnt);
+    }
+  }
   __syncthreads();
   const uint32_t cc = min(ccount, (uint32_t)SMALL);
   for (uint32_t e = threadIdx.x; e < cc; e += BS) {
@@ -991,6 +1119,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
       rank += (Kf < Ke || (Kf == Ke && cidx[f] < Ie)) ? 1u : 0u;
     }
     if (rank == r) { sh_kt = Ke; sh_it = Ie; sh_pt = cpos[e]; }
+    if (rank <= r) atomicAdd(&pcnt[cpart[e]], 1u);
   }
   __syncthreads();
   if (sh_pt == NONE || ccount > SMALL) {
@@ -1000,114 +1129,84 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   }
   const uint64_t Kt = sh_kt;
   const uint32_t It = sh_it;
-  // order-preserving compaction of (K, id) <= (Kt, It), BS*CILP candidates at
-  // a time: striped loads into LDS, then one blocked scan
-  uint64_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
-  uint32_t written = 0;
-  for (int k = 0; k < (int)g.nseg; ++k) {
-    const uint32_t L = g.len[k];
-    const bool lst = g.is_list[k];
-    const uint64_t base = g.base[k];
-    for (uint32_t j0 = 0; j0 < L; j0 += BS * CILP) {
-      uint32_t p[CILP], kb[CILP];
-      if (lst) {
-#pragma unroll
-        for (int u = 0; u < CILP; ++u) {
-          const uint64_t e = sa.lists[base + min(j0 + u * BS + threadIdx.x, L - 1)];
-          p[u] = entry_pos(e, sa.n_minus_1); kb[u] = entry_kb(e);
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < CILP; ++u) {
-          const uint32_t jc = min(j0 + u * BS + threadIdx.x, L - 1);
-          p[u] = (uint32_t)(base + jc); kb[u] = s.kb[base + jc];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < CILP; ++u)
-        if (j0 + u * BS + threadIdx.x >= L) p[u] = NONE;
-#pragma unroll 1
-      for (int u = 0; u < CILP; ++u) {
-        uint64_t keep = ~0ull;
-        if (p[u] != NONE) {
-          bool take = kb[u] < b0;
-          if (kb[u] == b0) {
-            const uint64_t K = exact_K(a, s, p[u]);
-            take = K < Kt || (K == Kt && s.idx[p[u]] <= It);
-          }
-          if (take) keep = (uint64_t)p[u] | ((uint64_t)kb[u] << 32);
-        }
-        stage[u * BS + threadIdx.x] = keep;
-      }
-      __syncthreads();
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int i = 0; i < CILP; ++i) cnt += stage[threadIdx.x * CILP + i] != ~0ull ? 1u : 0u;
-      uint32_t tot;
-      uint32_t o = written + block_excl_scan<uint32_t>(cnt, red32, tot);
-#pragma unroll
-      for (int i = 0; i < CILP; ++i) {
-        const uint64_t q = stage[threadIdx.x * CILP + i];
-        if (q != ~0ull) { if (o <= n) out[o] = q; ++o; }
-      }
-      written += tot;
-      __syncthreads();
-    }
-  }
+  const uint32_t pt = sh_pt;
   if (threadIdx.x == 0) {
-    t.wit[v] = sh_pt;
-    if (written != n + 1) set_status(a, STATUS_INTERNAL);
+    // part offsets (exclusive, candidate order) and the witness's tau
+    uint32_t run = 0;
+    for (uint32_t i = 0; i < g.nseg * W; ++i) { const uint32_t c = pcnt[i]; pcnt[i] = run; run += c; }
+    sh_total = run;
+    const uint32_t kt = s.key[pt];
+    const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
+    const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
+    sh_tau = weight_pow(s.w[pt], a.alpha) * 4294967296.0 / (double)Ut;
   }
   __syncthreads();
-}
-
-// Renormalised masses, quantisation and output of one selecting node (whole block).
-__device__ void output_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
-                            uint32_t v) {
-  __shared__ double red[1024 / WAVE + 1];
-  const uint32_t n = a.n;
-  const int alpha = a.alpha;
-  const uint32_t pt = t.wit[v];
-  if (pt == NONE || a.counts[1] > a.point_cap) return;
-  const uint64_t *list = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
-  const uint32_t kt = s.key[pt];
-  const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
-  const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
-  const double tau = weight_pow(s.w[pt], alpha) * 4294967296.0 / (double)Ut;
-  double acc = 0.0;
-  // list entries and gathers are loaded for every lane (clamped); only the
-  // arithmetic and the stores are predicated
-  for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += blockDim.x * ILP) {
-    uint32_t p[ILP], w[ILP];
-    float mm[ILP];
-#pragma unroll
-    for (int u = 0; u < ILP; ++u) p[u] = entry_pos(list[min(j0 + u * blockDim.x, n)], sa.n_minus_1);
-#pragma unroll
-    for (int u = 0; u < ILP; ++u) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; }
-#pragma unroll
-    for (int u = 0; u < ILP; ++u)
-      if (j0 + u * blockDim.x <= n && p[u] != pt) acc += (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
+  if (sh_total != n + 1) {
+    if (threadIdx.x == 0) set_status(a, STATUS_INTERNAL);
+    __syncthreads();
+    return;
   }
-  const double tot = block_reduce_sum<double>(acc, red);
-  const double scale = t.node_mass[v] / tot;
+  // write pass: list entries, and the stored points with their unscaled
+  // float64 masses (kept in this block's scratch row)
+  const double tau = sh_tau;
+  const bool out_ok = a.counts[1] <= a.point_cap;
+  uint64_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
+  double *mrow = sa.mhat + (uint64_t)blockIdx.x * n;
   const uint64_t ob = t.pt_begin[v];
   const int d = t.depth[v];
-  for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += blockDim.x * ILP) {
-    uint32_t p[ILP], w[ILP];
-    float mm[ILP];
-    PointIn q[ILP];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+  double acc = 0.0;
+  for (int k = 0; k < (int)g.nseg; ++k) {
+    uint32_t lo, hi;
+    wave_part(g.len[k], w, W, lo, hi);
+    uint32_t run = pcnt[k * W + w];
+    for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * SILP) {
+      uint32_t pos[SILP], kb[SILP], o[SILP];
+      bool take[SILP];
+      load_step(g, k, sa, s, j0, hi, pos, kb);
 #pragma unroll
-    for (int u = 0; u < ILP; ++u) p[u] = entry_pos(list[min(j0 + u * blockDim.x, n)], sa.n_minus_1);
+      for (int u = 0; u < SILP; ++u) {
+        bool tk = j0 + u * WAVE + lane < hi && kb[u] <= b0;
+        if (tk && kb[u] == b0) {
+          const uint64_t K = exact_K(a, s, pos[u]);
+          tk = K < Kt || (K == Kt && s.idx[pos[u]] <= It);
+        }
+        const uint64_t bal = __ballot(tk);
+        o[u] = run + (uint32_t)__popcll(bal & lt_mask);
+        run += (uint32_t)__popcll(bal);
+        take[u] = tk;
+      }
+      // gathers for every lane (untaken lanes read the witness, a cached line)
+      PointIn q[SILP];
+      uint32_t wv[SILP];
+      float mm[SILP];
 #pragma unroll
-    for (int u = 0; u < ILP; ++u) { w[u] = s.w[p[u]]; mm[u] = s.m[p[u]]; q[u] = read_point(s, p[u]); }
+      for (int u = 0; u < SILP; ++u) {
+        const uint32_t p = take[u] ? pos[u] : pt;
+        q[u] = read_point(s, p);
+        wv[u] = s.w[p];
+        mm[u] = s.m[p];
+      }
 #pragma unroll
-    for (int u = 0; u < ILP; ++u) {
-      const uint32_t j = j0 + u * blockDim.x;
-      if (j > n || p[u] == pt) continue;
-      const double mhat = (double)mm[u] / fmin(1.0, weight_pow(w[u], alpha) / tau);
-      store_point(a, t, q[u], ob + j - (p[u] > pt ? 1u : 0u), d, (float)(scale * mhat));
+      for (int u = 0; u < SILP; ++u) {
+        if (!take[u] || o[u] > n) continue;
+        out[o[u]] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
+        if (pos[u] == pt || !out_ok) continue;
+        const uint32_t j = o[u] - (pos[u] > pt ? 1u : 0u);
+        const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
+        store_point_pos(a, t, q[u], ob + j, d);
+        mrow[j] = mhat;
+        acc += mhat;
+      }
     }
   }
+  const double tot = block_reduce_sum<double>(acc, red64);   // (barrier inside)
+  if (out_ok) {
+    const double scale = t.node_mass[v] / tot;
+    for (uint32_t j = threadIdx.x; j < n; j += BS) t.pt_mass[ob + j] = (float)(scale * mrow[j]);
+  }
+  if (threadIdx.x == 0) t.wit[v] = pt;
+  __syncthreads();
 }
 
 // mode 1: one launch per level, one block per selecting node of that level.
@@ -1123,14 +1222,6 @@ __global__ __launch_bounds__(1024) void k_select_level(BuildArgs a, TreeArgs t, 
 __global__ __launch_bounds__(1024) void k_select_one(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, uint32_t v) {
   if (v >= t.lvl[a.D + 1] || t.part_count[v] <= a.n) return;
   select_node(a, t, s, sa, v);
-}
-
-__global__ __launch_bounds__(1024) void k_sel_output(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
-  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
-  for (uint32_t v = b + blockIdx.x; v < e; v += gridDim.x) {
-    if (t.part_count[v] <= a.n) continue;
-    output_node(a, t, s, sa, v);
-  }
 }
 
 // Selecting nodes none of whose children select: the starting points of the
@@ -1185,8 +1276,6 @@ __global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArg
       }
       __syncthreads();
       select_node(a, t, s, sa, v);
-      __syncthreads();
-      output_node(a, t, s, sa, v);
       __threadfence();
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1260,7 +1349,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
                                scan_tmp_elems<uint32_t>(L.node_cap + 1)));
   L.scan64 = take(8 * scan_tmp_elems<uint64_t>(L.node_cap));
   L.w = take(4 * Np);
-  L.kb = take(2 * Np);
+  L.kb = take(2 * Np + 16);            // bulk selection reads may overrun by 16 bytes
   L.lvl = take(4 * (size_t)(p.max_depth + 4));
   L.lsel = take(4 * (size_t)(p.max_depth + 4));
   L.cs = take(4 * 9 * (size_t)L.node_cap);
@@ -1271,7 +1360,9 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.bscan = take(4 * (size_t)(L.node_cap + 1));
   L.bottom = take(4 * (size_t)L.node_cap);
   L.ctl = take(64);
-  L.lists = take(8 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
+  L.lists = take(8 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)) + 16);
+  L.sel_rows = (uint32_t)std::min<uint64_t>(4096, N / ((uint64_t)p.n + 1) + n_snap + 1);
+  L.mhat = take(8 * (size_t)L.sel_rows * p.n);
   L.total = off;
   return L;
 }
@@ -1355,9 +1446,10 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
   LOD_LAUNCH(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
 
-  SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1)};
+  SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1), (double *)(W + L.mhat)};
   const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
-  const unsigned sel_grid = (unsigned)std::min<uint64_t>(4096, per_level + 1);
+  // one scratch row of float64 masses per block
+  const unsigned sel_grid = (unsigned)std::min<uint64_t>(L.sel_rows, per_level + 1);
   if (p.mode == 2) {
     uint32_t *bflag = (uint32_t *)(W + L.bflag), *bscan = (uint32_t *)(W + L.bscan);
     uint32_t *ctl = (uint32_t *)(W + L.ctl);
@@ -1369,7 +1461,8 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
     int dev = 0, cus = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const unsigned pgrid = p.persistent_blocks ? p.persistent_blocks : (unsigned)(2 * cus);
+    const unsigned pgrid = std::min<unsigned>(L.sel_rows, p.persistent_blocks ? p.persistent_blocks
+                                                                              : (unsigned)(2 * cus));
     LOD_LAUNCH(k_select_persistent, dim3(pgrid), dim3(sel_threads), 0, st, a, t, s, sa,
                (const uint32_t *)(W + L.bottom), ctl);
     return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
@@ -1400,7 +1493,6 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
     } else {
       LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
     }
-    LOD_LAUNCH(k_sel_output, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
   }
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
