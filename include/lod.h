@@ -68,7 +68,10 @@ typedef void *lod_stream_t;      /* hipStream_t */
  *           when it finishes the parent's last selecting child.
  * All modes produce identical bytes.  select_threads (threads per node
  * block) and persistent_blocks (mode 2 grid) are schedule parameters, e.g.
- * from lod_autotune; 0 picks the defaults (1024 threads, 2 blocks per CU). */
+ * from lod_autotune; 0 picks the defaults (1024 threads, 2 blocks per CU).
+ * In mode 1, levels that hold at most 64 nodes (depth <= 2) always use
+ * 1024-thread blocks; mode 2 grids are capped at the selection scratch rows
+ * (min(4096, N/(n+1) + snapshots + 1)). */
 typedef struct {
   uint32_t n;
   uint32_t max_depth;

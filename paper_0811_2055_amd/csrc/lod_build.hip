@@ -828,17 +828,20 @@ __device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArg
       const uint32_t u = fc + k;
       if (t.part_count[u] > n) {
         g.base[ns] = (uint64_t)t.sel_idx[u] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
+        ++ns;
+      } else if (ns > 0 && !g.is_list[ns - 1]) {
+        g.len[ns - 1] += (uint32_t)t.part_count[u];   // siblings are adjacent in sorted order
       } else {
         g.base[ns] = t.part_begin[u]; g.len[ns] = (uint32_t)t.part_count[u]; g.is_list[ns] = 0;
+        ++ns;
       }
-      ++ns;
     }
   }
   g.nseg = ns;
 }
 
 // The candidates of a node are the concatenation of its segments, in sorted
-// position order.  Wave w of the block owns the w-th of W equal contiguous
+// position order (runs of leaf children form one range segment).  Wave w of the block owns the w-th of W equal contiguous
 // parts of every segment, so (segment, wave) parts are in candidate order and
 // a wave streams its part in steps of 64 x SILP without block barriers.
 __device__ __forceinline__ void wave_part(uint32_t L, uint32_t w, uint32_t W, uint32_t &lo, uint32_t &hi) {
@@ -1130,11 +1133,17 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint64_t Kt = sh_kt;
   const uint32_t It = sh_it;
   const uint32_t pt = sh_pt;
+  {
+    // part offsets (exclusive, candidate order; at most 9 x 16 parts)
+    const uint32_t np = g.nseg * W;
+    const uint32_t c = threadIdx.x < np ? pcnt[threadIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t>(c, red32, tot);
+    if (threadIdx.x < np) pcnt[threadIdx.x] = ex;
+    if (threadIdx.x == 0) sh_total = tot;
+  }
   if (threadIdx.x == 0) {
-    // part offsets (exclusive, candidate order) and the witness's tau
-    uint32_t run = 0;
-    for (uint32_t i = 0; i < g.nseg * W; ++i) { const uint32_t c = pcnt[i]; pcnt[i] = run; run += c; }
-    sh_total = run;
+    // the witness's tau
     const uint32_t kt = s.key[pt];
     const uint32_t snap_t = (a.n_snap > 1) ? (uint32_t)((uint64_t)kt >> (3 * a.D)) : 0u;
     const uint64_t Ut = particle_U(local_id(a, snap_t, s.idx[pt]), snap_t, a.seed);
@@ -1203,7 +1212,14 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const double tot = block_reduce_sum<double>(acc, red64);   // (barrier inside)
   if (out_ok) {
     const double scale = t.node_mass[v] / tot;
-    for (uint32_t j = threadIdx.x; j < n; j += BS) t.pt_mass[ob + j] = (float)(scale * mrow[j]);
+    for (uint32_t j0 = threadIdx.x; j0 < n; j0 += BS * SILP) {
+      double mv[SILP];
+#pragma unroll
+      for (int u = 0; u < SILP; ++u) mv[u] = mrow[min(j0 + u * BS, n - 1)];
+#pragma unroll
+      for (int u = 0; u < SILP; ++u)
+        if (j0 + u * BS < n) t.pt_mass[ob + j0 + u * BS] = (float)(scale * mv[u]);
+    }
   }
   if (threadIdx.x == 0) t.wit[v] = pt;
   __syncthreads();
@@ -1491,7 +1507,9 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
         LOD_LAUNCH(k_select_one, dim3(1), dim3(sel_threads), 0, st, a, t, s, sa, v);
       }
     } else {
-      LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(sel_threads), 0, st, a, t, s, sa, d);
+      // a level of at most 64 nodes cannot fill the chip: give each node 1024 threads
+      const bool few = d <= 2 && ((uint64_t)n_snap << (3 * d)) <= 64;
+      LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(few ? 1024u : sel_threads), 0, st, a, t, s, sa, d);
     }
   }
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
