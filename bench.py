@@ -126,8 +126,9 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--count", type=int, default=None, help="override the particle count (c3)")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
-    ap.add_argument("--mode", type=int, default=2, choices=[0, 1, 2],
+    ap.add_argument("--mode", type=int, default=1, choices=[0, 1, 2],
                     help="selection schedule: 0 per-node launches, 1 per-level launches, 2 one persistent launch")
+    ap.add_argument("--select-threads", type=int, default=512, help="threads per node block in the selection")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default selection schedule")
     ap.add_argument("--compare-modes", action="store_true",
                     help="also time one build in each selection schedule")
@@ -153,7 +154,8 @@ def main():
     log(f"[bench] workload generated: {snap.n} particles in {time.perf_counter() - t0:.1f} s")
     x, y, z, m = (torch.from_numpy(a).to(dev) for a in (snap.x, snap.y, snap.z, snap.m))
     N = snap.n
-    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=args.mode)
+    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=args.mode,
+                             select_threads=args.select_threads)
     builder = lib.Builder(N, params, dev)
     cam = lib.Camera.ortho(cfg["W"], cfg["H"])
     tree = builder.tree

@@ -139,7 +139,7 @@ class BuildParams:
     density_level: int | None = None
     alpha: int = 1
     seed: int = 0
-    mode: int = 2
+    mode: int = 1
     select_threads: int = 0
     persistent_blocks: int = 0
 
