@@ -42,7 +42,7 @@ struct SplatLayout {
 constexpr int SPLAT_TS = 16;           // tile edge in pixels
 constexpr uint32_t SPLAT_MAX_TILES = 8192;
 constexpr uint32_t SPLAT_SLICE = 2048; // points per accumulation slice
-constexpr uint32_t SPLAT_MAX_CHUNKS = 32;
+constexpr uint32_t SPLAT_MAX_CHUNKS = 64;
 
 lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_params &sp,
                         SplatLayout &L);

@@ -41,6 +41,8 @@ struct Cam {
   float norm;       // 1 / (2 pi sigma^2)
   float inv_s2;     // 1 / sigma^2
   int win;          // candidate half-window, ceil(R) + 2
+  int narrow;       // 1 when a blob covers at most 8 pixels per axis (R < 4)
+  float kexp2;      // -log2(e) / (2 sigma^2): Gaussian factor = exp2(o^2 kexp2)
   uint32_t tiles_x, tiles_y;
 };
 
@@ -59,6 +61,8 @@ Cam make_cam(const lod_camera &c, const splat_params &sp, const lodh::SplatLayou
   k.norm = (float)(1.0 / (2.0 * M_PI * s64 * s64));
   k.inv_s2 = (float)(1.0 / (s64 * s64));
   k.win = (int)std::ceil((double)k.R) + 2;
+  k.narrow = (double)k.R < 4.0 ? 1 : 0;
+  k.kexp2 = (float)(-1.4426950408889634 / (2.0 * s64 * s64));
   if (L) { k.tiles_x = L->tiles_x; k.tiles_y = L->tiles_y; }
   return k;
 }
@@ -284,15 +288,17 @@ __device__ __forceinline__ uint64_t group_of(uint32_t t, bool has, int nbits) {
   return rest ? peers : mine;
 }
 
-template <class Src, bool FILL>
-__device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, int nbits,
-                                         uint32_t *lc, float *__restrict__ bu, float *__restrict__ bv,
+// Points [u0 per, min(n, (u0 + g) per)) with per = ceil(n / units): g
+// consecutive units of the partition.
+template <class Src, bool FILL, class CT>
+__device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, uint32_t u0, uint32_t g,
+                                         int nbits, CT *lc, float *__restrict__ bu, float *__restrict__ bv,
                                          float *__restrict__ bm, uint64_t max_pairs, uint64_t *status) {
   const int lane = threadIdx.x;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
   const uint64_t n = src.count();
   const uint64_t per = (n + units - 1) / units;
-  const uint64_t b = (uint64_t)blockIdx.x * per, e = min(n, b + per);
+  const uint64_t b = (uint64_t)u0 * per, e = min(n, b + (uint64_t)g * per);
   if (b >= e) return;
   typename Src::Cursor cur;
   cur.begin(src, b, e);
@@ -325,8 +331,8 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
           const uint64_t peers = group_of(t, has, nbits);
           const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
           const uint32_t cnt = (uint32_t)__popcll(peers);
-          const uint32_t old = has ? lc[t] : 0u;
-          if (has && below == 0) lc[t] = old + cnt;
+          const uint32_t old = has ? (uint32_t)lc[t] : 0u;
+          if (has && below == 0) lc[t] = (CT)(old + cnt);
           if (FILL && has) {
             const uint64_t slot = (uint64_t)old + below;
             if (slot < max_pairs) { bu[slot] = bl.u; bv[slot] = bl.v; bm[slot] = bl.m; }
@@ -338,15 +344,18 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
   }
 }
 
-// Pass 1: row u of the [U][tiles] count table.
-template <class Src>
+// Pass 1: row u of the [U][tiles] count table.  CT = uint16_t when a unit
+// holds at most 65535 points (a point adds at most one pair per tile), which
+// halves the LDS per wave and doubles the resident waves.
+template <class Src, class CT>
 __global__ __launch_bounds__(BW) void k_bin_count(Src src, Cam c, uint32_t units, int nbits,
                                                   uint32_t *__restrict__ ucount) {
-  extern __shared__ uint32_t lc[];
+  extern __shared__ uint32_t lds_raw[];
+  CT *lc = reinterpret_cast<CT *>(lds_raw);
   const uint32_t nt = c.tiles_x * c.tiles_y;
   for (uint32_t i = threadIdx.x; i < nt; i += BW) lc[i] = 0;
   __syncthreads();
-  bin_unit<Src, false>(src, c, units, nbits, lc, nullptr, nullptr, nullptr, 0, nullptr);
+  bin_unit<Src, false, CT>(src, c, units, blockIdx.x, 1, nbits, lc, nullptr, nullptr, nullptr, 0, nullptr);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nt; i += BW) ucount[(uint64_t)blockIdx.x * nt + i] = lc[i];
 }
@@ -382,10 +391,13 @@ __global__ void k_bin_chunkscan(uint32_t *__restrict__ pchunk, uint32_t nt, uint
   tile_count[t] = run;
 }
 
-// Pass 2: write the (u, v, m) records; the unit's cursor for tile t starts at
-// tile_off[t] + (pairs of earlier chunks) + (pairs of earlier units in its chunk).
+// Pass 2: write the (u, v, m) records.  Block f covers the g consecutive
+// units f g .. f g + g - 1 (a tile's list holds their pairs in unit order, so
+// one cursor per tile carries over from one unit to the next); its cursor for
+// tile t starts at tile_off[t] + (pairs of earlier chunks) + (pairs of earlier
+// units in its chunk).
 template <class Src>
-__global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units, int nbits,
+__global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units, uint32_t g, int nbits,
                                                  const uint32_t *__restrict__ ucount,
                                                  const uint32_t *__restrict__ pchunk,
                                                  const uint32_t *__restrict__ tile_off,
@@ -393,11 +405,12 @@ __global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units,
                                                  float *__restrict__ bm, uint64_t max_pairs, uint64_t *status) {
   extern __shared__ uint32_t lc[];
   const uint32_t nt = c.tiles_x * c.tiles_y;
-  const uint32_t ch = blockIdx.x / 64;
+  const uint32_t u0 = blockIdx.x * g;
+  const uint32_t ch = u0 / 64;
   for (uint32_t i = threadIdx.x; i < nt; i += BW)
-    lc[i] = tile_off[i] + pchunk[(uint64_t)ch * nt + i] + ucount[(uint64_t)blockIdx.x * nt + i];
+    lc[i] = tile_off[i] + pchunk[(uint64_t)ch * nt + i] + ucount[(uint64_t)u0 * nt + i];
   __syncthreads();
-  bin_unit<Src, true>(src, c, units, nbits, lc, bu, bv, bm, max_pairs, status);
+  bin_unit<Src, true, uint32_t>(src, c, units, u0, g, nbits, lc, bu, bv, bm, max_pairs, status);
 }
 
 // slices per tile
@@ -469,18 +482,37 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
       if (have && clip_range(u, c.R, tx0, txe, i0, i1)) {
         if (!clip_range(v, c.R, ty0, tye, j0, j1)) { i0 = 1; i1 = 0; }
       }
-      // every row element written once, zero outside the truncation square;
-      // the hardware exp2 (relative error ~3e-7 here) is ample for 1e-5
+      // rows are zero outside the truncation square; the Gaussian factor is
+      // the hardware exp2 of o^2 (-log2 e / 2 sigma^2) (relative error ~3e-7,
+      // ample for 1e-5)
       const float w = m * c.norm;
+      if (c.narrow) {
+        // at most 8 covered pixels per axis: zero the row, then write an
+        // 8-wide window that holds the covered run
+        const int wx = min(max(i0 - tx0, 0), TS - 8), wy = min(max(j0 - ty0, 0), TS - 8);
 #pragma unroll
-      for (int e = 0; e < TS; ++e) {
-        const int i = tx0 + e, j = ty0 + e;
-        const float ox = u - ((float)i + 0.5f);
-        const float oy = v - ((float)j + 0.5f);
-        const float ex = __expf(-(ox * ox) * c.inv2s2);
-        const float ey = __expf(-(oy * oy) * c.inv2s2);
-        gx[threadIdx.x][e] = (i >= i0 && i <= i1) ? ex : 0.0f;
-        gy[threadIdx.x][e] = (j >= j0 && j <= j1) ? w * ey : 0.0f;
+        for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = tx0 + wx + q, j = ty0 + wy + q;
+          const float ox = u - ((float)i + 0.5f);
+          const float oy = v - ((float)j + 0.5f);
+          const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
+          const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
+          gx[threadIdx.x][wx + q] = (i >= i0 && i <= i1) ? ex : 0.0f;
+          gy[threadIdx.x][wy + q] = (j >= j0 && j <= j1) ? w * ey : 0.0f;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < TS; ++e) {
+          const int i = tx0 + e, j = ty0 + e;
+          const float ox = u - ((float)i + 0.5f);
+          const float oy = v - ((float)j + 0.5f);
+          const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
+          const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
+          gx[threadIdx.x][e] = (i >= i0 && i <= i1) ? ex : 0.0f;
+          gy[threadIdx.x][e] = (j >= j0 && j <= j1) ? w * ey : 0.0f;
+        }
       }
       __syncthreads();
       // phase B: wave g accumulates points 64g..64g+63 with 16 MFMA steps of
@@ -719,8 +751,9 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   L.max_slices = nt + L.max_pairs / SPLAT_SLICE + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-  // units: 64 per chunk, one chunk per 2^18 points, at most 32 chunks
-  L.chunks = (uint32_t)std::min<uint64_t>(SPLAT_MAX_CHUNKS, std::max<uint64_t>(1, (max_points + (1u << 18) - 1) >> 18));
+  // units: 64 per chunk, one chunk per 2^21 points (units of at most 32768
+  // points), at most 64 chunks
+  L.chunks = (uint32_t)std::min<uint64_t>(SPLAT_MAX_CHUNKS, std::max<uint64_t>(1, (max_points + (1u << 21) - 1) >> 21));
   L.units = 64 * L.chunks;
   L.tile_count = take(4 * (nt + 1));
   L.tile_off = take(4 * (nt + 1));
@@ -759,7 +792,11 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   if (!status_word) fill_u64(ctr, 1, 0, st);
   const size_t lds = 4 * (size_t)nt;
   if (any) {
-    LOD_LAUNCH(k_bin_count<Src>, dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount);
+    if ((L.max_points + L.units - 1) / L.units <= 65535)
+      LOD_LAUNCH((k_bin_count<Src, uint16_t>), dim3(L.units), dim3(BW), 2 * (size_t)nt, st, src, c, L.units, nbits,
+                 ucount);
+    else
+      LOD_LAUNCH((k_bin_count<Src, uint32_t>), dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount);
     LOD_LAUNCH(k_bin_colscan, dim3((nt + 255) / 256, L.chunks), dim3(256), 0, st, ucount, nt, pchunk);
     LOD_LAUNCH(k_bin_chunkscan, dim3((nt + 255) / 256), dim3(256), 0, st, pchunk, nt, L.chunks, tcount);
   }
@@ -767,8 +804,11 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   LOD_LAUNCH(k_copy_u32, dim3((nt + 256) / 256), dim3(256), 0, st, tcount, toff, (uint64_t)nt + 1);
   device_scan<uint32_t>(toff, nt + 1, stmp, st);
   if (any) {
-    LOD_LAUNCH(k_bin_fill<Src>, dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount, pchunk, toff,
-               bu, bv, bm, L.max_pairs, status);
+    // fill blocks of two units when there are many (32-bit cursors take twice
+    // the LDS of the 16-bit counts: fewer resident waves)
+    const uint32_t g = L.units >= 4096 ? 2u : 1u;
+    LOD_LAUNCH(k_bin_fill<Src>, dim3(L.units / g), dim3(BW), lds, st, src, c, L.units, g, nbits, ucount, pchunk,
+               toff, bu, bv, bm, L.max_pairs, status);
   }
   LOD_LAUNCH(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
   fill_u32(soff + nt, 1, 0, st);
