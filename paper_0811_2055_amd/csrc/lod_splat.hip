@@ -419,6 +419,19 @@ __global__ void k_slice_count(const uint32_t *__restrict__ tile_count, uint32_t 
     ns[t] = (tile_count[t] + lodh::SPLAT_SLICE - 1) / lodh::SPLAT_SLICE;
 }
 
+// Slice descriptors: (first pair, tile | pairs << 16), one per slice.
+__global__ void k_slice_table(const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ tile_count,
+                              const uint32_t *__restrict__ slice_off, uint32_t nt, uint2 *__restrict__ table,
+                              uint64_t max_slices) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
+    const uint32_t b = slice_off[t], e = slice_off[t + 1], c = tile_count[t];
+    for (uint32_t k = 0; b + k < e && b + k < max_slices; ++k) {
+      const uint32_t n = min(c - k * lodh::SPLAT_SLICE, lodh::SPLAT_SLICE);
+      table[b + k] = make_uint2(tile_off[t] + k * lodh::SPLAT_SLICE, t | (n << 16));
+    }
+  }
+}
+
 __device__ __forceinline__ void neumaier(float &s, float &c, float x) {
   const float t = s + x;
   if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
@@ -438,8 +451,7 @@ __device__ __forceinline__ void neumaier(float &s, float &c, float x) {
 // each) are then folded into the pixel's compensated (Neumaier) float32 sum.
 constexpr int GXS = TS + 1;          // padded row: conflict-free phase-A writes
 typedef float float4v __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ tile_off,
-                                                   const uint32_t *__restrict__ tile_count,
+__global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ table,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
                                                    const float *__restrict__ bu, const float *__restrict__ bv,
                                                    const float *__restrict__ bm, Cam c,
@@ -448,35 +460,39 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
   __shared__ float gx[PT][GXS];
   __shared__ float gy[PT][GXS];
   __shared__ float part[4][TS * TS];
-  __shared__ uint32_t sh_t;
-  const uint32_t total_slices = slice_off[nt];
+  const uint32_t total_slices = (uint32_t)min((uint64_t)slice_off[nt], max_slices);
   const int grp = threadIdx.x / 64;                 // point group of phase B
   const int col = threadIdx.x % TS;                 // pixel column of phase B
   const int row0 = ((threadIdx.x % 64) / TS) * 4;   // first of 4 pixel rows of phase B
-  for (uint32_t sl = blockIdx.x; sl < total_slices && sl < max_slices; sl += gridDim.x) {
-    if (threadIdx.x == 0) {
-      uint32_t lo = 0, hi = nt;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (slice_off[mid] <= sl) lo = mid; else hi = mid;
-      }
-      sh_t = lo;
-    }
-    __syncthreads();
-    const uint32_t t = sh_t;
-    const uint32_t k = sl - slice_off[t];
-    const uint64_t pb = (uint64_t)tile_off[t] + (uint64_t)k * lodh::SPLAT_SLICE;
-    const uint64_t pe = min(min((uint64_t)tile_off[t] + tile_count[t], pb + lodh::SPLAT_SLICE), max_pairs);
+  if (blockIdx.x >= total_slices) return;
+  // pair records are loaded one chunk ahead, across slice boundaries too
+  // (clamped indices: every load is issued unconditionally)
+  const uint64_t last = max_pairs - 1;
+  uint2 sd = table[blockIdx.x];
+  float nu, nv, nm;
+  {
+    const uint64_t q = min((uint64_t)sd.x + threadIdx.x, last);
+    nu = bu[q]; nv = bv[q]; nm = bm[q];
+  }
+  for (uint32_t sl = blockIdx.x; sl < total_slices; sl += gridDim.x) {
+    const uint32_t t = sd.y & 0xFFFFu;
+    const uint64_t pb = sd.x;
+    const uint64_t pe = min(pb + (sd.y >> 16), max_pairs);
+    const uint32_t nsl = sl + gridDim.x;
+    const uint2 nsd = table[min(nsl, total_slices - 1)];
     const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
     const int txe = min(tx0 + TS, (int)c.W) - 1, tye = min(ty0 + TS, (int)c.H) - 1;
     float s = 0.0f, cc = 0.0f;
-    float nu = 0.0f, nv = 0.0f, nm = 0.0f;
-    if (pb + threadIdx.x < pe) { nu = bu[pb + threadIdx.x]; nv = bv[pb + threadIdx.x]; nm = bm[pb + threadIdx.x]; }
     for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
-      const float u = nu, v = nv, m = nm;
       const bool have = c0 + threadIdx.x < pe;
-      const uint64_t nq = c0 + PT + threadIdx.x;
-      if (nq < pe) { nu = bu[nq]; nv = bv[nq]; nm = bm[nq]; }
+      // lanes past the slice hold whatever the clamped prefetch read: zero them
+      // so that the 0/1 masking below multiplies finite values only
+      const float u = have ? nu : 0.0f, v = have ? nv : 0.0f, m = have ? nm : 0.0f;
+      {
+        const uint64_t q = (c0 + PT < pe) ? c0 + PT + threadIdx.x : (uint64_t)nsd.x + threadIdx.x;
+        const uint64_t qc = min(q, last);
+        nu = bu[qc]; nv = bv[qc]; nm = bm[qc];
+      }
       // phase A
       int i0 = 1, i1 = 0, j0 = 1, j1 = 0;
       if (have && clip_range(u, c.R, tx0, txe, i0, i1)) {
@@ -497,10 +513,12 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
           const int i = tx0 + wx + q, j = ty0 + wy + q;
           const float ox = u - ((float)i + 0.5f);
           const float oy = v - ((float)j + 0.5f);
+          // exp2 of a non-positive finite argument lies in [0, 1]: masking by
+          // a 0/1 factor is exact and keeps the code branch-free
           const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
-          gx[threadIdx.x][wx + q] = (i >= i0 && i <= i1) ? ex : 0.0f;
-          gy[threadIdx.x][wy + q] = (j >= j0 && j <= j1) ? w * ey : 0.0f;
+          gx[threadIdx.x][wx + q] = ex * (float)(i >= i0 && i <= i1);
+          gy[threadIdx.x][wy + q] = (w * ey) * (float)(j >= j0 && j <= j1);
         }
       } else {
 #pragma unroll
@@ -521,11 +539,16 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
       const int kb = grp * 64;
       const int ln = threadIdx.x % 64;
       float4v acc4 = {0.0f, 0.0f, 0.0f, 0.0f};
+      float av[16], bv[16];   // all LDS operands first: one wait, not sixteen
 #pragma unroll
       for (int st = 0; st < 16; ++st) {
         const int kk = kb + st * 4 + ln / 16;
-        acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(gy[kk][ln % 16], gx[kk][ln % 16], acc4, 0, 0, 0);
+        av[st] = gy[kk][ln % 16];
+        bv[st] = gx[kk][ln % 16];
       }
+      __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+#pragma unroll
+      for (int st = 0; st < 16; ++st) acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st], acc4, 0, 0, 0);
       const float a0 = acc4[0], a1 = acc4[1], a2 = acc4[2], a3 = acc4[3];
       part[grp][(row0 + 0) * TS + col] = a0;
       part[grp][(row0 + 1) * TS + col] = a1;
@@ -536,6 +559,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint32_t *__restrict__ 
       for (int g = 0; g < 4; ++g) neumaier(s, cc, part[g][threadIdx.x]);
     }
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
+    sd = nsd;
     __syncthreads();
   }
 }
@@ -766,6 +790,7 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   L.bv = take(4 * L.max_pairs);
   L.bm = take(4 * L.max_pairs);
   L.partial = take(4 * (size_t)TS * TS * L.max_slices);
+  L.slice_table = take(8 * (size_t)L.max_slices);
   L.total = off;
   return LOD_OK;
 }
@@ -813,9 +838,11 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   LOD_LAUNCH(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
   fill_u32(soff + nt, 1, 0, st);
   device_scan<uint32_t>(soff, nt + 1, stmp, st);
+  uint2 *stab = (uint2 *)(W + L.slice_table);
+  LOD_LAUNCH(k_slice_table, dim3((nt + 255) / 256), dim3(256), 0, st, toff, tcount, soff, nt, stab, L.max_slices);
   const unsigned agrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, L.max_slices));
   if (any) {
-    LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, toff, tcount, soff, nt, bu, bv, bm, c, partial,
+    LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, bu, bv, bm, c, partial,
                L.max_slices, L.max_pairs);
   }
   LOD_LAUNCH(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial, c, image,
