@@ -1155,8 +1155,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     __syncthreads();
     return;
   }
-  // write pass: list entries, and the stored points with their unscaled
-  // float64 masses (kept in this block's scratch row)
+  // compaction pass: the n+1 list entries, in candidate (= sorted position) order
   const double tau = sh_tau;
   const bool out_ok = a.counts[1] <= a.point_cap;
   uint64_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
@@ -1164,14 +1163,12 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint64_t ob = t.pt_begin[v];
   const int d = t.depth[v];
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-  double acc = 0.0;
   for (int k = 0; k < (int)g.nseg; ++k) {
     uint32_t lo, hi;
     wave_part(g.len[k], w, W, lo, hi);
     uint32_t run = pcnt[k * W + w];
     for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * SILP) {
-      uint32_t pos[SILP], kb[SILP], o[SILP];
-      bool take[SILP];
+      uint32_t pos[SILP], kb[SILP];
       load_step(g, k, sa, s, j0, hi, pos, kb);
 #pragma unroll
       for (int u = 0; u < SILP; ++u) {
@@ -1181,27 +1178,35 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
           tk = K < Kt || (K == Kt && s.idx[pos[u]] <= It);
         }
         const uint64_t bal = __ballot(tk);
-        o[u] = run + (uint32_t)__popcll(bal & lt_mask);
+        const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
         run += (uint32_t)__popcll(bal);
-        take[u] = tk;
+        if (tk && o <= n) out[o] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
       }
-      // gathers for every lane (untaken lanes read the witness, a cached line)
+    }
+  }
+  __syncthreads();
+  // output pass over the list (every lane busy): the stored points and their
+  // unscaled float64 masses, kept in this block's scratch row
+  double acc = 0.0;
+  if (out_ok) {
+    for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * SILP) {
+      uint32_t pos[SILP];
+#pragma unroll
+      for (int u = 0; u < SILP; ++u) pos[u] = entry_pos(out[min(j0 + u * BS, n)], sa.n_minus_1);
       PointIn q[SILP];
       uint32_t wv[SILP];
       float mm[SILP];
 #pragma unroll
       for (int u = 0; u < SILP; ++u) {
-        const uint32_t p = take[u] ? pos[u] : pt;
-        q[u] = read_point(s, p);
-        wv[u] = s.w[p];
-        mm[u] = s.m[p];
+        q[u] = read_point(s, pos[u]);
+        wv[u] = s.w[pos[u]];
+        mm[u] = s.m[pos[u]];
       }
 #pragma unroll
       for (int u = 0; u < SILP; ++u) {
-        if (!take[u] || o[u] > n) continue;
-        out[o[u]] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
-        if (pos[u] == pt || !out_ok) continue;
-        const uint32_t j = o[u] - (pos[u] > pt ? 1u : 0u);
+        const uint32_t jl = j0 + u * BS;
+        if (jl > n || pos[u] == pt) continue;
+        const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
         const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
         store_point_pos(a, t, q[u], ob + j, d);
         mrow[j] = mhat;
