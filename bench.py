@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--count", type=int, default=None, help="override the particle count (c3)")
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=5_000_000)
     ap.add_argument("--mode", type=int, default=1, choices=[0, 1, 2],
                     help="selection schedule: 0 per-node launches, 1 per-level launches, 2 one persistent launch")
     ap.add_argument("--select-threads", type=int, default=512, help="threads per node block in the selection")

@@ -353,7 +353,7 @@ def decoded_points(tree: Tree, nodes=None):
 
 
 def node_direct(x, y, z, m, cell, d: int, n: int, D: int, L_rho: int | None = None, alpha: int = 1,
-                seed: int = 0, dens_counts=None, keys_D=None):
+                seed: int = 0, dens_counts=None, keys_D=None, snap: int = 0):
     """Stored points of the single depth-d node with cell coordinates `cell`
     (cx, cy, cz), straight from the definition over the raw particles.
 
@@ -361,6 +361,8 @@ def node_direct(x, y, z, m, cell, d: int, n: int, D: int, L_rho: int | None = No
     ids are the stored particles in the node's output order.  dens_counts may
     pass precomputed depth-L cell counts (see `density_counts`), keys_D the
     depth-D Morton keys of all particles (membership is then a key prefix test).
+    For snapshot `snap` of a batch, x, y, z, m are that snapshot's particles
+    (ids local to it) and snap enters the random stream.
     """
     if L_rho is None:
         L_rho = D
@@ -384,7 +386,7 @@ def node_direct(x, y, z, m, cell, d: int, n: int, D: int, L_rho: int | None = No
             dens_counts = density_counts(x, y, z, L_rho)
         cl = (cell_coords(x[members], L_rho), cell_coords(y[members], L_rho), cell_coords(z[members], L_rho))
         w = dens_counts[cl[0] + (cl[1] << L_rho) + (cl[2] << (2 * L_rho))].astype(np.uint64)
-        U = particle_uniform(members, 0, seed)
+        U = particle_uniform(members, snap, seed)
         K = selection_keys(U, w, alpha)
         rank = np.lexsort((members, K))
         top = rank[:n + 1]
