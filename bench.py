@@ -237,6 +237,22 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
                 "traffic": None, "kernel": dom_name, "avg_launch_ms": round(dom_avg, 4)}
+    # a plain device copy of 2 x 1 GiB, for the achievable-bandwidth context
+    ca = torch.empty(256 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        cb.copy_(ca)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ca.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del ca, cb
+    roof["copy_measured_GBs"] = round(copy_gbs, 1)
+    if roof.get("achieved") is not None:
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     S = h["n_points"]
     b_alg = 48.0 * N + 14.0 * S
     build_frac = b_alg / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS

@@ -440,26 +440,30 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   }
   __syncthreads();
   const int t0 = threadIdx.x * ITEMS;
-  // run starts: thread-local running max of start positions
-  uint64_t st[ITEMS];
-  uint64_t runmax = 0;
+  // Positions within the tile are kept as 32-bit local offsets: a run start
+  // as li + 1 (0: the run began before the tile, at first_start); a run end
+  // as li + 1 < tile_n, or tile_n for the tile's last run (which ends at
+  // last_end).
+  // run starts: thread-local running max
+  uint32_t st[ITEMS];
+  uint32_t runmax = 0;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const int li = t0 + i;
     const bool starts = (li == 0) ? (!has_prev || cell[0] != cell[1]) : (cell[li] != cell[li + 1]);
-    if (li < (int)tile_n && starts) runmax = max(runmax, base + li);
+    if (li < (int)tile_n && starts) runmax = (uint32_t)li + 1;
     st[i] = runmax;
   }
-  incl_max[threadIdx.x] = block_incl_scan_op<true>(runmax, tmp);
-  // run ends: thread-local suffix min of end positions (exclusive end index)
-  uint64_t en[ITEMS];
-  uint64_t runmin = ~0ull;
+  incl_max[threadIdx.x] = block_incl_scan_op<true>((uint64_t)runmax, tmp);
+  // run ends: thread-local suffix min
+  uint32_t en[ITEMS];
+  uint32_t runmin = 0xFFFFFFFFu;
 #pragma unroll
   for (int i = ITEMS - 1; i >= 0; --i) {
     const int li = t0 + i;
     if (li < (int)tile_n) {
-      if (li == (int)tile_n - 1) runmin = min(runmin, last_end);
-      else if (cell[li + 1] != cell[li + 2]) runmin = min(runmin, base + li + 1);
+      if (li == (int)tile_n - 1) runmin = tile_n;
+      else if (cell[li + 1] != cell[li + 2]) runmin = min(runmin, (uint32_t)li + 1);
     }
     en[i] = runmin;
   }
@@ -471,39 +475,50 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   __syncthreads();
   rev_min[threadIdx.x] = block_incl_scan_op<false>(mirrored, tmp);
   __syncthreads();
-  const uint64_t prev_max = max(first_start, threadIdx.x ? incl_max[threadIdx.x - 1] : 0ull);
+  const uint32_t prev_max = threadIdx.x ? (uint32_t)incl_max[threadIdx.x - 1] : 0u;
   // min over threads > t == reversed inclusive scan at position TB-2-t
-  const uint64_t next_min = (threadIdx.x < TB - 1) ? rev_min[TB - 2 - threadIdx.x] : ~0ull;
+  const uint32_t next_min = (threadIdx.x < TB - 1) ? (uint32_t)min(rev_min[TB - 2 - threadIdx.x], 0xFFFFFFFFull)
+                                                   : 0xFFFFFFFFu;
+  const uint64_t fs = first_start, le = last_end;
   // run lengths, blocked -> LDS, then striped (coalesced) keys, ids and outputs
   uint32_t *wl = (uint32_t *)cell;           // cell[] is no longer needed; reuse it
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const int li = t0 + i;
-    if (li < (int)tile_n) wl[li] = (uint32_t)(min(en[i], next_min) - max(st[i], prev_max));
+    if (li < (int)tile_n) {
+      const uint32_t sl = max(st[i], prev_max), el = min(en[i], next_min);
+      const uint64_t sg = sl ? base + sl - 1 : fs;
+      const uint64_t eg = (el == tile_n) ? le : base + el;
+      wl[li] = (uint32_t)(eg - sg);
+    }
   }
   __syncthreads();
   const int sdb = 3 * a.D;
-  uint32_t ids[ITEMS], snaps[ITEMS];
+  constexpr int DCH = 8;                     // ids loaded together
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    ids[i] = sidx[min(base + (uint64_t)(i * TB + threadIdx.x), N - 1)];
-    snaps[i] = 0u;
-  }
-  if (a.n_snap > 1) {
+  for (int c = 0; c < ITEMS; c += DCH) {
+    uint32_t ids[DCH], snaps[DCH];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-      snaps[i] = (uint32_t)((uint64_t)skey[min(base + (uint64_t)(i * TB + threadIdx.x), N - 1)] >> sdb);
-  }
+    for (int i = 0; i < DCH; ++i) {
+      ids[i] = sidx[min(base + (uint64_t)((c + i) * TB + threadIdx.x), N - 1)];
+      snaps[i] = 0u;
+    }
+    if (a.n_snap > 1) {
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const int li = i * TB + threadIdx.x;
-    if (li < (int)tile_n) {
-      const uint64_t e = base + li;
-      const uint32_t w = wl[li];
-      const uint64_t U = particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed);
-      w_out[e] = w;
-      kb_out[e] = (uint16_t)kbin(selection_key(U, w, a.alpha));
+      for (int i = 0; i < DCH; ++i)
+        snaps[i] = (uint32_t)((uint64_t)skey[min(base + (uint64_t)((c + i) * TB + threadIdx.x), N - 1)] >> sdb);
+    }
+#pragma unroll
+    for (int i = 0; i < DCH; ++i) {
+      const int li = (c + i) * TB + threadIdx.x;
+      if (li < (int)tile_n) {
+        const uint64_t e = base + li;
+        const uint32_t w = wl[li];
+        const uint64_t U = particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed);
+        w_out[e] = w;
+        kb_out[e] = (uint16_t)kbin(selection_key(U, w, a.alpha));
+      }
     }
   }
 }

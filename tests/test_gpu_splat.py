@@ -174,3 +174,18 @@ def test_lod_render_equals_render_of_decoded_points(n):
             assert c == min(cap, total)
             ref = lib.splat(x[:c], y[:c], z[:c], m[:c], cam).cpu().numpy()
             assert np.array_equal(img.view(np.int32), ref.view(np.int32)), (n, len(lst), cap)
+
+
+def test_splat_maximum_tile_count():
+    """8,192 tiles of 16x16 (2040x1018, the limit; 13-bit tile
+    ids in the wave matching) and a ragged last tile column and row; one more
+    tile column is refused as unsupported."""
+    s = synth.small_clustered(40000, 74)
+    W, H = 2040, 1018
+    for cam, ocam in ((lib.Camera.ortho(W, H), osplat.Camera(0, W, H)),):
+        img = lib.splat(*to_dev(s), cam).cpu().numpy()
+        ref = osplat.render(ocam, s.x, s.y, s.z, s.m)
+        err, zeros_ok = image_rel_err(img, ref)
+        assert zeros_ok and err <= TOL, err
+    with pytest.raises(RuntimeError):
+        lib.splat(*to_dev(s), lib.Camera.ortho(2064, 1024))
