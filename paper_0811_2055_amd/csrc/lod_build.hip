@@ -810,6 +810,7 @@ constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
 constexpr int ILP = 8;        // list entries in flight per thread in the candidate passes
 constexpr int SILP = 8;       // candidates per lane per wave step
+constexpr int OILP = 4;       // list entries per thread per step of the output pass
 constexpr int QCAP = 2048;    // bin-b0 candidates queued in LDS by the collect pass
 
 // A list entry packs a sorted position (low 32 bits) and its key bin (next 16).
@@ -817,6 +818,7 @@ struct SelArgs {
   uint64_t *lists;            // top-(n+1) lists by selecting rank
   uint32_t n_minus_1;         // N - 1
   double *mhat;               // float64 mass scratch, one row of n per block
+  uint32_t *src;              // source of each list entry, one row of n+1 per block
 };
 
 __device__ __forceinline__ uint32_t entry_pos(uint64_t e, uint32_t n_minus_1) {
@@ -829,6 +831,11 @@ struct Segs {
   uint64_t base[9];   // start sorted position (range) or list offset (list)
   uint32_t len[9];
   uint32_t is_list[9];
+  // list segments: the child's witness position, its first stored point and
+  // its octant (the bit each cell coordinate gains from parent to child)
+  uint32_t cwit[9];
+  uint64_t cob[9];
+  uint32_t coct[9];
 };
 
 __device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArgs &t, uint32_t v, Segs &g) {
@@ -843,6 +850,7 @@ __device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArg
       const uint32_t u = fc + k;
       if (t.part_count[u] > n) {
         g.base[ns] = (uint64_t)t.sel_idx[u] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
+        g.cwit[ns] = t.wit[u]; g.cob[ns] = t.pt_begin[u]; g.coct[ns] = (uint32_t)(t.prefix[u] & 7u);
         ++ns;
       } else if (ns > 0 && !g.is_list[ns - 1]) {
         g.len[ns - 1] += (uint32_t)t.part_count[u];   // siblings are adjacent in sorted order
@@ -1175,6 +1183,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const bool out_ok = a.counts[1] <= a.point_cap;
   uint64_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
   double *mrow = sa.mhat + (uint64_t)blockIdx.x * n;
+  uint32_t *srow = sa.src + (uint64_t)blockIdx.x * (n + 1);
   const uint64_t ob = t.pt_begin[v];
   const int d = t.depth[v];
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
@@ -1195,7 +1204,17 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
         const uint64_t bal = __ballot(tk);
         const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
         run += (uint32_t)__popcll(bal);
-        if (tk && o <= n) out[o] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
+        if (tk && o <= n) {
+          out[o] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
+          // a list entry other than the child's witness is one of the child's
+          // stored points: record where (segment, index among its points)
+          uint32_t src = NONE;
+          if (g.is_list[k] && pos[u] != g.cwit[k] && n < (1u << 24)) {
+            const uint32_t jc = j0 + u * WAVE + lane;
+            src = ((uint32_t)k << 24) | (jc - (pos[u] > g.cwit[k] ? 1u : 0u));
+          }
+          srow[o] = src;
+        }
       }
     }
   }
@@ -1204,28 +1223,80 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   // unscaled float64 masses, kept in this block's scratch row
   double acc = 0.0;
   if (out_ok) {
-    for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * SILP) {
-      uint32_t pos[SILP];
+    bool lists = false;
+    for (int k = 0; k < (int)g.nseg; ++k) lists |= g.is_list[k] != 0;
+    if (!lists) {
+      // only ranges: every entry is gathered from the sorted arrays
+      for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * SILP) {
+        uint32_t pos[SILP];
 #pragma unroll
-      for (int u = 0; u < SILP; ++u) pos[u] = entry_pos(out[min(j0 + u * BS, n)], sa.n_minus_1);
-      PointIn q[SILP];
-      uint32_t wv[SILP];
-      float mm[SILP];
+        for (int u = 0; u < SILP; ++u) pos[u] = entry_pos(out[min(j0 + u * BS, n)], sa.n_minus_1);
+        PointIn q[SILP];
+        uint32_t wv[SILP];
+        float mm[SILP];
 #pragma unroll
-      for (int u = 0; u < SILP; ++u) {
-        q[u] = read_point(s, pos[u]);
-        wv[u] = s.w[pos[u]];
-        mm[u] = s.m[pos[u]];
+        for (int u = 0; u < SILP; ++u) {
+          q[u] = read_point(s, pos[u]);
+          wv[u] = s.w[pos[u]];
+          mm[u] = s.m[pos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < SILP; ++u) {
+          const uint32_t jl = j0 + u * BS;
+          if (jl > n || pos[u] == pt) continue;
+          const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
+          const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
+          store_point_pos(a, t, q[u], ob + j, d);
+          mrow[j] = mhat;
+          acc += mhat;
+        }
       }
+    } else {
+      for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * OILP) {
+        uint32_t pos[OILP], src[OILP];
 #pragma unroll
-      for (int u = 0; u < SILP; ++u) {
-        const uint32_t jl = j0 + u * BS;
-        if (jl > n || pos[u] == pt) continue;
-        const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
-        const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
-        store_point_pos(a, t, q[u], ob + j, d);
-        mrow[j] = mhat;
-        acc += mhat;
+        for (int u = 0; u < OILP; ++u) {
+          const uint32_t jl = min(j0 + u * BS, n);
+          pos[u] = entry_pos(out[jl], sa.n_minus_1);
+          src[u] = srow[jl];
+        }
+        // entries from a child's list take id and codes from the child's stored
+        // point (contiguous reads; each code gains the child's octant bit on
+        // top); the others are gathered from the sorted arrays.  Every lane
+        // issues both sets of loads at clamped addresses (the unused set hits
+        // one cached line) and the mass inputs.
+        PointIn q[OILP];
+        uint32_t cid[OILP], cq[OILP][3], wv[OILP];
+        float mm[OILP];
+#pragma unroll
+        for (int u = 0; u < OILP; ++u) {
+          const bool fc = src[u] != NONE;
+          const uint32_t kk = fc ? src[u] >> 24 : 0u;
+          const uint64_t ci = fc ? g.cob[kk] + (src[u] & 0xFFFFFFu) : 0u;
+          q[u] = read_point(s, fc ? pt : pos[u]);
+          cid[u] = t.pt_id[ci];
+          cq[u][0] = t.qx[ci]; cq[u][1] = t.qy[ci]; cq[u][2] = t.qz[ci];
+          wv[u] = s.w[pos[u]];
+          mm[u] = s.m[pos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < OILP; ++u) {
+          const uint32_t jl = j0 + u * BS;
+          if (jl > n || pos[u] == pt) continue;
+          const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
+          const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
+          if (src[u] != NONE) {
+            const uint32_t oc = g.coct[src[u] >> 24];
+            t.pt_id[ob + j] = cid[u];
+            t.qx[ob + j] = (uint16_t)((cq[u][0] >> 1) | ((oc & 1u) << 15));
+            t.qy[ob + j] = (uint16_t)((cq[u][1] >> 1) | (((oc >> 1) & 1u) << 15));
+            t.qz[ob + j] = (uint16_t)((cq[u][2] >> 1) | (((oc >> 2) & 1u) << 15));
+          } else {
+            store_point_pos(a, t, q[u], ob + j, d);
+          }
+          mrow[j] = mhat;
+          acc += mhat;
+        }
       }
     }
   }
@@ -1399,6 +1470,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.lists = take(8 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)) + 16);
   L.sel_rows = (uint32_t)std::min<uint64_t>(4096, N / ((uint64_t)p.n + 1) + n_snap + 1);
   L.mhat = take(8 * (size_t)L.sel_rows * p.n);
+  L.src = take(4 * (size_t)L.sel_rows * ((uint64_t)p.n + 1));
   L.total = off;
   return L;
 }
@@ -1482,7 +1554,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
   LOD_LAUNCH(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
 
-  SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1), (double *)(W + L.mhat)};
+  SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1), (double *)(W + L.mhat), (uint32_t *)(W + L.src)};
   const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
   // one scratch row of float64 masses per block
   const unsigned sel_grid = (unsigned)std::min<uint64_t>(L.sel_rows, per_level + 1);

@@ -18,7 +18,7 @@ struct BuildLayout {
   size_t lvl, lsel, cs, sel_idx, wit, pend, bflag, bscan, bottom, ctl;
   size_t lists;
   uint32_t sel_rows;             // blocks of a selection launch (rows of mhat)
-  size_t mhat;
+  size_t mhat, src;
   size_t total;
 };
 
