@@ -249,13 +249,26 @@ struct Blob {
   int tx0, ty0, ntx, nty;
 };
 
+// Pixels [lo, hi] (clipped to [0, size)) that contain every pixel a blob at
+// screen coordinate t can cover: the float32 offset test |t - (i + 1/2)| <= R
+// is decided to within 2^-8 for |t| < 2^15 (the camera limits), so a margin
+// of 1/100 pixel makes the range conservative.  A tile this admits without a
+// covered pixel only adds a pair whose rows are zero in the accumulation.
+__device__ __forceinline__ bool cover_range(const Cam &c, float t, uint32_t size, int &lo, int &hi) {
+  const float lim = c.R + 4.0f;
+  if (!(t > -lim && t < (float)size + lim)) return false;
+  lo = max((int)ceilf(t - 0.5f - c.R - 0.01f), 0);
+  hi = min((int)floorf(t - 0.5f + c.R + 0.01f), (int)size - 1);
+  return lo <= hi;
+}
+
 __device__ __forceinline__ Blob make_blob(const Cam &c, bool valid, float px, float py, float pz, float pm) {
   Blob b{0.0f, 0.0f, pm, 0, 0, 0, 0};
   if (!valid) return b;
   float xc, yc, zc;
   if (!project(c, px, py, pz, b.u, b.v, xc, yc, zc)) return b;
   int i0, i1, j0, j1;
-  if (!axis_range(c, b.u, c.W, i0, i1) || !axis_range(c, b.v, c.H, j0, j1)) return b;
+  if (!cover_range(c, b.u, c.W, i0, i1) || !cover_range(c, b.v, c.H, j0, j1)) return b;
   b.tx0 = i0 / TS; b.ty0 = j0 / TS;
   b.ntx = i1 / TS - b.tx0 + 1;
   b.nty = j1 / TS - b.ty0 + 1;
@@ -767,7 +780,7 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   if (nt == 0 || nt > SPLAT_MAX_TILES) return LOD_EUNSUPPORTED;
   L.n_tiles = (uint32_t)nt;
   const double R = (double)(sp.radius_sigmas * sp.sigma_px);
-  const uint64_t width = 2 * (uint64_t)std::floor(R) + 2;        // pixels a blob can span
+  const uint64_t width = 2 * (uint64_t)std::ceil(R) + 3;         // pixels a blob's tile range can span
   const uint64_t tpa = std::min<uint64_t>((width + TS - 1) / TS + 1, std::max(L.tiles_x, L.tiles_y));
   L.max_points = max_points;
   L.max_pairs = std::max<uint64_t>(1, max_points * tpa * tpa);
