@@ -215,21 +215,34 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
   const uint64_t tile = blockIdx.x;
   const uint64_t tbase = tile * STILE;
   const uint64_t ebase = tbase + (uint64_t)w * PER_WAVE + lane;
+  // this tile's global digit offsets, loaded first (every thread, clamped
+  // index) so that waiting for them does not wait for the element loads
+  const uint32_t g0 = thist[(uint64_t)min((int)threadIdx.x, RADIX - 1) * n_tiles + tile];
   uint32_t kk[ROUNDS], ii[ROUNDS];
   uint64_t ll[ROUNDS];
   float mm[ROUNDS];
+  if (FIRST) {
+    // every load of the thread first (the key computation branches on the
+    // snapshot count, and a load issued after a branch waits for it)
+    float xs[ROUNDS], ys[ROUNDS], zs[ROUNDS];
 #pragma unroll
-  for (int r = 0; r < ROUNDS; ++r) {
-    // clamped, unconditional loads; lanes past N are masked out below
-    const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
-    if (FIRST) {
-      const float xe = in.x[e], ye = in.y[e], ze = in.z[e];
-      mm[r] = in.m[e];
-      const PKey pk = particle_key(a, xe, ye, ze, mm[r], e);
+    for (int r = 0; r < ROUNDS; ++r) {
+      // clamped, unconditional loads; lanes past N are masked out below
+      const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
+      xs[r] = in.x[e]; ys[r] = in.y[e]; zs[r] = in.z[e]; mm[r] = in.m[e];
+    }
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
+      const PKey pk = particle_key(a, xs[r], ys[r], zs[r], mm[r], e);
       kk[r] = pk.key;
       ll[r] = pk.lo;
       ii[r] = (uint32_t)(ebase + (uint64_t)r * WAVE);
-    } else {
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
       kk[r] = in.key[e];
       ii[r] = in.idx[e];
       ll[r] = in.lo[e];
@@ -237,7 +250,7 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
     }
   }
   for (int i = threadIdx.x; i < NW * RADIX; i += STB) (&wcnt[0][0])[i] = 0;
-  if (threadIdx.x < RADIX) gofs[threadIdx.x] = thist[(uint64_t)threadIdx.x * n_tiles + tile];
+  if (threadIdx.x < RADIX) gofs[threadIdx.x] = g0;
   __syncthreads();
 
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
@@ -260,6 +273,12 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
     dig[r] = d;
     rnk[r] = old + below;
   }
+  // The payload loads have landed during the ranking: wait for them here,
+  // before any store is issued.  Loads and stores share one counter, so a
+  // wait placed where the values are first used would also wait for the
+  // stores of the fields written before.  (Encoding: vmcnt 0, expcnt and
+  // lgkmcnt left at their maxima.)
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
   // per digit: wave prefix (in place) and tile total
   uint32_t tot = 0;
@@ -281,21 +300,29 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
   for (int r = 0; r < ROUNDS; ++r) slot[r] = bin_start[dig[r]] + wcnt[w][dig[r]] + rnk[r];
   const uint32_t tile_n = (uint32_t)min((uint64_t)STILE, N - tbase);
 
-  // keys (with their output positions), then ids, fractions, masses
+  // keys (with their output positions), then ids, fractions, masses.  LDS
+  // reads are unconditional (slots past the tile hold stale values) and
+  // issued together; only the stores are predicated.
   uint64_t gpos[SITEMS];
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r)
     if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = kk[r];
   __syncthreads();
+  {
+    uint32_t k[SITEMS], go[SITEMS], bs[SITEMS];
 #pragma unroll
-  for (int i = 0; i < SITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
-    gpos[i] = ~0ull;
-    if (s < tile_n) {
-      const uint32_t k = (uint32_t)stage[s];
-      const uint32_t d = (k >> shift) & 0xFFu;
-      gpos[i] = (uint64_t)gofs[d] + (s - bin_start[d]);
-      key_out[gpos[i]] = k;
+    for (int i = 0; i < SITEMS; ++i) k[i] = (uint32_t)stage[i * STB + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < SITEMS; ++i) {
+      const uint32_t d = (k[i] >> shift) & 0xFFu;
+      go[i] = gofs[d];
+      bs[i] = bin_start[d];
+    }
+#pragma unroll
+    for (int i = 0; i < SITEMS; ++i) {
+      const uint32_t s = (uint32_t)i * STB + threadIdx.x;
+      gpos[i] = (uint64_t)go[i] + (s - bs[i]);
+      if (s < tile_n) key_out[gpos[i]] = k[i];
     }
   }
   __syncthreads();
@@ -303,30 +330,39 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
   for (int r = 0; r < ROUNDS; ++r)
     if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = ii[r];
   __syncthreads();
+  {
+    uint32_t v[SITEMS];
 #pragma unroll
-  for (int i = 0; i < SITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
-    if (s < tile_n) idx_out[gpos[i]] = (uint32_t)stage[s];
+    for (int i = 0; i < SITEMS; ++i) v[i] = (uint32_t)stage[i * STB + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < SITEMS; ++i)
+      if ((uint32_t)i * STB + threadIdx.x < tile_n) idx_out[gpos[i]] = v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r)
     if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = ll[r];
   __syncthreads();
+  {
+    uint64_t v[SITEMS];
 #pragma unroll
-  for (int i = 0; i < SITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
-    if (s < tile_n) lo_out[gpos[i]] = stage[s];
+    for (int i = 0; i < SITEMS; ++i) v[i] = stage[i * STB + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < SITEMS; ++i)
+      if ((uint32_t)i * STB + threadIdx.x < tile_n) lo_out[gpos[i]] = v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r)
     if (ebase + (uint64_t)r * WAVE < N) stage[slot[r]] = (uint64_t)__float_as_uint(mm[r]);
   __syncthreads();
+  {
+    uint32_t v[SITEMS];
 #pragma unroll
-  for (int i = 0; i < SITEMS; ++i) {
-    const uint32_t s = (uint32_t)i * STB + threadIdx.x;
-    if (s < tile_n) m_out[gpos[i]] = __uint_as_float((uint32_t)stage[s]);
+    for (int i = 0; i < SITEMS; ++i) v[i] = (uint32_t)stage[i * STB + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < SITEMS; ++i)
+      if ((uint32_t)i * STB + threadIdx.x < tile_n) m_out[gpos[i]] = __uint_as_float(v[i]);
   }
 }
 
@@ -544,6 +580,7 @@ struct TreeArgs {
   uint32_t *lvl;      // [D+3] level starts; lvl[d+1] = end of level d
   uint32_t *cs;       // [node_cap * 9] octant starts (sorted positions) of internal nodes
   uint32_t *sel_idx;  // [node_cap] rank among all selecting nodes (levels in order), or NONE
+  uint32_t *sel_node; // [node_cap] node of each selecting rank (NONE if it was not emitted)
   uint32_t *wit;      // [node_cap] witness sorted position, or NONE
   uint32_t *pend;     // [node_cap] number of selecting children not yet reduced
   uint32_t *lsel;     // [D+3] selecting nodes at levels < d (cumulative)
@@ -585,7 +622,11 @@ __global__ __launch_bounds__(1024) void k_roots(BuildArgs a, TreeArgs t, const u
         t.prefix[v] = s; t.depth[v] = 0; t.parent[v] = NONE; t.first_child[v] = NONE;
         t.child_mask[v] = 0; t.part_begin[v] = lo; t.part_count[v] = hi - lo;
         t.sel_idx[v] = se ? base_sel + os : NONE; t.wit[v] = NONE; t.pend[v] = 0;
-      } else set_status(a, LOD_STATUS_CAPACITY);
+        if (se && base_sel + os < a.node_cap) t.sel_node[base_sel + os] = v;
+      } else {
+        set_status(a, LOD_STATUS_CAPACITY);
+        if (se && base_sel + os < a.node_cap) t.sel_node[base_sel + os] = NONE;
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) { base_nodes += tot_n; base_sel += tot_s; }
@@ -630,10 +671,14 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
   for (uint32_t v0 = b; v0 < e; v0 += blockDim.x) {
     const uint32_t v = v0 + threadIdx.x;
     uint32_t nkids = 0, nsel = 0, mask = 0;
+    // unconditional loads at a clamped node (a load under a branch is waited
+    // for on its own); octant starts of a node that is not split are unused
+    const uint32_t vc = min(v, e - 1);
+    const uint64_t pc = t.part_count[vc];
     uint32_t st[9];
-    if (v < e && t.part_count[v] > a.n && d < a.D) {
 #pragma unroll
-      for (int o = 0; o < 9; ++o) st[o] = t.cs[(uint64_t)v * 9 + o];
+    for (int o = 0; o < 9; ++o) st[o] = t.cs[(uint64_t)vc * 9 + o];
+    if (v < e && pc > a.n && d < a.D) {
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
         const uint32_t c = st[o + 1] - st[o];
@@ -652,6 +697,8 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
         if ((uint64_t)c + nkids > a.node_cap) {
           set_status(a, LOD_STATUS_CAPACITY);
           t.first_child[v] = NONE;
+          for (uint32_t j = 0; j < nsel; ++j)
+            if (sidx + j < a.node_cap) t.sel_node[sidx + j] = NONE;
         } else {
           t.first_child[v] = c;
           const uint64_t pfx = t.prefix[v] << 3;
@@ -665,7 +712,12 @@ __global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
             t.child_mask[c] = 0;
             t.part_begin[c] = st[o];
             t.part_count[c] = cnt;
-            t.sel_idx[c] = cnt > a.n ? sidx++ : NONE;
+            if (cnt > a.n) {
+              if (sidx < a.node_cap) t.sel_node[sidx] = c;
+              t.sel_idx[c] = sidx++;
+            } else {
+              t.sel_idx[c] = NONE;
+            }
             t.wit[c] = NONE;
             t.pend[c] = 0;
             ++c;
@@ -755,8 +807,36 @@ __device__ __forceinline__ uint64_t exact_K(const BuildArgs &a, const Sorted &s,
   return selection_key(U, s.w[p], a.alpha);
 }
 
-constexpr int LILP = 4;       // particles per thread per step in k_leaves
+constexpr int LILP = 4;       // particles per thread per step when copying a leaf
 
+// Copies leaf v's particles to its stored points (codes at the leaf's depth,
+// float32 masses as given), whole block.
+__device__ __forceinline__ void copy_leaf_points(const BuildArgs &a, const TreeArgs &t, const Sorted &s,
+                                                 uint32_t v) {
+  const uint64_t b = t.part_begin[v], c = t.part_count[v];
+  const uint64_t ob = t.pt_begin[v];
+  const int d = t.depth[v];
+  const uint32_t BS = blockDim.x;
+  for (uint64_t i0 = threadIdx.x; i0 < c; i0 += (uint64_t)BS * LILP) {
+    float mm[LILP];
+    PointIn q[LILP];
+#pragma unroll
+    for (int u = 0; u < LILP; ++u) {
+      const uint64_t pos = b + min(i0 + (uint64_t)u * BS, c - 1);
+      mm[u] = s.m[pos];
+      q[u] = read_point(s, pos);
+    }
+#pragma unroll
+    for (int u = 0; u < LILP; ++u) {
+      const uint64_t i = i0 + (uint64_t)u * BS;
+      if (i < c) store_point(a, t, q[u], ob + i, d, mm[u]);
+    }
+  }
+}
+
+// Leaves: float64 mass of every leaf and, with COPY, its stored points (the
+// per-level schedule copies them inside the selection launches instead).
+template <bool COPY>
 __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s) {
   __shared__ double red[TB / WAVE + 1];
   const uint32_t nn = t.lvl[a.D + 1];
@@ -764,26 +844,38 @@ __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s
   for (uint32_t v = blockIdx.x; v < nn; v += gridDim.x) {
     if (t.first_child[v] != NONE) continue;
     const uint64_t b = t.part_begin[v], c = t.part_count[v];
-    const bool copy = c <= a.n && cap_ok;
+    const bool copy = COPY && c <= a.n && cap_ok;
     const uint64_t ob = t.pt_begin[v];
     const int d = t.depth[v];
     double acc = 0.0;
-    for (uint64_t i0 = threadIdx.x; i0 < c; i0 += TB * LILP) {
-      float mm[LILP];
-      PointIn q[LILP];
+    if (copy) {
+      for (uint64_t i0 = threadIdx.x; i0 < c; i0 += TB * LILP) {
+        float mm[LILP];
+        PointIn q[LILP];
 #pragma unroll
-      for (int u = 0; u < LILP; ++u) {
-        const uint64_t pos = b + min(i0 + (uint64_t)u * TB, c - 1);
-        mm[u] = s.m[pos];
-        if (copy) q[u] = read_point(s, pos);
-      }
-#pragma unroll
-      for (int u = 0; u < LILP; ++u) {
-        const uint64_t i = i0 + (uint64_t)u * TB;
-        if (i < c) {
-          acc += (double)mm[u];
-          if (copy) store_point(a, t, q[u], ob + i, d, mm[u]);
+        for (int u = 0; u < LILP; ++u) {
+          const uint64_t pos = b + min(i0 + (uint64_t)u * TB, c - 1);
+          mm[u] = s.m[pos];
+          q[u] = read_point(s, pos);
         }
+#pragma unroll
+        for (int u = 0; u < LILP; ++u) {
+          const uint64_t i = i0 + (uint64_t)u * TB;
+          if (i < c) {
+            acc += (double)mm[u];
+            store_point(a, t, q[u], ob + i, d, mm[u]);
+          }
+        }
+      }
+    } else {
+      constexpr int MILP = 4 * LILP;
+      for (uint64_t i0 = threadIdx.x; i0 < c; i0 += TB * MILP) {
+        float mm[MILP];
+#pragma unroll
+        for (int u = 0; u < MILP; ++u) mm[u] = s.m[b + min(i0 + (uint64_t)u * TB, c - 1)];
+#pragma unroll
+        for (int u = 0; u < MILP; ++u)
+          if (i0 + (uint64_t)u * TB < c) acc += (double)mm[u];
       }
     }
     const double M = block_reduce_sum<double>(acc, red);
@@ -1317,12 +1409,60 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
 }
 
 // mode 1: one launch per level, one block per selecting node of that level.
-__global__ __launch_bounds__(1024) void k_select_level(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d) {
+// The stored points of the leaves (needed by nothing in the build) are copied
+// by the same launches, so that the copy fills the chip while a level's last
+// nodes are being selected.  Block j of every launch owns the nodes
+// v = k G + j (G blocks per launch, k = 0, 1, ...) and resumes at its cursor
+// leaf_ctl[j].  Above level 0 a block copies only while the level still has
+// nodes being selected (done count in leaf_ctl[G + d]), and a block that
+// selected a node only once every block with a node has started (count in
+// leaf_ctl[G + D + 1 + d]), so that copying never holds back the dispatch of a
+// selecting block.  Level 0, launched last, copies what is left.  No block
+// waits for another.  leaf_ctl starts at zero.
+__global__ __launch_bounds__(1024) void k_select_level(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa, int d,
+                                                       uint32_t *leaf_ctl) {
+  __shared__ uint32_t sh_go;
   const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
-  for (uint32_t v = b + blockIdx.x; v < e; v += gridDim.x) {
-    if (t.part_count[v] <= a.n) continue;
+  const uint32_t G = gridDim.x;
+  uint32_t *done = leaf_ctl ? leaf_ctl + G : nullptr;
+  uint32_t *started = leaf_ctl ? leaf_ctl + G + a.D + 1 : nullptr;
+  // the level's selecting nodes by rank, so that the blocks with a node come first
+  const uint32_t r0 = t.lsel[d];
+  const uint32_t r1 = (uint32_t)min((uint64_t)t.lsel[d + 1], a.node_cap);
+  const uint32_t sel_blocks = r1 > r0 ? min(G, r1 - r0) : 0u;
+  if (started && blockIdx.x < sel_blocks && threadIdx.x == 0) atomicAdd(&started[d], 1u);
+  for (uint32_t r = r0 + blockIdx.x; r < r1; r += G) {
+    const uint32_t v = t.sel_node[r];
+    if (v == NONE || v < b || v >= e || t.part_count[v] <= a.n) continue;
     select_node(a, t, s, sa, v);
+    if (done && threadIdx.x == 0) atomicAdd(&done[d], 1u);
   }
+  if (!leaf_ctl) return;
+  const uint32_t total = t.lsel[d + 1] - t.lsel[d];   // selecting nodes of this level
+  if (d > 0 && blockIdx.x < sel_blocks) {
+    __syncthreads();
+    if (threadIdx.x == 0)
+      sh_go = __hip_atomic_load(&started[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= sel_blocks;
+    __syncthreads();
+    if (!sh_go) return;
+  }
+  const uint32_t nn = t.lvl[a.D + 1];
+  const bool cap_ok = a.counts[1] <= a.point_cap;
+  uint32_t k = leaf_ctl[blockIdx.x];
+  while (true) {
+    const uint64_t v = (uint64_t)k * G + blockIdx.x;
+    if (v >= nn) break;
+    if (d > 0) {
+      __syncthreads();
+      if (threadIdx.x == 0)
+        sh_go = __hip_atomic_load(&done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < total;
+      __syncthreads();
+      if (!sh_go) break;
+    }
+    if (t.first_child[v] == NONE && t.part_count[v] <= a.n && cap_ok) copy_leaf_points(a, t, s, (uint32_t)v);
+    ++k;
+  }
+  if (threadIdx.x == 0) leaf_ctl[blockIdx.x] = k;
 }
 
 // mode 0: one launch per selecting node.
@@ -1461,6 +1601,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.lsel = take(4 * (size_t)(p.max_depth + 4));
   L.cs = take(4 * 9 * (size_t)L.node_cap);
   L.sel_idx = take(4 * (size_t)L.node_cap);
+  L.sel_node = take(4 * (size_t)L.node_cap);
   L.wit = take(4 * (size_t)L.node_cap);
   L.pend = take(4 * (size_t)L.node_cap);
   L.bflag = take(4 * (size_t)(L.node_cap + 1));
@@ -1471,6 +1612,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.sel_rows = (uint32_t)std::min<uint64_t>(4096, N / ((uint64_t)p.n + 1) + n_snap + 1);
   L.mhat = take(8 * (size_t)L.sel_rows * p.n);
   L.src = take(4 * (size_t)L.sel_rows * ((uint64_t)p.n + 1));
+  L.leafctl = take(4 * ((size_t)L.sel_rows + 2 * (p.max_depth + 1)));   // leaf-copy cursors, level counts
   L.total = off;
   return L;
 }
@@ -1536,6 +1678,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   t.pt_begin = out.pt_begin; t.pt_count = out.pt_count; t.node_mass = out.node_mass;
   t.pt_id = out.pt_id; t.qx = out.qx; t.qy = out.qy; t.qz = out.qz; t.pt_mass = out.pt_mass;
   t.lvl = lvl; t.cs = (uint32_t *)(W + L.cs); t.sel_idx = (uint32_t *)(W + L.sel_idx);
+  t.sel_node = (uint32_t *)(W + L.sel_node);
   t.wit = (uint32_t *)(W + L.wit); t.pend = (uint32_t *)(W + L.pend); t.lsel = (uint32_t *)(W + L.lsel);
 
   const int D = (int)p.max_depth;
@@ -1552,7 +1695,14 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   LOD_LAUNCH(k_ptfinish, dim3(1), dim3(1), 0, st, a, t);
 
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
-  LOD_LAUNCH(k_leaves, dim3(node_grid), dim3(TB), 0, st, a, t, s);
+  // the per-level schedule copies the leaves' points inside its selection launches
+  uint32_t *leaf_ctl = p.mode == 1 ? (uint32_t *)(W + L.leafctl) : nullptr;
+  if (leaf_ctl) {
+    fill_u32(leaf_ctl, (uint64_t)L.sel_rows + 2 * (p.max_depth + 1), 0, st);
+    LOD_LAUNCH(k_leaves<false>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
+  } else {
+    LOD_LAUNCH(k_leaves<true>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
+  }
 
   SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1), (double *)(W + L.mhat), (uint32_t *)(W + L.src)};
   const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
@@ -1601,7 +1751,8 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
     } else {
       // a level of at most 64 nodes cannot fill the chip: give each node 1024 threads
       const bool few = d <= 2 && ((uint64_t)n_snap << (3 * d)) <= 64;
-      LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(few ? 1024u : sel_threads), 0, st, a, t, s, sa, d);
+      LOD_LAUNCH(k_select_level, dim3(sel_grid), dim3(few ? 1024u : sel_threads), 0, st, a, t, s, sa, d,
+                 leaf_ctl);
     }
   }
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
