@@ -41,7 +41,7 @@ struct Cam {
   float norm;       // 1 / (2 pi sigma^2)
   float inv_s2;     // 1 / sigma^2
   int win;          // candidate half-window, ceil(R) + 2
-  int narrow;       // 1 when a blob covers at most 8 pixels per axis (R < 4)
+  int narrow;       // 1 when a blob covers fewer than 8 pixels per axis (R < 3.98)
   float kexp2;      // -log2(e) / (2 sigma^2): Gaussian factor = exp2(o^2 kexp2)
   uint32_t tiles_x, tiles_y;
 };
@@ -61,7 +61,7 @@ Cam make_cam(const lod_camera &c, const splat_params &sp, const lodh::SplatLayou
   k.norm = (float)(1.0 / (2.0 * M_PI * s64 * s64));
   k.inv_s2 = (float)(1.0 / (s64 * s64));
   k.win = (int)std::ceil((double)k.R) + 2;
-  k.narrow = (double)k.R < 4.0 ? 1 : 0;
+  k.narrow = (double)k.R < 3.98 ? 1 : 0;
   k.kexp2 = (float)(-1.4426950408889634 / (2.0 * s64 * s64));
   if (L) { k.tiles_x = L->tiles_x; k.tiles_y = L->tiles_y; }
   return k;
@@ -494,7 +494,6 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
     const uint32_t nsl = sl + gridDim.x;
     const uint2 nsd = table[min(nsl, total_slices - 1)];
     const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
-    const int txe = min(tx0 + TS, (int)c.W) - 1, tye = min(ty0 + TS, (int)c.H) - 1;
     float s = 0.0f, cc = 0.0f;
     for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
       const bool have = c0 + threadIdx.x < pe;
@@ -506,19 +505,21 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
         const uint64_t qc = min(q, last);
         nu = bu[qc]; nv = bv[qc]; nm = bm[qc];
       }
-      // phase A
-      int i0 = 1, i1 = 0, j0 = 1, j1 = 0;
-      if (have && clip_range(u, c.R, tx0, txe, i0, i1)) {
-        if (!clip_range(v, c.R, ty0, tye, j0, j1)) { i0 = 1; i1 = 0; }
-      }
-      // rows are zero outside the truncation square; the Gaussian factor is
-      // the hardware exp2 of o^2 (-log2 e / 2 sigma^2) (relative error ~3e-7,
-      // ample for 1e-5)
+      // phase A: rows are zero outside the truncation square.  A pixel is
+      // covered when its float32 offset fl(t - (i + 1/2)) lies in [-R, R],
+      // tested pixel by pixel (the covered pixels of an axis form one run).
+      // Pixels past the image edge are computed and dropped by the final sum.
+      // The Gaussian factor is the hardware exp2 of o^2 (-log2 e / 2 sigma^2)
+      // (relative error ~3e-7, ample for 1e-5); lanes past the slice carry
+      // mass 0.
+      const float R = c.R;
       const float w = m * c.norm;
       if (c.narrow) {
-        // at most 8 covered pixels per axis: zero the row, then write an
-        // 8-wide window that holds the covered run
-        const int wx = min(max(i0 - tx0, 0), TS - 8), wy = min(max(j0 - ty0, 0), TS - 8);
+        // fewer than 8 covered pixels per axis: zero the row, then write an
+        // 8-wide window from a lower bound of the run's first pixel (float32
+        // offsets are within 1/100 pixel of the exact ones)
+        const int lx = (int)ceilf(u - 0.5f - R - 0.01f), ly = (int)ceilf(v - 0.5f - R - 0.01f);
+        const int wx = min(max(lx - tx0, 0), TS - 8), wy = min(max(ly - ty0, 0), TS - 8);
 #pragma unroll
         for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
 #pragma unroll
@@ -530,8 +531,8 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
           // a 0/1 factor is exact and keeps the code branch-free
           const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
-          gx[threadIdx.x][wx + q] = ex * (float)(i >= i0 && i <= i1);
-          gy[threadIdx.x][wy + q] = (w * ey) * (float)(j >= j0 && j <= j1);
+          gx[threadIdx.x][wx + q] = ex * (float)(ox >= -R && ox <= R);
+          gy[threadIdx.x][wy + q] = (w * ey) * (float)(oy >= -R && oy <= R);
         }
       } else {
 #pragma unroll
@@ -541,8 +542,8 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
           const float oy = v - ((float)j + 0.5f);
           const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
-          gx[threadIdx.x][e] = (i >= i0 && i <= i1) ? ex : 0.0f;
-          gy[threadIdx.x][e] = (j >= j0 && j <= j1) ? w * ey : 0.0f;
+          gx[threadIdx.x][e] = (ox >= -R && ox <= R) ? ex : 0.0f;
+          gy[threadIdx.x][e] = (oy >= -R && oy <= R) ? w * ey : 0.0f;
         }
       }
       __syncthreads();
