@@ -522,28 +522,29 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
         const int wx = min(max(lx - tx0, 0), TS - 8), wy = min(max(ly - ty0, 0), TS - 8);
 #pragma unroll
         for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
+        // pixel centres i + 1/2 are small half-integers: adding q to the
+        // first one is exact
+        const float cx0 = (float)(tx0 + wx) + 0.5f, cy0 = (float)(ty0 + wy) + 0.5f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const int i = tx0 + wx + q, j = ty0 + wy + q;
-          const float ox = u - ((float)i + 0.5f);
-          const float oy = v - ((float)j + 0.5f);
-          // exp2 of a non-positive finite argument lies in [0, 1]: masking by
-          // a 0/1 factor is exact and keeps the code branch-free
+          const float ox = u - (cx0 + (float)q);
+          const float oy = v - (cy0 + (float)q);
+          // exp2 of a non-positive finite argument lies in [0, 1]
           const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
-          gx[threadIdx.x][wx + q] = ex * (float)(ox >= -R && ox <= R);
-          gy[threadIdx.x][wy + q] = (w * ey) * (float)(oy >= -R && oy <= R);
+          gx[threadIdx.x][wx + q] = fabsf(ox) <= R ? ex : 0.0f;
+          gy[threadIdx.x][wy + q] = fabsf(oy) <= R ? w * ey : 0.0f;
         }
       } else {
+        const float cx0 = (float)tx0 + 0.5f, cy0 = (float)ty0 + 0.5f;
 #pragma unroll
         for (int e = 0; e < TS; ++e) {
-          const int i = tx0 + e, j = ty0 + e;
-          const float ox = u - ((float)i + 0.5f);
-          const float oy = v - ((float)j + 0.5f);
+          const float ox = u - (cx0 + (float)e);
+          const float oy = v - (cy0 + (float)e);
           const float ex = __builtin_amdgcn_exp2f((ox * ox) * c.kexp2);
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
-          gx[threadIdx.x][e] = (ox >= -R && ox <= R) ? ex : 0.0f;
-          gy[threadIdx.x][e] = (oy >= -R && oy <= R) ? w * ey : 0.0f;
+          gx[threadIdx.x][e] = fabsf(ox) <= R ? ex : 0.0f;
+          gy[threadIdx.x][e] = fabsf(oy) <= R ? w * ey : 0.0f;
         }
       }
       __syncthreads();
