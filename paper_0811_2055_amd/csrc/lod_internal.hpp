@@ -35,7 +35,7 @@ struct SplatLayout {
   uint32_t units, chunks;            // binning units (waves), 64 per chunk
   uint64_t max_points, max_pairs, max_slices;
   size_t tile_count, tile_off, ucount, pchunk, slice_off, scan_tmp, counters;
-  size_t bu, bv, bm, partial, slice_table;
+  size_t rec, partial, slice_table;   // rec: (u, v, m) float32 records of the (point, tile) pairs
   size_t total;
 };
 

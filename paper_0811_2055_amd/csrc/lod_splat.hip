@@ -305,8 +305,7 @@ __device__ __forceinline__ uint64_t group_of(uint32_t t, bool has, int nbits) {
 // consecutive units of the partition.
 template <class Src, bool FILL, class CT>
 __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, uint32_t u0, uint32_t g,
-                                         int nbits, CT *lc, float *__restrict__ bu, float *__restrict__ bv,
-                                         float *__restrict__ bm, uint64_t max_pairs, uint64_t *status) {
+                                         int nbits, CT *lc, float3 *__restrict__ rec) {
   const int lane = threadIdx.x;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
   const uint64_t n = src.count();
@@ -346,11 +345,7 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
           const uint32_t cnt = (uint32_t)__popcll(peers);
           const uint32_t old = has ? (uint32_t)lc[t] : 0u;
           if (has && below == 0) lc[t] = (CT)(old + cnt);
-          if (FILL && has) {
-            const uint64_t slot = (uint64_t)old + below;
-            if (slot < max_pairs) { bu[slot] = bl.u; bv[slot] = bl.v; bm[slot] = bl.m; }
-            else atomicOr((unsigned long long *)status, (unsigned long long)LOD_STATUS_CAPACITY);
-          }
+          if (FILL && has) rec[old + below] = make_float3(bl.u, bl.v, bl.m);
         }
       }
     }
@@ -368,7 +363,7 @@ __global__ __launch_bounds__(BW) void k_bin_count(Src src, Cam c, uint32_t units
   const uint32_t nt = c.tiles_x * c.tiles_y;
   for (uint32_t i = threadIdx.x; i < nt; i += BW) lc[i] = 0;
   __syncthreads();
-  bin_unit<Src, false, CT>(src, c, units, blockIdx.x, 1, nbits, lc, nullptr, nullptr, nullptr, 0, nullptr);
+  bin_unit<Src, false, CT>(src, c, units, blockIdx.x, 1, nbits, lc, nullptr);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nt; i += BW) ucount[(uint64_t)blockIdx.x * nt + i] = lc[i];
 }
@@ -408,22 +403,27 @@ __global__ void k_bin_chunkscan(uint32_t *__restrict__ pchunk, uint32_t nt, uint
 // units f g .. f g + g - 1 (a tile's list holds their pairs in unit order, so
 // one cursor per tile carries over from one unit to the next); its cursor for
 // tile t starts at tile_off[t] + (pairs of earlier chunks) + (pairs of earlier
-// units in its chunk).
+// units in its chunk).  The pair count (tile_off[nt]) is checked against the
+// record capacity once: past it nothing is written and the status word says
+// so.
 template <class Src>
 __global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units, uint32_t g, int nbits,
                                                  const uint32_t *__restrict__ ucount,
                                                  const uint32_t *__restrict__ pchunk,
                                                  const uint32_t *__restrict__ tile_off,
-                                                 float *__restrict__ bu, float *__restrict__ bv,
-                                                 float *__restrict__ bm, uint64_t max_pairs, uint64_t *status) {
+                                                 float3 *__restrict__ rec, uint64_t max_pairs, uint64_t *status) {
   extern __shared__ uint32_t lc[];
   const uint32_t nt = c.tiles_x * c.tiles_y;
+  if (tile_off[nt] > max_pairs) {
+    if (threadIdx.x == 0) atomicOr((unsigned long long *)status, (unsigned long long)LOD_STATUS_CAPACITY);
+    return;
+  }
   const uint32_t u0 = blockIdx.x * g;
   const uint32_t ch = u0 / 64;
   for (uint32_t i = threadIdx.x; i < nt; i += BW)
     lc[i] = tile_off[i] + pchunk[(uint64_t)ch * nt + i] + ucount[(uint64_t)u0 * nt + i];
   __syncthreads();
-  bin_unit<Src, true, uint32_t>(src, c, units, u0, g, nbits, lc, bu, bv, bm, max_pairs, status);
+  bin_unit<Src, true, uint32_t>(src, c, units, u0, g, nbits, lc, rec);
 }
 
 // slices per tile
@@ -466,8 +466,7 @@ constexpr int GXS = TS + 1;          // padded row: conflict-free phase-A writes
 typedef float float4v __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ table,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
-                                                   const float *__restrict__ bu, const float *__restrict__ bv,
-                                                   const float *__restrict__ bm, Cam c,
+                                                   const float3 *__restrict__ rec, Cam c,
                                                    float *__restrict__ partial, uint64_t max_slices,
                                                    uint64_t max_pairs) {
   __shared__ float gx[PT][GXS];
@@ -485,7 +484,8 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
   float nu, nv, nm;
   {
     const uint64_t q = min((uint64_t)sd.x + threadIdx.x, last);
-    nu = bu[q]; nv = bv[q]; nm = bm[q];
+    const float3 r = rec[q];
+    nu = r.x; nv = r.y; nm = r.z;
   }
   for (uint32_t sl = blockIdx.x; sl < total_slices; sl += gridDim.x) {
     const uint32_t t = sd.y & 0xFFFFu;
@@ -503,7 +503,8 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
       {
         const uint64_t q = (c0 + PT < pe) ? c0 + PT + threadIdx.x : (uint64_t)nsd.x + threadIdx.x;
         const uint64_t qc = min(q, last);
-        nu = bu[qc]; nv = bv[qc]; nm = bm[qc];
+        const float3 r = rec[qc];
+        nu = r.x; nv = r.y; nm = r.z;
       }
       // phase A: rows are zero outside the truncation square.  A pixel is
       // covered when its float32 offset fl(t - (i + 1/2)) lies in [-R, R],
@@ -801,9 +802,7 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   L.slice_off = take(4 * (nt + 1));
   L.scan_tmp = take(4 * scan_tmp_elems<uint32_t>(nt + 1));
   L.counters = take(64);
-  L.bu = take(4 * L.max_pairs);
-  L.bv = take(4 * L.max_pairs);
-  L.bm = take(4 * L.max_pairs);
+  L.rec = take(12 * L.max_pairs);
   L.partial = take(4 * (size_t)TS * TS * L.max_slices);
   L.slice_table = take(8 * (size_t)L.max_slices);
   L.total = off;
@@ -824,7 +823,7 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   uint32_t *stmp = (uint32_t *)(W + L.scan_tmp);
   uint64_t *ctr = (uint64_t *)(W + L.counters);
   uint64_t *status = status_word ? status_word : ctr;
-  float *bu = (float *)(W + L.bu), *bv = (float *)(W + L.bv), *bm = (float *)(W + L.bm);
+  float3 *rec = (float3 *)(W + L.rec);
   float *partial = (float *)(W + L.partial);
   int nbits = 0;
   while ((1u << nbits) < nt) ++nbits;
@@ -848,7 +847,7 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
     // the LDS of the 16-bit counts: fewer resident waves)
     const uint32_t g = L.units >= 4096 ? 2u : 1u;
     LOD_LAUNCH(k_bin_fill<Src>, dim3(L.units / g), dim3(BW), lds, st, src, c, L.units, g, nbits, ucount, pchunk,
-               toff, bu, bv, bm, L.max_pairs, status);
+               toff, rec, L.max_pairs, status);
   }
   LOD_LAUNCH(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
   fill_u32(soff + nt, 1, 0, st);
@@ -857,7 +856,7 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   LOD_LAUNCH(k_slice_table, dim3((nt + 255) / 256), dim3(256), 0, st, toff, tcount, soff, nt, stab, L.max_slices);
   const unsigned agrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, L.max_slices));
   if (any) {
-    LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, bu, bv, bm, c, partial,
+    LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial,
                L.max_slices, L.max_pairs);
   }
   LOD_LAUNCH(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial, c, image,
