@@ -275,30 +275,61 @@ __device__ __forceinline__ Blob make_blob(const Cam &c, bool valid, float px, fl
   return b;
 }
 
-// Lanes of the wave holding the same tile t as this lane (among lanes with
-// `has`).  Spatially coherent points share few tiles, so groups are peeled
-// off by their lowest lane first; after four groups the rest is matched bit
-// by bit.  The grouping, not the method, decides the ranks.
-__device__ __forceinline__ uint64_t group_of(uint32_t t, bool has, int nbits) {
+__device__ __forceinline__ void lds_count_add(uint32_t *lc, uint32_t t, uint32_t cnt) { atomicAdd(&lc[t], cnt); }
+__device__ __forceinline__ void lds_count_add(uint16_t *lc, uint32_t t, uint32_t cnt) {
+  atomicAdd(reinterpret_cast<uint32_t *>(lc) + (t >> 1), cnt << (16 * (t & 1u)));
+}
+
+// One tile of every lane with `has` (tile t): lanes holding the same tile form
+// a group and rank by lane index inside it; a group adds its size to the
+// tile's counter and, with FILL, writes its records at the counter's old
+// value plus the rank.  Spatially coherent points share few tiles, so groups
+// are peeled off by their lowest lane first, with the group mask in scalar
+// registers; after four groups the rest is matched bit by bit.  The grouping,
+// not the method, decides the ranks.  Counting adds to LDS without reading
+// back (16-bit counters are added in their 32-bit word; a unit's counts stay
+// below 2^16, so no carry crosses the halves).
+template <bool FILL, class CT>
+__device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *lc, float3 *__restrict__ rec,
+                                          const Blob &bl) {
+  const int lane = threadIdx.x & (WAVE - 1);
   uint64_t pending = __ballot(has);
-  uint64_t mine = 0;
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
-    if (!pending) return mine;
+    if (!pending) return;
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const uint32_t tl = __builtin_amdgcn_readlane(t, leader);
-    const uint64_t grp = __ballot(has && t == tl);
-    if (has && t == tl) mine = grp;
+    const bool mine = has && t == tl;
+    const uint64_t grp = __ballot(mine);
+    const uint32_t cnt = (uint32_t)__popcll(grp);
+    if (FILL) {
+      const uint32_t old = (uint32_t)lc[tl];
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+      if (mine) rec[old + rank] = make_float3(bl.u, bl.v, bl.m);
+      if (lane == leader) lc[tl] = (CT)(old + cnt);
+    } else {
+      if (lane == leader) lds_count_add(lc, t, cnt);   // the leader's own tile (t == tl)
+    }
     pending &= ~grp;
   }
-  if (!pending) return mine;
-  const bool rest = ((pending >> (threadIdx.x & (WAVE - 1))) & 1ull) != 0;
+  if (!pending) return;
+  const bool rest = ((pending >> lane) & 1ull) != 0;
   uint64_t peers = pending;
   for (int b = 0; b < nbits; ++b) {
     const uint64_t bal = __ballot((t >> b) & 1u);
     peers &= ((t >> b) & 1u) ? bal : ~bal;
   }
-  return rest ? peers : mine;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+  const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+  const uint32_t cnt = (uint32_t)__popcll(peers);
+  if (FILL) {
+    const uint32_t old = rest ? (uint32_t)lc[t] : 0u;
+    if (rest && below == 0) lc[t] = (CT)(old + cnt);
+    if (rest) rec[old + below] = make_float3(bl.u, bl.v, bl.m);
+  } else if (rest && below == 0) {
+    lds_count_add(lc, t, cnt);
+  }
 }
 
 // Points [u0 per, min(n, (u0 + g) per)) with per = ceil(n / units): g
@@ -307,7 +338,6 @@ template <class Src, bool FILL, class CT>
 __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, uint32_t u0, uint32_t g,
                                          int nbits, CT *lc, float3 *__restrict__ rec) {
   const int lane = threadIdx.x;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
   const uint64_t n = src.count();
   const uint64_t per = (n + units - 1) / units;
   const uint64_t b = (uint64_t)u0 * per, e = min(n, b + (uint64_t)g * per);
@@ -340,12 +370,7 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
         for (int dx = 0; __ballot(dy < bl.nty && dx < bl.ntx); ++dx) {
           const bool has = dy < bl.nty && dx < bl.ntx;
           const uint32_t t = has ? (uint32_t)((bl.ty0 + dy) * (int)c.tiles_x + bl.tx0 + dx) : 0u;
-          const uint64_t peers = group_of(t, has, nbits);
-          const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
-          const uint32_t cnt = (uint32_t)__popcll(peers);
-          const uint32_t old = has ? (uint32_t)lc[t] : 0u;
-          if (has && below == 0) lc[t] = (CT)(old + cnt);
-          if (FILL && has) rec[old + below] = make_float3(bl.u, bl.v, bl.m);
+          emit_tile<FILL, CT>(t, has, nbits, lc, rec, bl);
         }
       }
     }
