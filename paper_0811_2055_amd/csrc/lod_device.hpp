@@ -22,10 +22,10 @@ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint3
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    // one 32 x 32 -> 64-bit multiply gives both halves of each product
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
   }
   return c0;
 }
@@ -37,14 +37,18 @@ __device__ __forceinline__ uint64_t particle_U(uint64_t id, uint32_t snap, uint6
 }
 
 // floor(U 2^31 / w) for U <= 2^32, 1 <= w < 2^31, without a 64-bit divide:
-// 2^31 = a w + b, so the quotient is U a + floor(U b / w); the float64
-// estimates are off by at most one unit and the remainder corrects them.
+// 2^31 = a w + b, so the quotient is U a + floor(U b / w).  Both quotients
+// come from one float64 reciprocal of w (relative error 2^-53 before the
+// products): a is off by at most one and corrected both ways, U b / w < 2^32
+// is off by far less than one unit and its remainder corrects it.
 __device__ __forceinline__ uint64_t div_u2p31(uint64_t U, uint32_t w) {
-  uint32_t a = (uint32_t)(2147483648.0 / (double)w);
+  const double rw = 1.0 / (double)w;
+  uint32_t a = (uint32_t)(2147483648.0 * rw);
   if ((uint64_t)a * w > 2147483648ull) --a;
+  if ((uint64_t)(a + 1) * w <= 2147483648ull) ++a;
   const uint32_t b = (uint32_t)(2147483648ull - (uint64_t)a * w);
   const uint64_t x = U * (uint64_t)b;
-  uint64_t q = (uint64_t)((double)x / (double)w);
+  uint64_t q = (uint64_t)((double)x * rw);
   int64_t r = (int64_t)(x - q * (uint64_t)w);
   while (r < 0) { --q; r += w; }
   while (r >= (int64_t)w) { ++q; r -= w; }
