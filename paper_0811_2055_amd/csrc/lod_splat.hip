@@ -483,10 +483,13 @@ __device__ __forceinline__ void neumaier(float &s, float &c, float x) {
 // Gy^T Gx to the 16x16 tile, with Gx[k][i] = exp(-ox^2/2s^2) and Gy[k][j] =
 // m norm exp(-oy^2/2s^2) inside point k's truncation square and 0 outside.
 // Phase A: thread k fills row k of Gx and Gy in LDS.  Phase B: wave g
-// contracts points 64g..64g+63 on the matrix cores (MFMA 16x16x4, float32),
-// each lane ending with 4 pixels of one column -- no atomics, so the image is
-// bit-reproducible.  The four wave partials of a pixel (at most 64 products
-// each) are then folded into the pixel's compensated (Neumaier) float32 sum.
+// contracts its own points 64g..64g+63 on the matrix cores (MFMA 16x16x4,
+// float32), each lane ending with 4 pixels of one column, and folds them
+// (at most 64 products each) into its compensated (Neumaier) float32 sums.
+// A wave reads only the rows its own lanes wrote, and LDS operations of one
+// wave complete in order, so the waves of a block run the chunks without
+// block barriers; at the end of the slice the four wave sums of each pixel
+// are folded in wave order.  No atomics: the image is bit-reproducible.
 constexpr int GXS = TS + 1;          // padded row: conflict-free phase-A writes
 typedef float float4v __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ table,
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
                                                    uint64_t max_pairs) {
   __shared__ float gx[PT][GXS];
   __shared__ float gy[PT][GXS];
-  __shared__ float part[4][TS * TS];
+  __shared__ float part[4][TS * TS];   // the waves' slice sums
   const uint32_t total_slices = (uint32_t)min((uint64_t)slice_off[nt], max_slices);
   const int grp = threadIdx.x / 64;                 // point group of phase B
   const int col = threadIdx.x % TS;                 // pixel column of phase B
@@ -519,7 +522,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
     const uint32_t nsl = sl + gridDim.x;
     const uint2 nsd = table[min(nsl, total_slices - 1)];
     const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
-    float s = 0.0f, cc = 0.0f;
+    float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f}, c4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
       const bool have = c0 + threadIdx.x < pe;
       // lanes past the slice hold whatever the clamped prefetch read: zero them
@@ -573,7 +576,10 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
           gy[threadIdx.x][e] = fabsf(oy) <= R ? w * ey : 0.0f;
         }
       }
-      __syncthreads();
+      // the rows of this wave's points were written by this wave
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // phase B: wave g accumulates points 64g..64g+63 with 16 MFMA steps of
       // 16x16x4 (float32); lane l feeds A[l%16][l/16] = Gy[k][row] and
       // B[l/16][l%16] = Gx[k][col] and receives rows 4(l/16)..+3 of column l%16
@@ -590,15 +596,19 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
       __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
 #pragma unroll
       for (int st = 0; st < 16; ++st) acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st], acc4, 0, 0, 0);
-      const float a0 = acc4[0], a1 = acc4[1], a2 = acc4[2], a3 = acc4[3];
-      part[grp][(row0 + 0) * TS + col] = a0;
-      part[grp][(row0 + 1) * TS + col] = a1;
-      part[grp][(row0 + 2) * TS + col] = a2;
-      part[grp][(row0 + 3) * TS + col] = a3;
-      __syncthreads();
 #pragma unroll
-      for (int g = 0; g < 4; ++g) neumaier(s, cc, part[g][threadIdx.x]);
+      for (int i = 0; i < 4; ++i) neumaier(s4[i], c4[i], acc4[i]);
+      // the next chunk rewrites this wave's rows after its reads above
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[grp][(row0 + i) * TS + col] = s4[i] + c4[i];
+    __syncthreads();
+    float s = 0.0f, cc = 0.0f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) neumaier(s, cc, part[g][threadIdx.x]);
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
     sd = nsd;
     __syncthreads();
