@@ -904,6 +904,11 @@ constexpr int ILP = 8;        // list entries in flight per thread in the candid
 constexpr int SILP = 8;       // candidates per lane per wave step
 constexpr int OILP = 4;       // list entries per thread per step of the output pass
 constexpr int QCAP = 2048;    // bin-b0 candidates queued in LDS by the collect pass
+constexpr int HT = 2 * SMALL; // slots of the table of ranked candidates (load <= 1/2)
+static_assert(2 * HT <= KBINS, "the table lives in the histogram's storage");
+
+__device__ __forceinline__ uint32_t ht_slot(uint32_t p) { return (p * 2654435761u) >> 22; }   // HT = 2^10
+static_assert(HT == 1024, "ht_slot takes the top 10 bits");
 
 // A list entry packs a sorted position (low 32 bits) and its key bin (next 16).
 struct SelArgs {
@@ -1228,6 +1233,12 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   }
   __syncthreads();
   const uint32_t cc = min(ccount, (uint32_t)SMALL);
+  // The ranked candidates go into a hash table (sorted position -> taken),
+  // kept in the histogram's storage (no longer needed), so that the
+  // compaction pass decides them without recomputing their keys.
+  uint32_t *ht_key = hist, *ht_tk = hist + HT;
+  for (int i = threadIdx.x; i < HT; i += BS) ht_key[i] = NONE;
+  __syncthreads();
   for (uint32_t e = threadIdx.x; e < cc; e += BS) {
     const uint64_t Ke = ck[e];
     const uint32_t Ie = cidx[e];
@@ -1238,6 +1249,10 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     }
     if (rank == r) { sh_kt = Ke; sh_it = Ie; sh_pt = cpos[e]; }
     if (rank <= r) atomicAdd(&pcnt[cpart[e]], 1u);
+    const uint32_t pe = cpos[e];
+    uint32_t h = ht_slot(pe);
+    while (atomicCAS(&ht_key[h], NONE, pe) != NONE) h = (h + 1) & (HT - 1);   // keys are distinct
+    ht_tk[h] = rank <= r ? 1u : 0u;
   }
   __syncthreads();
   if (sh_pt == NONE || ccount > SMALL) {
@@ -1290,8 +1305,20 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
       for (int u = 0; u < SILP; ++u) {
         bool tk = j0 + u * WAVE + lane < hi && kb[u] <= b0;
         if (tk && kb[u] == b0) {
-          const uint64_t K = exact_K(a, s, pos[u]);
-          tk = K < Kt || (K == Kt && s.idx[pos[u]] <= It);
+          // ranked above (the usual case) or decided by its exact key
+          uint32_t h = ht_slot(pos[u]), found = 2u;
+          for (int pr = 0; pr < HT; ++pr) {
+            const uint32_t kh = ht_key[h];
+            if (kh == pos[u]) { found = ht_tk[h]; break; }
+            if (kh == NONE) break;
+            h = (h + 1) & (HT - 1);
+          }
+          if (found != 2u) {
+            tk = found != 0u;
+          } else {
+            const uint64_t K = exact_K(a, s, pos[u]);
+            tk = K < Kt || (K == Kt && s.idx[pos[u]] <= It);
+          }
         }
         const uint64_t bal = __ballot(tk);
         const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
