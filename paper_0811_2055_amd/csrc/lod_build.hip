@@ -903,6 +903,7 @@ constexpr int KBINS = 4096;
 constexpr int ILP = 8;        // list entries in flight per thread in the candidate passes
 constexpr int SILP = 8;       // candidates per lane per wave step
 constexpr int OILP = 4;       // list entries per thread per step of the output pass
+constexpr int FILP = 2;       // candidates per lane per step of the fused pass of range-only nodes
 constexpr int QCAP = 2048;    // bin-b0 candidates queued in LDS by the collect pass
 constexpr int HT = 2 * SMALL; // slots of the table of ranked candidates (load <= 1/2)
 static_assert(2 * HT <= KBINS, "the table lives in the histogram's storage");
@@ -1062,6 +1063,13 @@ __device__ __forceinline__ void for_parts(const Segs &g, const SelArgs &sa, cons
         if (j0 + u * WAVE + lane < hi) f(k, pos[u], kb[u]);
     }
   }
+}
+
+// Whether the candidate at sorted position p lies at or below the witness
+// (K_t, id_t) in (K, id) order, from its exact key.
+__device__ __forceinline__ bool taken_exact(const BuildArgs &a, const Sorted &s, uint32_t p, uint64_t Kt, uint32_t It) {
+  const uint64_t K = exact_K(a, s, p);
+  return K < Kt || (K == Kt && s.idx[p] <= It);
 }
 
 // One selecting node, whole block: the n+1 smallest (K, id) among its
@@ -1294,83 +1302,96 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint64_t ob = t.pt_begin[v];
   const int d = t.depth[v];
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-  for (int k = 0; k < (int)g.nseg; ++k) {
-    uint32_t lo, hi;
-    wave_part(g.len[k], w, W, lo, hi);
-    uint32_t run = pcnt[k * W + w];
-    for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * SILP) {
-      uint32_t pos[SILP], kb[SILP];
-      load_step(g, k, sa, s, j0, hi, pos, kb);
+  bool lists = false;
+  for (int k = 0; k < (int)g.nseg; ++k) lists |= g.is_list[k] != 0;
+  // whether a candidate of the threshold bin is taken: ranked above (the
+  // usual case) or decided by its exact key
+  auto taken_b0 = [&](uint32_t p) -> bool {
+    uint32_t h = ht_slot(p), found = 2u;
+    for (int pr = 0; pr < HT; ++pr) {
+      const uint32_t kh = ht_key[h];
+      if (kh == p) { found = ht_tk[h]; break; }
+      if (kh == NONE) break;
+      h = (h + 1) & (HT - 1);
+    }
+    if (found != 2u) return found != 0u;
+    return taken_exact(a, s, p, Kt, It);
+  };
+  double acc = 0.0;
+  if (!lists) {
+    // Only ranges: one pass writes the list and the stored points, the
+    // candidates' data loaded alongside their key bins (contiguous reads).
+    for (int k = 0; k < (int)g.nseg; ++k) {
+      uint32_t lo, hi;
+      wave_part(g.len[k], w, W, lo, hi);
+      uint32_t run = pcnt[k * W + w];
+      const uint64_t base = g.base[k];
+      for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * FILP) {
+        uint32_t pp[FILP], kbv[FILP], wv[FILP];
+        PointIn q[FILP];
+        float mm[FILP];
 #pragma unroll
-      for (int u = 0; u < SILP; ++u) {
-        bool tk = j0 + u * WAVE + lane < hi && kb[u] <= b0;
-        if (tk && kb[u] == b0) {
-          // ranked above (the usual case) or decided by its exact key
-          uint32_t h = ht_slot(pos[u]), found = 2u;
-          for (int pr = 0; pr < HT; ++pr) {
-            const uint32_t kh = ht_key[h];
-            if (kh == pos[u]) { found = ht_tk[h]; break; }
-            if (kh == NONE) break;
-            h = (h + 1) & (HT - 1);
-          }
-          if (found != 2u) {
-            tk = found != 0u;
-          } else {
-            const uint64_t K = exact_K(a, s, pos[u]);
-            tk = K < Kt || (K == Kt && s.idx[pos[u]] <= It);
-          }
+        for (int u = 0; u < FILP; ++u) {
+          const uint32_t pu = (uint32_t)(base + min(j0 + u * WAVE + lane, hi - 1));
+          pp[u] = pu;
+          kbv[u] = s.kb[pu];
+          q[u] = read_point(s, pu);
+          wv[u] = s.w[pu];
+          mm[u] = s.m[pu];
         }
-        const uint64_t bal = __ballot(tk);
-        const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
-        run += (uint32_t)__popcll(bal);
-        if (tk && o <= n) {
-          out[o] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
-          // a list entry other than the child's witness is one of the child's
-          // stored points: record where (segment, index among its points)
-          uint32_t src = NONE;
-          if (g.is_list[k] && pos[u] != g.cwit[k] && n < (1u << 24)) {
-            const uint32_t jc = j0 + u * WAVE + lane;
-            src = ((uint32_t)k << 24) | (jc - (pos[u] > g.cwit[k] ? 1u : 0u));
+#pragma unroll
+        for (int u = 0; u < FILP; ++u) {
+          bool tk = j0 + u * WAVE + lane < hi && kbv[u] <= b0;
+          if (tk && kbv[u] == b0) tk = taken_b0(pp[u]);
+          const uint64_t bal = __ballot(tk);
+          const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
+          run += (uint32_t)__popcll(bal);
+          if (tk && o <= n) {
+            out[o] = (uint64_t)pp[u] | ((uint64_t)kbv[u] << 32);
+            if (out_ok && pp[u] != pt) {
+              const uint32_t j = o - (pp[u] > pt ? 1u : 0u);
+              const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
+              store_point_pos(a, t, q[u], ob + j, d);
+              mrow[j] = mhat;
+              acc += mhat;
+            }
           }
-          srow[o] = src;
         }
       }
     }
-  }
-  __syncthreads();
-  // output pass over the list (every lane busy): the stored points and their
-  // unscaled float64 masses, kept in this block's scratch row
-  double acc = 0.0;
-  if (out_ok) {
-    bool lists = false;
-    for (int k = 0; k < (int)g.nseg; ++k) lists |= g.is_list[k] != 0;
-    if (!lists) {
-      // only ranges: every entry is gathered from the sorted arrays
-      for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * SILP) {
-        uint32_t pos[SILP];
-#pragma unroll
-        for (int u = 0; u < SILP; ++u) pos[u] = entry_pos(out[min(j0 + u * BS, n)], sa.n_minus_1);
-        PointIn q[SILP];
-        uint32_t wv[SILP];
-        float mm[SILP];
+  } else {
+    for (int k = 0; k < (int)g.nseg; ++k) {
+      uint32_t lo, hi;
+      wave_part(g.len[k], w, W, lo, hi);
+      uint32_t run = pcnt[k * W + w];
+      for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * SILP) {
+        uint32_t pos[SILP], kb[SILP];
+        load_step(g, k, sa, s, j0, hi, pos, kb);
 #pragma unroll
         for (int u = 0; u < SILP; ++u) {
-          q[u] = read_point(s, pos[u]);
-          wv[u] = s.w[pos[u]];
-          mm[u] = s.m[pos[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < SILP; ++u) {
-          const uint32_t jl = j0 + u * BS;
-          if (jl > n || pos[u] == pt) continue;
-          const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
-          const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
-          store_point_pos(a, t, q[u], ob + j, d);
-          mrow[j] = mhat;
-          acc += mhat;
+          bool tk = j0 + u * WAVE + lane < hi && kb[u] <= b0;
+          if (tk && kb[u] == b0) tk = taken_b0(pos[u]);
+          const uint64_t bal = __ballot(tk);
+          const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
+          run += (uint32_t)__popcll(bal);
+          if (tk && o <= n) {
+            out[o] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
+            // a list entry other than the child's witness is one of the child's
+            // stored points: record where (segment, index among its points)
+            uint32_t src = NONE;
+            if (g.is_list[k] && pos[u] != g.cwit[k] && n < (1u << 24)) {
+              const uint32_t jc = j0 + u * WAVE + lane;
+              src = ((uint32_t)k << 24) | (jc - (pos[u] > g.cwit[k] ? 1u : 0u));
+            }
+            srow[o] = src;
+          }
         }
       }
-    } else {
+    }
+    __syncthreads();
+    // output pass over the list (every lane busy): the stored points and their
+    // unscaled float64 masses, kept in this block's scratch row
+    if (out_ok) {
       for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * OILP) {
         uint32_t pos[OILP], src[OILP];
 #pragma unroll
