@@ -659,83 +659,110 @@ __global__ __launch_bounds__(TB) void k_octants(BuildArgs a, TreeArgs t, const u
   }
 }
 
-// Emit level d+1 from level d (single block): child offsets by block scans.
-__global__ __launch_bounds__(1024) void k_emit(BuildArgs a, TreeArgs t, int d) {
-  __shared__ uint32_t tmp[1024 / WAVE + 1];
-  __shared__ uint32_t run_nodes, run_sel;
+// Emit level d+1 from level d in three launches.  Thread (i, o) of a block
+// of 1024 handles octant o of node i (8 nodes per wave, 128 per block), so a
+// child's index is the node-major, octant-minor count of non-empty octants
+// before it: per-block totals (k_emit_count), one scan of them
+// (k_emit_scan), and the writes (k_emit_write) with a block scan inside.
+constexpr int EMIT_NODES = 1024 / 8;   // nodes per block
+
+struct EmitOct {
+  uint32_t v, cnt, begin;
+  bool valid, split;
+};
+
+__device__ __forceinline__ EmitOct emit_octant(const BuildArgs &a, const TreeArgs &t, int d) {
   const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
-  if (threadIdx.x == 0) { run_nodes = 0; run_sel = 0; }
+  EmitOct r{};
+  const uint64_t v = (uint64_t)b + (uint64_t)blockIdx.x * EMIT_NODES + threadIdx.x / 8;
+  const uint32_t o = threadIdx.x & 7u;
+  r.valid = v < e;
+  r.v = (uint32_t)v;
+  const uint32_t vc = r.valid ? r.v : b;   // in bounds when the level is not empty
+  r.split = r.valid && t.part_count[vc] > a.n && d < a.D;
+  const uint32_t s0 = t.cs[(uint64_t)vc * 9 + o], s1 = t.cs[(uint64_t)vc * 9 + o + 1];
+  r.cnt = r.split ? s1 - s0 : 0u;
+  r.begin = s0;
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_emit_count(BuildArgs a, TreeArgs t, int d, uint32_t *__restrict__ tot) {
+  __shared__ uint32_t tmp[1024 / WAVE + 1];
+  if (t.lvl[d] + (uint64_t)blockIdx.x * EMIT_NODES >= t.lvl[d + 1]) {
+    if (threadIdx.x == 0) { tot[2 * blockIdx.x] = 0; tot[2 * blockIdx.x + 1] = 0; }
+    return;
+  }
+  const EmitOct x = emit_octant(a, t, d);
+  uint32_t tk, ts;
+  block_excl_scan<uint32_t>(x.cnt > 0 ? 1u : 0u, tmp, tk);
+  block_excl_scan<uint32_t>(x.cnt > a.n ? 1u : 0u, tmp, ts);
+  if (threadIdx.x == 0) { tot[2 * blockIdx.x] = tk; tot[2 * blockIdx.x + 1] = ts; }
+}
+
+// exclusive scan of the (children, selecting children) totals of nb blocks,
+// and the extent of level d+1
+__global__ __launch_bounds__(1024) void k_emit_scan(BuildArgs a, TreeArgs t, int d, uint32_t *__restrict__ tot,
+                                                    uint32_t nb) {
+  __shared__ uint32_t tmp[1024 / WAVE + 1];
+  __shared__ uint32_t run_k, run_s;
+  if (threadIdx.x == 0) { run_k = 0; run_s = 0; }
   __syncthreads();
-  const uint32_t next_base = e;
-  const uint32_t sel_base = t.lsel[d + 1];
-  for (uint32_t v0 = b; v0 < e; v0 += blockDim.x) {
-    const uint32_t v = v0 + threadIdx.x;
-    uint32_t nkids = 0, nsel = 0, mask = 0;
-    // unconditional loads at a clamped node (a load under a branch is waited
-    // for on its own); octant starts of a node that is not split are unused
-    const uint32_t vc = min(v, e - 1);
-    const uint64_t pc = t.part_count[vc];
-    uint32_t st[9];
-#pragma unroll
-    for (int o = 0; o < 9; ++o) st[o] = t.cs[(uint64_t)vc * 9 + o];
-    if (v < e && pc > a.n && d < a.D) {
-#pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const uint32_t c = st[o + 1] - st[o];
-        if (c) { mask |= 1u << o; ++nkids; if (c > a.n) ++nsel; }
-      }
-    }
+  for (uint32_t j0 = 0; j0 < nb; j0 += blockDim.x) {
+    const uint32_t j = j0 + threadIdx.x;
+    const uint32_t ck = j < nb ? tot[2 * j] : 0u, cs = j < nb ? tot[2 * j + 1] : 0u;
     uint32_t tk, ts;
-    const uint32_t ok = block_excl_scan<uint32_t>(nkids, tmp, tk);
-    const uint32_t os = block_excl_scan<uint32_t>(nsel, tmp, ts);
-    if (v < e) {
-      t.child_mask[v] = (uint8_t)mask;
-      t.pend[v] = nsel;
-      if (nkids) {
-        uint32_t c = next_base + run_nodes + ok;
-        uint32_t sidx = sel_base + run_sel + os;
-        if ((uint64_t)c + nkids > a.node_cap) {
-          set_status(a, LOD_STATUS_CAPACITY);
-          t.first_child[v] = NONE;
-          for (uint32_t j = 0; j < nsel; ++j)
-            if (sidx + j < a.node_cap) t.sel_node[sidx + j] = NONE;
-        } else {
-          t.first_child[v] = c;
-          const uint64_t pfx = t.prefix[v] << 3;
-          for (int o = 0; o < 8; ++o) {
-            const uint32_t cnt = st[o + 1] - st[o];
-            if (!cnt) continue;
-            t.prefix[c] = pfx | (uint64_t)o;
-            t.depth[c] = (uint8_t)(d + 1);
-            t.parent[c] = v;
-            t.first_child[c] = NONE;
-            t.child_mask[c] = 0;
-            t.part_begin[c] = st[o];
-            t.part_count[c] = cnt;
-            if (cnt > a.n) {
-              if (sidx < a.node_cap) t.sel_node[sidx] = c;
-              t.sel_idx[c] = sidx++;
-            } else {
-              t.sel_idx[c] = NONE;
-            }
-            t.wit[c] = NONE;
-            t.pend[c] = 0;
-            ++c;
-          }
-        }
-      } else {
-        t.first_child[v] = NONE;
-      }
-    }
+    const uint32_t ek = block_excl_scan<uint32_t>(ck, tmp, tk);
+    const uint32_t es = block_excl_scan<uint32_t>(cs, tmp, ts);
+    if (j < nb) { tot[2 * j] = run_k + ek; tot[2 * j + 1] = run_s + es; }
     __syncthreads();
-    if (threadIdx.x == 0) { run_nodes += tk; run_sel += ts; }
+    if (threadIdx.x == 0) { run_k += tk; run_s += ts; }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    uint64_t end = (uint64_t)next_base + run_nodes;
+    const uint64_t end = (uint64_t)t.lvl[d + 1] + run_k;
     t.lvl[d + 2] = (uint32_t)min(end, a.node_cap);
-    t.lsel[d + 2] = sel_base + run_sel;
+    t.lsel[d + 2] = t.lsel[d + 1] + run_s;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_emit_write(BuildArgs a, TreeArgs t, int d,
+                                                     const uint32_t *__restrict__ tot) {
+  __shared__ uint32_t tmp[1024 / WAVE + 1];
+  if (t.lvl[d] + (uint64_t)blockIdx.x * EMIT_NODES >= t.lvl[d + 1]) return;
+  const EmitOct x = emit_octant(a, t, d);
+  const uint32_t o = threadIdx.x & 7u;
+  const bool ne = x.cnt > 0, se = x.cnt > a.n;
+  uint32_t tk, ts;
+  const uint32_t ok = block_excl_scan<uint32_t>(ne ? 1u : 0u, tmp, tk);
+  const uint32_t os = block_excl_scan<uint32_t>(se ? 1u : 0u, tmp, ts);
+  const uint64_t c = (uint64_t)t.lvl[d + 1] + tot[2 * blockIdx.x] + ok;   // this octant's child
+  const uint32_t sidx = t.lsel[d + 1] + tot[2 * blockIdx.x + 1] + os;
+  // the node's 8 octants are 8 consecutive lanes of one wave
+  const int sh = (int)(threadIdx.x & (WAVE - 1) & ~7u);
+  const uint32_t mask = (uint32_t)(__ballot(ne) >> sh) & 0xFFu;
+  const uint32_t nsel = (uint32_t)__popc((uint32_t)(__ballot(se) >> sh) & 0xFFu);
+  if (x.valid && o == 0) {
+    t.child_mask[x.v] = (uint8_t)mask;
+    t.pend[x.v] = nsel;
+    t.first_child[x.v] = (mask && c + __popc(mask) <= a.node_cap) ? (uint32_t)c : NONE;
+  }
+  if (!ne) return;
+  if (c >= a.node_cap) {
+    set_status(a, LOD_STATUS_CAPACITY);
+    if (se && sidx < a.node_cap) t.sel_node[sidx] = NONE;
+    return;
+  }
+  t.prefix[c] = (t.prefix[x.v] << 3) | (uint64_t)o;
+  t.depth[c] = (uint8_t)(d + 1);
+  t.parent[c] = x.v;
+  t.first_child[c] = NONE;
+  t.child_mask[c] = 0;
+  t.part_begin[c] = x.begin;
+  t.part_count[c] = x.cnt;
+  t.sel_idx[c] = se ? sidx : NONE;
+  if (se && sidx < a.node_cap) t.sel_node[sidx] = (uint32_t)c;
+  t.wit[c] = NONE;
+  t.pend[c] = 0;
 }
 
 // pt_count for every slot < node_cap (0 beyond the node count) and n_nodes.
@@ -1621,6 +1648,14 @@ void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Blocks of the emit kernels: enough for the largest level.  A level below
+// the roots holds at most 8 children of each splitting node above it, and the
+// splitting nodes of a level hold more than n particles each, disjointly.
+static unsigned emit_blocks(uint64_t N, uint32_t n, uint32_t n_snap) {
+  const uint64_t max_level = std::max<uint64_t>(8 * (N / ((uint64_t)n + 1)), n_snap);
+  return (unsigned)std::max<uint64_t>(1, (max_level + EMIT_NODES - 1) / EMIT_NODES);
+}
+
 BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   BuildLayout L{};
   const uint64_t Np = N ? N : 1;
@@ -1661,6 +1696,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.mhat = take(8 * (size_t)L.sel_rows * p.n);
   L.src = take(4 * (size_t)L.sel_rows * ((uint64_t)p.n + 1));
   L.leafctl = take(4 * ((size_t)L.sel_rows + 2 * (p.max_depth + 1)));   // leaf-copy cursors, level counts
+  L.emit_tot = take(8 * ((size_t)emit_blocks(N, p.n, n_snap) + 1));   // per-block child totals of the emit
   L.total = off;
   return L;
 }
@@ -1733,9 +1769,15 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   LOD_LAUNCH(k_roots, dim3(1), dim3(1024), 0, st, a, t, ks);
   const uint64_t per_level = N / ((uint64_t)p.n + 1) + n_snap;
   const unsigned oct_grid = (unsigned)std::min<uint64_t>(4096, (per_level * 8 + TB - 1) / TB + 1);
+  // blocks of the emit kernels: enough for the largest level (every level but
+  // the roots' holds at most 8 children per selecting node of the level above)
+  const unsigned emit_grid = emit_blocks(N, p.n, n_snap);
+  uint32_t *emit_tot = (uint32_t *)(W + L.emit_tot);
   for (int d = 0; d < D; ++d) {
     LOD_LAUNCH(k_octants, dim3(oct_grid), dim3(TB), 0, st, a, t, ks, d);
-    LOD_LAUNCH(k_emit, dim3(1), dim3(1024), 0, st, a, t, d);
+    LOD_LAUNCH(k_emit_count, dim3(emit_grid), dim3(1024), 0, st, a, t, d, emit_tot);
+    LOD_LAUNCH(k_emit_scan, dim3(1), dim3(1024), 0, st, a, t, d, emit_tot, emit_grid);
+    LOD_LAUNCH(k_emit_write, dim3(emit_grid), dim3(1024), 0, st, a, t, d, emit_tot);
   }
   const unsigned cap_grid = (unsigned)std::min<uint64_t>(4096, (L.node_cap + TB - 1) / TB);
   LOD_LAUNCH(k_ptcount, dim3(cap_grid), dim3(TB), 0, st, a, t, D);
