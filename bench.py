@@ -29,7 +29,7 @@ METRIC = "LOD build Mparticles/s + %HBM roofline; splat Mpts/s; LOD-vs-full imag
 # Algorithmic bytes per unit for each kernel (unit: particle for the build
 # kernels, point for the splat binning, (point, tile) pair for accumulation).
 KERNEL_BYTES = {
-    "k_keygen": 16.0,            # read x,y,z,m (16); histogram only
+    "k_keygen": 12.0,            # read x,y,z (12); histogram only (masses checked in the first scatter)
     "k_scatter<true>": 36.0,     # read x,y,z,m (16) write key,id,fraction,mass (20)
     "k_scatter<false>": 40.0,    # read 20 write 20
     "k_upsweep": 4.0,            # read key

@@ -123,8 +123,8 @@ __device__ __forceinline__ PKey particle_key(const BuildArgs &a, float xe, float
 // keygen: domain check and digit-0 tile histograms (reads the input only; the
 // first scatter pass recomputes the keys instead of reading them back)
 __global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, const float *__restrict__ y,
-                                               const float *__restrict__ z, const float *__restrict__ m,
-                                               BuildArgs a, uint32_t *__restrict__ thist, uint64_t n_tiles) {
+                                               const float *__restrict__ z, BuildArgs a, uint32_t *__restrict__ thist,
+                                               uint64_t n_tiles) {
   __shared__ uint32_t hist[RADIX];
   __shared__ int bad;
   for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
@@ -134,17 +134,18 @@ __global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, cons
   bool my_bad = false;
   // all loads first (clamped indices: a predicated load is waited for alone)
   for (int c = 0; c < HITEMS; c += HCHUNK) {
-    float xs[HCHUNK], ys[HCHUNK], zs[HCHUNK], ms[HCHUNK];
+    float xs[HCHUNK], ys[HCHUNK], zs[HCHUNK];
 #pragma unroll
     for (int i = 0; i < HCHUNK; ++i) {
       const uint64_t e = min(tile * STILE + (uint64_t)(c + i) * TB + threadIdx.x, a.N - 1);
-      xs[i] = x[e]; ys[i] = y[e]; zs[i] = z[e]; ms[i] = m[e];
+      xs[i] = x[e]; ys[i] = y[e]; zs[i] = z[e];
     }
 #pragma unroll
     for (int i = 0; i < HCHUNK; ++i) {
       const uint64_t e = tile * STILE + (uint64_t)(c + i) * TB + threadIdx.x;
       if (e < a.N) {
-        const PKey pk = particle_key(a, xs[i], ys[i], zs[i], ms[i], e);
+        // positions only: the masses are checked by the first scatter pass
+        const PKey pk = particle_key(a, xs[i], ys[i], zs[i], 0.0f, e);
         my_bad |= !pk.ok;
         atomicAdd(&hist[pk.key & 0xFFu], 1u);
       }
@@ -231,6 +232,7 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
       const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
       xs[r] = in.x[e]; ys[r] = in.y[e]; zs[r] = in.z[e]; mm[r] = in.m[e];
     }
+    bool bad_mass = false;
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
       const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
@@ -238,7 +240,10 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
       kk[r] = pk.key;
       ll[r] = pk.lo;
       ii[r] = (uint32_t)(ebase + (uint64_t)r * WAVE);
+      // keygen checked the positions; the masses are checked here
+      bad_mass |= ebase + (uint64_t)r * WAVE < N && !(mm[r] >= 0.0f && mm[r] <= 3.4028235e38f);
     }
+    if (bad_mass) atomicOr((unsigned long long *)&a.counts[2], (unsigned long long)LOD_STATUS_DOMAIN);
   } else {
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
@@ -1735,7 +1740,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const uint64_t hist_n = (uint64_t)RADIX * tiles;
   const uint64_t dtiles = (N + TILE - 1) / TILE;
 
-  LOD_LAUNCH(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, in.mass, a, thist, tiles);
+  LOD_LAUNCH(k_keygen, dim3((unsigned)tiles), dim3(TB), 0, st, in.x, in.y, in.z, a, thist, tiles);
   const int kb = key_bits(p, n_snap);
   const int passes = std::max(1, (kb + 7) / 8);
   // pass 0 reads the particles (keys recomputed, ids implicit) and writes B
