@@ -130,7 +130,7 @@ __global__ __launch_bounds__(TB) void k_keygen(const float *__restrict__ x, cons
   for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   bool my_bad = false;
   // all loads first (clamped indices: a predicated load is waited for alone)
   for (int c = 0; c < HITEMS; c += HCHUNK) {
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key
   __shared__ uint32_t hist[RADIX];
   for (int i = threadIdx.x; i < RADIX; i += TB) hist[i] = 0;
   __syncthreads();
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   for (int c = 0; c < HITEMS; c += 2 * HCHUNK) {
     uint32_t ks[2 * HCHUNK];
 #pragma unroll
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
 
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x / WAVE;
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint64_t tbase = tile * STILE;
   const uint64_t ebase = tbase + (uint64_t)w * PER_WAVE + lane;
   // this tile's global digit offsets, loaded first (every thread, clamped

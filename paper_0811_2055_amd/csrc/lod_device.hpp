@@ -79,6 +79,17 @@ __device__ __forceinline__ double weight_pow(uint32_t w, int alpha) {
 }
 
 // ---------------------------------------------------------------------------
+// Workgroups go to the eight XCDs round-robin (block b to XCD b mod 8), and
+// each XCD has its own L2.  Giving XCD x the x-th contiguous share of n work
+// items (sort tiles) puts neighbouring items, whose outputs end and begin in
+// the same cache lines, on one L2.  A bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, i = b >> 3;
+  const uint32_t per = n >> 3, extra = n & 7u;   // XCD x takes per + (x < extra) items
+  return x * per + min(x, extra) + i;
+}
+
+// ---------------------------------------------------------------------------
 // Morton: spread the low 10 bits of v to every third bit.
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   v &= 0x3FFu;
