@@ -945,16 +945,15 @@ static_assert(HT == 1024, "ht_slot takes the top 10 bits");
 
 // A list entry packs a sorted position (low 32 bits) and its key bin (next 16).
 struct SelArgs {
-  uint64_t *lists;            // top-(n+1) lists by selecting rank
+  uint32_t *lpos;             // top-(n+1) lists by selecting rank: sorted positions
+  uint16_t *lkb;              // and their key bins (a separate array: the counting passes read only these)
   uint32_t n_minus_1;         // N - 1
   double *mhat;               // float64 mass scratch, one row of n per block
   uint32_t *src;              // source of each list entry, one row of n+1 per block
 };
 
-__device__ __forceinline__ uint32_t entry_pos(uint64_t e, uint32_t n_minus_1) {
-  return min((uint32_t)e, n_minus_1);
-}
-__device__ __forceinline__ uint32_t entry_kb(uint64_t e) { return (uint32_t)(e >> 32) & 0xFFFFu; }
+// sorted position of list entry i (clamped: the lists are workspace)
+__device__ __forceinline__ uint32_t entry_pos(const SelArgs &sa, uint64_t i) { return min(sa.lpos[i], sa.n_minus_1); }
 
 struct Segs {
   uint32_t nseg;
@@ -1012,9 +1011,9 @@ __device__ __forceinline__ void load_step(const Segs &g, int k, const SelArgs &s
   if (g.is_list[k]) {
 #pragma unroll
     for (int u = 0; u < SILP; ++u) {
-      const uint64_t e = sa.lists[base + min(j0 + u * WAVE + lane, hi - 1)];
-      pos[u] = entry_pos(e, sa.n_minus_1);
-      kb[u] = entry_kb(e);
+      const uint64_t i = base + min(j0 + u * WAVE + lane, hi - 1);
+      pos[u] = entry_pos(sa, i);
+      kb[u] = sa.lkb[i];
     }
   } else {
 #pragma unroll
@@ -1026,10 +1025,12 @@ __device__ __forceinline__ void load_step(const Segs &g, int k, const SelArgs &s
   }
 }
 
-// Calls f(k, pos, kb) for every candidate of this wave's parts, in no
-// particular order (f is inlined many times: keep it small), with 16-byte loads (8 key bins or 2 list entries per
-// lane and load) so that many bytes are in flight per wave.  Reads may run up
-// to 16 bytes past a part; the key-bin and list arrays are padded for it.
+// Calls f(k, p, kb) for every candidate of this wave's parts, in no
+// particular order (f is inlined many times: keep it small), with 16-byte
+// loads of 8 key bins per lane so that many bytes are in flight per wave.  p
+// is the sorted position for a range segment and the index within the list
+// for a list segment (entry_pos gives its position).  Reads may run up to 16
+// bytes past a part; the key-bin arrays are padded for it.
 constexpr int BU = 4;         // 16-byte loads in flight per lane
 template <typename F>
 __device__ __forceinline__ void for_parts_bulk(const Segs &g, const SelArgs &sa, const Sorted &s, F f) {
@@ -1039,41 +1040,24 @@ __device__ __forceinline__ void for_parts_bulk(const Segs &g, const SelArgs &sa,
     wave_part(g.len[k], w, W, lo, hi);
     if (lo >= hi) continue;
     const uint64_t b = g.base[k] + lo, e = g.base[k] + hi;   // element range [b, e)
-    if (g.is_list[k]) {
-      const uint64_t a0 = b & ~1ull, last = (e - 1) & ~1ull;
-      for (uint64_t q0 = a0; q0 < e; q0 += 2ull * WAVE * BU) {
-        uint64_t v0[BU], v1[BU];
+    const uint16_t *kbp = g.is_list[k] ? sa.lkb : s.kb;
+    const uint64_t off = g.is_list[k] ? g.base[k] : 0;
+    const uint64_t a0 = b & ~7ull, last = (e - 1) & ~7ull;
+    for (uint64_t q0 = a0; q0 < e; q0 += 8ull * WAVE * BU) {
+      uint4 v[BU];
 #pragma unroll
-        for (int u = 0; u < BU; ++u) {
-          const uint64_t i = min(q0 + 2ull * (u * WAVE + lane), last);
-          const ulonglong2 pr = *reinterpret_cast<const ulonglong2 *>(sa.lists + i);
-          v0[u] = pr.x; v1[u] = pr.y;
-        }
-#pragma unroll
-        for (int u = 0; u < BU; ++u) {
-          const uint64_t i = q0 + 2ull * (u * WAVE + lane);
-          if (i >= b && i < e) f(k, entry_pos(v0[u], sa.n_minus_1), entry_kb(v0[u]));
-          if (i + 1 >= b && i + 1 < e) f(k, entry_pos(v1[u], sa.n_minus_1), entry_kb(v1[u]));
-        }
+      for (int u = 0; u < BU; ++u) {
+        const uint64_t i = min(q0 + 8ull * (u * WAVE + lane), last);
+        v[u] = *reinterpret_cast<const uint4 *>(kbp + i);
       }
-    } else {
-      const uint64_t a0 = b & ~7ull, last = (e - 1) & ~7ull;
-      for (uint64_t q0 = a0; q0 < e; q0 += 8ull * WAVE * BU) {
-        uint4 v[BU];
 #pragma unroll
-        for (int u = 0; u < BU; ++u) {
-          const uint64_t i = min(q0 + 8ull * (u * WAVE + lane), last);
-          v[u] = *reinterpret_cast<const uint4 *>(s.kb + i);
-        }
+      for (int u = 0; u < BU; ++u) {
+        const uint64_t i = q0 + 8ull * (u * WAVE + lane);
+        const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-        for (int u = 0; u < BU; ++u) {
-          const uint64_t i = q0 + 8ull * (u * WAVE + lane);
-          const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-          for (int h = 0; h < 8; ++h) {
-            const uint64_t ih = i + h;
-            if (ih >= b && ih < e) f(k, (uint32_t)ih, (wd[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
-          }
+        for (int h = 0; h < 8; ++h) {
+          const uint64_t ih = i + h;
+          if (ih >= b && ih < e) f(k, (uint32_t)(ih - off), (wd[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
         }
       }
     }
@@ -1258,7 +1242,11 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
       });
       if (cur >= 0 && below_cnt) atomicAdd(&pcnt[cur * W + w], below_cnt);
       __syncthreads();
-      for (uint32_t q = threadIdx.x; q < nq; q += BS) visit_b0(qpart[q], qpos[q]);
+      for (uint32_t q = threadIdx.x; q < nq; q += BS) {
+        // a queued list candidate is its index in the list: look up its position
+        const uint32_t k = qpart[q] / W, p = qpos[q];
+        visit_b0(qpart[q], g.is_list[k] ? entry_pos(sa, g.base[k] + p) : p);
+      }
     } else {
       for_parts(g, sa, s, [&](int k, uint32_t p, uint32_t kb) {
         if (k != cur) {
@@ -1328,7 +1316,8 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   // compaction pass: the n+1 list entries, in candidate (= sorted position) order
   const double tau = sh_tau;
   const bool out_ok = a.counts[1] <= a.point_cap;
-  uint64_t *out = sa.lists + (uint64_t)t.sel_idx[v] * (n + 1);
+  uint32_t *out_pos = sa.lpos + (uint64_t)t.sel_idx[v] * (n + 1);
+  uint16_t *out_kb = sa.lkb + (uint64_t)t.sel_idx[v] * (n + 1);
   double *mrow = sa.mhat + (uint64_t)blockIdx.x * n;
   uint32_t *srow = sa.src + (uint64_t)blockIdx.x * (n + 1);
   const uint64_t ob = t.pt_begin[v];
@@ -1379,7 +1368,8 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
           const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
           run += (uint32_t)__popcll(bal);
           if (tk && o <= n) {
-            out[o] = (uint64_t)pp[u] | ((uint64_t)kbv[u] << 32);
+            out_pos[o] = pp[u];
+            out_kb[o] = (uint16_t)kbv[u];
             if (out_ok && pp[u] != pt) {
               const uint32_t j = o - (pp[u] > pt ? 1u : 0u);
               const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
@@ -1407,7 +1397,8 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
           const uint32_t o = run + (uint32_t)__popcll(bal & lt_mask);
           run += (uint32_t)__popcll(bal);
           if (tk && o <= n) {
-            out[o] = (uint64_t)pos[u] | ((uint64_t)kb[u] << 32);
+            out_pos[o] = pos[u];
+            out_kb[o] = (uint16_t)kb[u];
             // a list entry other than the child's witness is one of the child's
             // stored points: record where (segment, index among its points)
             uint32_t src = NONE;
@@ -1429,7 +1420,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
 #pragma unroll
         for (int u = 0; u < OILP; ++u) {
           const uint32_t jl = min(j0 + u * BS, n);
-          pos[u] = entry_pos(out[jl], sa.n_minus_1);
+          pos[u] = min(out_pos[jl], sa.n_minus_1);
           src[u] = srow[jl];
         }
         // entries from a child's list take id and codes from the child's stored
@@ -1696,7 +1687,10 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   L.bscan = take(4 * (size_t)(L.node_cap + 1));
   L.bottom = take(4 * (size_t)L.node_cap);
   L.ctl = take(64);
-  L.lists = take(8 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)) + 16);
+  // lists: position and key bin of each entry (the key bins padded for the
+  // 16-byte reads of the counting passes)
+  L.lpos = take(4 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
+  L.lkb = take(2 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)) + 16);
   L.sel_rows = (uint32_t)std::min<uint64_t>(4096, N / ((uint64_t)p.n + 1) + n_snap + 1);
   L.mhat = take(8 * (size_t)L.sel_rows * p.n);
   L.src = take(4 * (size_t)L.sel_rows * ((uint64_t)p.n + 1));
@@ -1799,7 +1793,8 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
     LOD_LAUNCH(k_leaves<true>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
   }
 
-  SelArgs sa{(uint64_t *)(W + L.lists), (uint32_t)(N - 1), (double *)(W + L.mhat), (uint32_t *)(W + L.src)};
+  SelArgs sa{(uint32_t *)(W + L.lpos), (uint16_t *)(W + L.lkb), (uint32_t)(N - 1), (double *)(W + L.mhat),
+             (uint32_t *)(W + L.src)};
   const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
   // one scratch row of float64 masses per block
   const unsigned sel_grid = (unsigned)std::min<uint64_t>(L.sel_rows, per_level + 1);
