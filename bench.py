@@ -41,10 +41,11 @@ def selection_bytes(h, n):
     """Algorithmic bytes of one build's per-level selection launches, which
     also copy the leaves' particles to their stored points.
 
-    Per selecting node: every candidate read once (8 B per entry of a
-    selecting child's list, 2 B key bin per particle of a leaf child or of the
-    node's own range), its n stored points gathered (id 4, codes 6, w 4, m 4)
-    and written (14 B), its list of n+1 entries written (8 B each).  Per
+    Per selecting node: every candidate read once (6 B per entry of a
+    selecting child's list: position and key bin; 2 B key bin per particle of
+    a leaf child or of the node's own range), its n stored points gathered
+    (id 4, codes 6, w 4, m 4) and written (14 B), its list of n+1 entries
+    written (6 B each).  Per
     particle of a leaf holding at most n: 20 B read (key, id, fraction, mass)
     and 14 B written.
     """
@@ -61,7 +62,7 @@ def selection_bytes(h, n):
     ranges = int(cnt[child_of_sel & ~sel].sum()) + int(cnt[sel & (fc == NONE)].sum())
     n_sel = int(np.count_nonzero(sel))
     leaf_particles = int(cnt[(fc == NONE) & ~sel].sum())
-    return (8.0 * (n + 1) * lists + 2.0 * ranges + (18.0 + 14.0) * n * n_sel + 8.0 * (n + 1) * n_sel
+    return (6.0 * (n + 1) * lists + 2.0 * ranges + (18.0 + 14.0) * n * n_sel + 6.0 * (n + 1) * n_sel
             + 34.0 * leaf_particles)
 
 
