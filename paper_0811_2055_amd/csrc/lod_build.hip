@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lod.h"
@@ -1700,6 +1701,39 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   return L;
 }
 
+// A second stream of the device (default priority) and two events: the density
+// kernel runs on it beside the tree construction, which does not read its
+// output.  Created at the first build outside stream capture; a build captured
+// before that runs on one stream.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static SideStream *side_stream(hipStream_t st) {
+  static std::mutex mu;
+  static SideStream per_dev[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  SideStream &r = per_dev[dev];
+  if (!r.s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      (void)hipStreamDestroy(s);
+      return nullptr;
+    }
+    r.s = s; r.fork = a; r.join = b;
+  }
+  return &r;
+}
+
 int key_bits(const lod_params &p, uint32_t n_snap) {
   int sb = 0;
   while ((1ull << sb) < n_snap) ++sb;
@@ -1752,8 +1786,18 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   }
   Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint16_t *)(W + L.kb)};
 
-  LOD_LAUNCH(k_density, dim3((unsigned)dtiles), dim3(TB), 0, st, a, ks, is,
+  // density weights and key bins on the side stream, beside the tree
+  // construction; joined before the selection
+  SideStream *side = side_stream(st);
+  hipStream_t dst = st;
+  if (side) {
+    if (hipEventRecord(side->fork, st) != hipSuccess || hipStreamWaitEvent(side->s, side->fork, 0) != hipSuccess)
+      return LOD_EDEVICE;
+    dst = side->s;
+  }
+  LOD_LAUNCH(k_density, dim3((unsigned)dtiles), dim3(TB), 0, dst, a, ks, is,
              (uint32_t *)(W + L.w), (uint16_t *)(W + L.kb));
+  if (side && hipEventRecord(side->join, side->s) != hipSuccess) return LOD_EDEVICE;
 
   TreeArgs t{};
   t.prefix = out.prefix; t.depth = out.depth; t.parent = out.parent; t.first_child = out.first_child;
@@ -1792,6 +1836,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   } else {
     LOD_LAUNCH(k_leaves<true>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
   }
+  if (side && hipStreamWaitEvent(st, side->join, 0) != hipSuccess) return LOD_EDEVICE;
 
   SelArgs sa{(uint32_t *)(W + L.lpos), (uint16_t *)(W + L.lkb), (uint32_t)(N - 1), (double *)(W + L.mhat),
              (uint32_t *)(W + L.src)};
