@@ -171,9 +171,13 @@ lod_status lod_build_plan(const lod_input *in, const lod_params *p,
  * selection keys; per node holding more than n particles, the n smallest
  * (key, id) taken bottom up from the children's n+1 smallest; float64
  * mass renormalisation; 16-bit quantisation; output.  No host
- * synchronisation; safe to capture in a HIP graph.  workspace: device,
- * >= the planned size, 256-byte aligned.  LOD_ECAPACITY when
- * out->node_capacity or point_capacity is below the plan's bound. */
+ * synchronisation; safe to capture in a HIP graph.  The density step runs on
+ * a second stream of the device owned by the library (created by the first
+ * call made outside stream capture), forked from and joined back into
+ * `stream`; builds on one device must therefore not be issued from several
+ * host threads at once.  workspace: device, >= the planned size, 256-byte
+ * aligned.  LOD_ECAPACITY when out->node_capacity or point_capacity is below
+ * the plan's bound. */
 lod_status lod_build(const lod_input *in, const lod_params *p, void *workspace,
                      size_t workspace_bytes, lod_tree *out, lod_stream_t stream);
 
