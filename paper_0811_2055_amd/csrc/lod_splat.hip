@@ -505,6 +505,14 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
   const int col = threadIdx.x % TS;                 // pixel column of phase B
   const int row0 = ((threadIdx.x % 64) / TS) * 4;   // first of 4 pixel rows of phase B
   if (blockIdx.x >= total_slices) return;
+  // Each thread owns rows threadIdx.x of gx and gy for the whole launch.  In
+  // the narrow case they start at zero and each chunk clears only the
+  // previous chunk's 8-wide windows before writing its own.
+  int pwx = 0, pwy = 0;
+  if (c.narrow) {
+#pragma unroll
+    for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
+  }
   // pair records are loaded one chunk ahead, across slice boundaries too
   // (clamped indices: every load is issued unconditionally)
   const uint64_t last = max_pairs - 1;
@@ -544,13 +552,15 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
       const float R = c.R;
       const float w = m * c.norm;
       if (c.narrow) {
-        // fewer than 8 covered pixels per axis: zero the row, then write an
-        // 8-wide window from a lower bound of the run's first pixel (float32
-        // offsets are within 1/100 pixel of the exact ones)
+        // fewer than 8 covered pixels per axis: clear the previous window,
+        // then write an 8-wide window from a lower bound of the run's first
+        // pixel (float32 offsets are within 1/100 pixel of the exact ones);
+        // the rest of the row is still zero
         const int lx = (int)ceilf(u - 0.5f - R - 0.01f), ly = (int)ceilf(v - 0.5f - R - 0.01f);
         const int wx = min(max(lx - tx0, 0), TS - 8), wy = min(max(ly - ty0, 0), TS - 8);
 #pragma unroll
-        for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
+        for (int e = 0; e < 8; ++e) { gx[threadIdx.x][pwx + e] = 0.0f; gy[threadIdx.x][pwy + e] = 0.0f; }
+        pwx = wx; pwy = wy;
         // pixel centres i + 1/2 are small half-integers: adding q to the
         // first one is exact
         const float cx0 = (float)(tx0 + wx) + 0.5f, cy0 = (float)(ty0 + wy) + 0.5f;
