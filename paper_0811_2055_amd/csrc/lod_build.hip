@@ -551,6 +551,7 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
       for (int i = 0; i < DCH; ++i)
         snaps[i] = (uint32_t)((uint64_t)skey[min(base + (uint64_t)((c + i) * TB + threadIdx.x), N - 1)] >> sdb);
     }
+    uint32_t exact = 0;                      // items whose bin needs the exact key (rare)
 #pragma unroll
     for (int i = 0; i < DCH; ++i) {
       const int li = (c + i) * TB + threadIdx.x;
@@ -559,8 +560,21 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
         const uint32_t w = wl[li];
         const uint64_t U = particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed);
         w_out[e] = w;
-        kb_out[e] = (uint16_t)kbin(selection_key(U, w, a.alpha));
+        uint32_t bin;
+        if (a.alpha <= 0) bin = kbin(selection_key(U, w, a.alpha));
+        else if (!kbin_div_fast(U, w, bin)) exact |= 1u << i;
+        if (!((exact >> i) & 1u)) kb_out[e] = (uint16_t)bin;
       }
+    }
+    // one copy of the exact path, entered by few lanes
+    while (exact) {
+      const int i = __ffs(exact) - 1;
+      exact &= exact - 1u;
+      const int li = (c + i) * TB + threadIdx.x;
+      const uint64_t e = base + li;
+      const uint32_t snap = a.n_snap > 1 ? (uint32_t)((uint64_t)skey[e] >> sdb) : 0u;
+      const uint64_t U = particle_U(local_id(a, snap, sidx[e]), snap, a.seed);
+      kb_out[e] = (uint16_t)kbin(div_u2p31(U, wl[li]));
     }
   }
 }

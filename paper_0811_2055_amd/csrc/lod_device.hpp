@@ -71,6 +71,29 @@ __device__ __forceinline__ uint32_t kbin(uint64_t K) {
   return 128u + (uint32_t)(e - 7) * 64u + (uint32_t)((K >> (e - 6)) & 63u);
 }
 
+// kbin(floor(U 2^31 / w)) without the 64-bit quotient, when float64 decides
+// it.  The bin edges are integers, so the quotient lies in the bin of the
+// real x = U 2^31 / w.  In float64, x is found to within a relative 2^-50:
+// U is exact, 1/w comes from the hardware reciprocal refined by three Newton
+// steps (each squares the relative error and adds rounding: any start below
+// 2^-8 ends near 2^-52), and the product is rounded once.  Its bin is that of x unless x
+// lies within 64 float64 steps (2^-46 relative) of an edge (the 46 bits below
+// the bin bits are nearly all zeros or all ones) or below 256.  Returns false
+// in those (rare) cases: then the exact quotient decides.
+__device__ __forceinline__ bool kbin_div_fast(uint64_t U, uint32_t w, uint32_t &bin) {
+  const double wd = (double)w;
+  double r = __builtin_amdgcn_rcp(wd);
+  r = __builtin_fma(r, __builtin_fma(-wd, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-wd, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-wd, r, 1.0), r);
+  const double x = ((double)(uint32_t)(U - 1ull) + 1.0) * r * 2147483648.0;
+  const uint64_t bits = (uint64_t)__double_as_longlong(x);
+  const int E = (int)(bits >> 52) - 1023;
+  const uint64_t rest = bits & ((1ull << 46) - 1ull);
+  bin = 128u + (uint32_t)(E - 7) * 64u + (uint32_t)((bits >> 46) & 63u);
+  return E >= 8 && rest > 64ull && rest < (1ull << 46) - 64ull;
+}
+
 // w^alpha as float64 (alpha in {-1,0,1}).
 __device__ __forceinline__ double weight_pow(uint32_t w, int alpha) {
   if (alpha > 0) return (double)w;

@@ -114,3 +114,18 @@ def check_node_against_definition(h, v, x, y, z, m, n, D, dens, keys_D, snap=0):
     assert np.array_equal(h["qz"][pb:pb + pc], qz)
     assert ulp_diff(h["pt_mass"][pb:pb + pc], mass).max(initial=0) <= 1, v
     assert abs(h["node_mass"][v] - M) <= 1e-12 * M
+
+
+def kbin_of(K):
+    """The 12-bit log-scale bin the selection keeps per particle: K < 128 maps
+    to itself, larger K to 128 + 64 (e - 7) + the 6 bits after the leading one
+    (e = its index)."""
+    K = np.asarray(K, dtype=np.uint64)
+    e = np.zeros(K.shape, dtype=np.int64)
+    for b in range(1, 64):
+        e[(K >> np.uint64(b)) != 0] = b
+    out = np.where(K < 128, K, 0).astype(np.int64)
+    big = K >= 128
+    eb = e[big]
+    out[big] = 128 + 64 * (eb - 7) + ((K[big] >> (eb - 6).astype(np.uint64)) & np.uint64(63)).astype(np.int64)
+    return out
