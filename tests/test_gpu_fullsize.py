@@ -15,6 +15,8 @@ from oracle import lod as olod
 from oracle import splat as osplat
 from paper_0811_2055_amd import autotune, lib
 
+from gpu_util import kbin_of
+
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 
@@ -61,6 +63,11 @@ def test_sort_and_tree_properties(c3):
     kn = keys.cpu().numpy()
     lo = np.searchsorted(kn, kn[pos], "left"); hi = np.searchsorted(kn, kn[pos], "right")
     assert np.array_equal(w[torch.from_numpy(pos).cuda()].cpu().numpy(), hi - lo)
+    # key bins at the sampled positions: the bins of the oracle's keys K(U(id), w)
+    kb = b.view(3, torch.uint16).view(torch.int16).long() & 0xFFFF
+    U = olod.particle_uniform(gi.astype(np.uint64), 0, 0)
+    K = olod.selection_keys(U, (hi - lo).astype(np.uint64), 1)
+    assert np.array_equal(kb[torch.from_numpy(pos).cuda()].cpu().numpy(), kbin_of(K))
     # tree invariants
     n, D = 16000, 8
     internal = h["first_child"] != lib.NONE
