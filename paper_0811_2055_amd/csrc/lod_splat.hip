@@ -7,9 +7,10 @@
 // wave), so a tile's pair list depends on the input alone.  Each list is cut
 // into slices of at most 2048 points; one 256-thread block per slice adds the
 // separable blobs to its 16x16 tile as rank-64 products on the matrix cores
-// (MFMA 16x16x4, float32) and folds the four wave partials of a pixel into a
-// compensated (Neumaier) float32 sum.  A final pass adds a tile's slice
-// partials in slice order, again compensated.  No floating-point atomics:
+// (MFMA 16x16x4, float32).  Each wave folds its products into compensated
+// (Neumaier) float32 sums of its own, and the four wave sums of a pixel are
+// folded in wave order at the end of the slice.  A final pass adds a tile's
+// slice partials in slice order, again compensated.  No floating-point atomics:
 // the image is bit-reproducible.  The LOD render feeds the binning straight
 // from the tree's 16-bit node-relative points, decoding them in registers.
 //
