@@ -15,9 +15,11 @@
  *
  * Conventions shared by every entry point:
  *  - Every pointer named "device" is GPU memory owned by the caller; the
- *    library allocates nothing and keeps no state between calls.  Each call
- *    only enqueues work on `stream` (a hipStream_t; NULL = the null stream)
- *    and returns; results are valid once the stream has reached them.
+ *    library allocates no device memory and keeps no data between calls
+ *    (its only state is one extra stream and two events per device, used by
+ *    lod_build, and an open lod_trace_begin/lod_trace_end record).  Each call only enqueues work on `stream` (a hipStream_t;
+ *    NULL = the null stream) and returns; results are valid once the stream
+ *    has reached them.
  *  - Arguments are checked on the host before anything is enqueued; a bad
  *    argument returns LOD_EINVAL (or LOD_EUNSUPPORTED / LOD_ECAPACITY) and
  *    enqueues nothing.  Data-dependent errors found on the device (a
