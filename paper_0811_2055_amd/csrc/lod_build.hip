@@ -10,14 +10,18 @@
 //              LDS-staged coalesced writes; payload (id, fraction, mass) rides
 //              along so nothing is gathered at random afterwards
 //   density    run lengths of equal depth-L cells (block max/min scans), then
-//              Philox U and the integer selection key K per sorted position
-//   tree       level by level: octant boundaries by binary search, one-block
-//              compaction of the next level
-//   leaves     float64 node masses; leaves holding <= n copy their particles
-//   selection  bottom up, per node holding > n: radix select of the (n+1)-th
-//              smallest (K, id) over the children's top lists or own range,
-//              then an order-preserving compaction; float64 renormalisation,
-//              16-bit quantisation and output
+//              Philox U and the 12-bit bin of the integer selection key K per
+//              sorted position (on a second stream, beside the tree)
+//   tree       level by level: octant boundaries by binary search, then the
+//              next level emitted with one thread per (node, octant): counts,
+//              one scan, writes
+//   leaves     float64 leaf masses; the per-level schedule copies the leaves'
+//              particles inside its selection launches
+//   selection  bottom up, per node holding > n: the node's float64 mass from
+//              its children, the (n+1)-th smallest (K, id) over the children's
+//              top lists or own range (key-bin histogram, exact keys only in
+//              the threshold bin), then an order-preserving compaction;
+//              float64 renormalisation, 16-bit quantisation and output
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -558,7 +562,11 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
       if (li < (int)tile_n) {
         const uint64_t e = base + li;
         const uint32_t w = wl[li];
-        const uint64_t U = particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed);
+        // one snapshot: the counter's words 1-3 are zero, which folds the
+        // first round's second product
+        const uint64_t U = a.n_snap > 1 ? particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed)
+                                        : (uint64_t)philox_word0(ids[i], 0u, 0u, 0u, (uint32_t)a.seed,
+                                                                 (uint32_t)(a.seed >> 32)) + 1ull;
         w_out[e] = w;
         uint32_t bin;
         if (a.alpha <= 0) bin = kbin(selection_key(U, w, a.alpha));
@@ -930,18 +938,6 @@ __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s
   }
 }
 
-__global__ __launch_bounds__(TB) void k_internal_mass(BuildArgs a, TreeArgs t, int d) {
-  const uint32_t b = t.lvl[d], e = t.lvl[d + 1];
-  for (uint32_t v = b + blockIdx.x * blockDim.x + threadIdx.x; v < e; v += gridDim.x * blockDim.x) {
-    const uint32_t fc = t.first_child[v];
-    if (fc == NONE) continue;
-    const int nk = __popc((uint32_t)t.child_mask[v]);
-    double M = 0.0;
-    for (int k = 0; k < nk; ++k) M += t.node_mass[fc + k];
-    t.node_mass[v] = M;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // selection: per node holding > n particles, the n+1 smallest (K, id)
 
@@ -1136,7 +1132,18 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint32_t n = a.n;
   const int BS = blockDim.x;
   const uint32_t W = BS / WAVE, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  if (threadIdx.x == 0) build_segments(a, t, v, g);
+  if (threadIdx.x == 0) {
+    build_segments(a, t, v, g);
+    // an internal node's float64 mass: its children's, summed in octant order
+    // (read back by this block after the barriers below)
+    const uint32_t fc = t.first_child[v];
+    if (fc != NONE) {
+      const int nk = __popc((uint32_t)t.child_mask[v]);
+      double M = 0.0;
+      for (int k = 0; k < nk; ++k) M += t.node_mass[fc + k];
+      t.node_mass[v] = M;
+    }
+  }
   for (int i = threadIdx.x; i < KBINS; i += BS) hist[i] = 0;
   for (int i = threadIdx.x; i < 9 * (int)W; i += BS) pcnt[i] = 0;
   if (threadIdx.x == 0) { sh_b = 0; sh_below = 0; sh_cnt = 0; }
@@ -1597,16 +1604,9 @@ __global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArg
     __syncthreads();
     if (v == NONE) break;
     while (true) {
+      // the children's masses and lists, written by other blocks, are visible
+      // (select_node sums the node's mass from them)
       __threadfence();
-      if (threadIdx.x == 0) {
-        const uint32_t fc = t.first_child[v];
-        if (fc != NONE) {
-          const int nk = __popc((uint32_t)t.child_mask[v]);
-          double M = 0.0;
-          for (int k = 0; k < nk; ++k) M += t.node_mass[fc + k];
-          t.node_mass[v] = M;
-        }
-      }
       __syncthreads();
       select_node(a, t, s, sa, v);
       __threadfence();
@@ -1889,9 +1889,6 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
       return LOD_EDEVICE;
   }
   for (int d = D; d >= 0; --d) {
-    if (d < D)
-      LOD_LAUNCH(k_internal_mass, dim3((unsigned)std::min<uint64_t>(1024, L.node_cap / TB + 1)), dim3(TB), 0, st,
-                 a, t, d);
     if (p.mode == 0) {
       for (uint32_t v = hl[d]; v < hl[d + 1]; ++v) {
         if (hcount[v] <= p.n) continue;
