@@ -41,7 +41,9 @@ extern "C" {
 typedef enum {
   LOD_OK = 0,
   LOD_EINVAL = -1,        /* bad argument (null pointer, out-of-range parameter) */
-  LOD_EDOMAIN = -2,       /* input outside the method's domain (host-detected) */
+  LOD_EDOMAIN = -2,       /* reserved: no entry point returns it; positions or masses
+                             outside the domain are found on the device and reported
+                             by the status bit LOD_STATUS_DOMAIN instead */
   LOD_ENOMEM = -3,        /* workspace smaller than the plan requires */
   LOD_EDEVICE = -4,       /* a HIP call failed (launch error, no device) */
   LOD_ECAPACITY = -5,     /* an output array is smaller than its bound */
@@ -275,11 +277,14 @@ lod_status lod_autotune(const lod_input *in, lod_params *p, void *workspace, siz
 /* ---- introspection ----------------------------------------------------- */
 
 /* Device pointers into a lod_build workspace, valid after a build with the
- * same input sizes and parameters.  which: 0 sorted keys (uint32, snapshot
- * bits above 3D key bits), 1 sorted particle index (uint32, global), 2
- * density w (uint32, sorted order), 3 selection key K (uint64, sorted
- * order), 4 per-node witness sorted position (uint32, LOD_NONE if none).
- * For tests and diagnostics. */
+ * same input sizes and parameters.  which: 0 sorted keys (uint32 [N],
+ * snapshot bits above 3D key bits), 1 sorted particle index (uint32 [N],
+ * global), 2 density w (uint32 [N], sorted order), 3 the 12-bit key bin of
+ * the selection key K (uint16 [N], sorted order: K itself for K < 128, else
+ * 128 + 64 (e - 7) + the six bits of K after its leading one, e = the
+ * leading one's position; the exact 64-bit K is not kept), 4 per-node
+ * witness sorted position (uint32 [node capacity], LOD_NONE if none).
+ * *count receives the number of elements.  For tests and diagnostics. */
 lod_status lod_workspace_view(const lod_input *in, const lod_params *p, void *workspace,
                               uint32_t which, void **device_ptr, uint64_t *count);
 

@@ -26,6 +26,7 @@ kernel), the oracle implements one fixed reading; each is listed in the
 project's design notes and in the docstring of the function that uses it.
 
 Modules: ``philox`` (counter-based generator), ``lod`` (the build),
-``splat`` (render and its adjoint), ``cut`` (view-dependent node choice).
+``splat`` (render and its adjoint), ``cut`` (view-dependent node choice),
+``refine`` (one step of the gradient refinement of a node).
 """
-from . import philox, lod, splat, cut  # noqa: F401
+from . import philox, lod, splat, cut, refine  # noqa: F401

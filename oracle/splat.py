@@ -196,3 +196,60 @@ def render_backward(cam: Camera, x, y, z, m, grad_img, sigma=1.0, radius_sigmas=
             out[:] = gu * (a * r[ax] - bu * fw[ax]) + gv * (a * up[ax] - bv * fw[ax])
         gx[~keep] = 0.0; gy[~keep] = 0.0; gz[~keep] = 0.0
     return gm, np.stack([gx, gy, gz], axis=1)
+
+
+def render_backward_bound(cam: Camera, x, y, z, m, weight_img, sigma=1.0, radius_sigmas=3.0):
+    """Per-point sums of |dI_p/d(parameter)| * weight_img[p] (float64).
+
+    Returns (bm, bxyz [N, 3]): the sums of absolute contributions that bound,
+    element by element, how far a gradient sum_p dI_p/d(.) g_p can move when
+    each g_p (or each term) carries an error of at most weight_img[p].  Same
+    footprint and projection as `render_backward`.  The position bound adds
+    the magnitudes of the projection Jacobian's terms separately (perspective:
+    (|F/zc| |r| + |F xc/zc^2| |f|) for u, likewise for v), so it also covers
+    rounding in an evaluation that cancels those terms.
+    """
+    x = np.asarray(x, dtype=f32); npt = len(x)
+    bm = np.zeros(npt); bu = np.zeros(npt); bv = np.zeros(npt)
+    if npt == 0:
+        return bm, np.zeros((0, 3))
+    wimg = np.abs(np.asarray(weight_img, dtype=np.float64))
+    R32 = f32(radius_sigmas) * f32(sigma)
+    u, v, keep, xc, yc, zc = project(cam, x, y, z)
+    keep = _visible(cam, u, v, keep, float(R32))
+    s64 = float(f32(sigma))
+    inv2s2 = 1.0 / (2.0 * s64 * s64)
+    norm = 1.0 / (2.0 * math.pi * s64 * s64)
+    m64 = np.abs(np.asarray(m, dtype=f32).astype(np.float64))
+    win = _window(float(R32))
+    for dj in range(-win, win + 1):
+        for di in range(-win, win + 1):
+            i, j, ox, oy, ok = _covers(cam, u, v, keep, R32, di, dj)
+            if not ok.any():
+                continue
+            k = np.nonzero(ok)[0]
+            o64x = ox[k].astype(np.float64); o64y = oy[k].astype(np.float64)
+            G = np.exp(-(o64x * o64x + o64y * o64y) * inv2s2) * norm
+            wp = wimg[j[k], i[k]]
+            np.add.at(bm, k, G * wp)
+            np.add.at(bu, k, m64[k] * G * np.abs(o64x) / (s64 * s64) * wp)
+            np.add.at(bv, k, m64[k] * G * np.abs(o64y) / (s64 * s64) * wp)
+    out = np.zeros((npt, 3))
+    if cam.projection == 0:
+        out[:, 0] = bu * float(cam.W)
+        out[:, 1] = bv * float(cam.H)
+    else:
+        F = float(f32(cam.F))
+        zc64 = np.where(keep, zc.astype(np.float64), 1.0)
+        xc64 = xc.astype(np.float64); yc64 = yc.astype(np.float64)
+        r = np.array([float(f32(a)) for a in cam.right])
+        up = np.array([float(f32(a)) for a in cam.up])
+        fw = np.array([float(f32(a)) for a in cam.fwd])
+        a = F / zc64
+        cu = F * xc64 / (zc64 * zc64)
+        cv = F * yc64 / (zc64 * zc64)
+        for ax in range(3):
+            out[:, ax] = (bu * (np.abs(a * r[ax]) + np.abs(cu * fw[ax]))
+                          + bv * (np.abs(a * up[ax]) + np.abs(cv * fw[ax])))
+        out[~keep] = 0.0
+    return bm, out

@@ -64,6 +64,67 @@ class RefineResult:
     seconds: float
 
 
+class NodeRefiner:
+    """Adam over (log m, x, y, z) of one node's points against the renders of
+    its full particle set.  One `step()` is: zero the gradients, render the
+    points in every training view, loss and backward (the hand-written
+    adjoint), Adam, then clamp the positions to the node's cube and shift the
+    log-masses so that the masses sum to the node mass."""
+
+    def __init__(self, px, py, pz, pm, full, lo, side: float, node_mass: float, train_cams,
+                 lr_mass: float = 1e-2, lr_pos_frac: float = 1e-3, sigma: float = 1.0):
+        dev = px.device
+        self.sigma = sigma
+        self.cams = list(train_cams)
+        full_train = [lib.splat(*full, c, sigma) for c in self.cams]
+        self.means = [f.mean() for f in full_train]
+        self.targets = [log_image(f, mu) for f, mu in zip(full_train, self.means)]
+        self.theta = torch.log(pm.clamp_min(1e-30)).clone().requires_grad_(True)
+        self.xs = [a.clone().requires_grad_(True) for a in (px, py, pz)]
+        self.lr_mass, self.lr_pos = lr_mass, lr_pos_frac * side
+        self.opt = torch.optim.Adam([{"params": [self.theta], "lr": self.lr_mass},
+                                     {"params": self.xs, "lr": self.lr_pos}])
+        self.lo_t = [torch.tensor(float(v), device=dev) for v in lo]
+        self.hi_t = [torch.tensor(float(v) + side, device=dev) for v in lo]
+        self.logM = math.log(node_mass) if node_mass > 0 else 0.0
+
+    def loss(self):
+        m = torch.exp(self.theta)
+        loss = 0.0
+        for cam, tgt, mu in zip(self.cams, self.targets, self.means):
+            img = splat_render(self.xs[0], self.xs[1], self.xs[2], m, cam, self.sigma)
+            loss = loss + torch.mean((log_image(img, mu) - tgt) ** 2)
+        return loss / len(self.cams)
+
+    def step(self) -> float:
+        self.opt.zero_grad(set_to_none=True)
+        loss = self.loss()
+        loss.backward()
+        self.opt.step()
+        with torch.no_grad():
+            for a, l, h in zip(self.xs, self.lo_t, self.hi_t):
+                a.clamp_(l, h)
+            self.theta -= torch.logsumexp(self.theta, 0) - self.logM
+        return float(loss.detach())
+
+    def params(self):
+        """(theta, x, y, z, masses) detached."""
+        x, y, z = (a.detach() for a in self.xs)
+        return self.theta.detach(), x, y, z, torch.exp(self.theta).detach()
+
+    def grads(self):
+        """Gradients of the last step: (dL/dtheta, dL/dx, dL/dy, dL/dz)."""
+        return (self.theta.grad,) + tuple(a.grad for a in self.xs)
+
+    def adam_state(self, t):
+        """(exp_avg, exp_avg_sq, step) of parameter tensor t (zeros before the first step)."""
+        st = self.opt.state.get(t, {})
+        if not st:
+            z = torch.zeros_like(t)
+            return z, z, 0
+        return st["exp_avg"], st["exp_avg_sq"], int(st["step"])
+
+
 def refine_node(px, py, pz, pm, full, lo, side: float, node_mass: float, train_cams, test_cams,
                 steps: int = 200, lr_mass: float = 1e-2, lr_pos_frac: float = 1e-3, sigma: float = 1.0):
     """Refine one node's points (device float32 tensors) against its full particle set.
@@ -71,11 +132,7 @@ def refine_node(px, py, pz, pm, full, lo, side: float, node_mass: float, train_c
     full: (x, y, z, m) device tensors of every particle in the node's cube.
     lo: the cube's lower corner (3 floats); side: its edge length.
     """
-    dev = px.device
-    full_train = [lib.splat(*full, c, sigma) for c in train_cams]
     full_test = [lib.splat(*full, c, sigma) for c in test_cams]
-    means = [f.mean() for f in full_train]
-    targets = [log_image(f, mu) for f, mu in zip(full_train, means)]
 
     def evaluate(x, y, z, m):
         with torch.no_grad():
@@ -83,38 +140,18 @@ def refine_node(px, py, pz, pm, full, lo, side: float, node_mass: float, train_c
         return float(np.mean(errs))
 
     before = evaluate(px, py, pz, pm)
-    theta = torch.log(pm.clamp_min(1e-30)).clone().requires_grad_(True)
-    xs = [a.clone().requires_grad_(True) for a in (px, py, pz)]
-    opt = torch.optim.Adam([{"params": [theta], "lr": lr_mass},
-                            {"params": xs, "lr": lr_pos_frac * side}])
-    lo_t = [torch.tensor(float(v), device=dev) for v in lo]
-    hi_t = [torch.tensor(float(v) + side, device=dev) for v in lo]
-    logM = math.log(node_mass) if node_mass > 0 else 0.0
+    r = NodeRefiner(px, py, pz, pm, full, lo, side, node_mass, train_cams, lr_mass, lr_pos_frac, sigma)
     first = last = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        opt.zero_grad(set_to_none=True)
-        m = torch.exp(theta)
-        loss = 0.0
-        for cam, tgt, mu in zip(train_cams, targets, means):
-            img = splat_render(xs[0], xs[1], xs[2], m, cam, sigma)
-            loss = loss + torch.mean((log_image(img, mu) - tgt) ** 2)
-        loss = loss / len(train_cams)
-        loss.backward()
-        opt.step()
-        with torch.no_grad():
-            for a, l, h in zip(xs, lo_t, hi_t):
-                a.clamp_(l, h)
-            theta -= torch.logsumexp(theta, 0) - logM
-        v = float(loss.detach())
+        v = r.step()
         first = v if first is None else first
         last = v
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    with torch.no_grad():
-        after = evaluate(xs[0].detach(), xs[1].detach(), xs[2].detach(), torch.exp(theta).detach())
-    return RefineResult(before, after, first, last, steps, secs), (xs[0].detach(), xs[1].detach(),
-                                                                   xs[2].detach(), torch.exp(theta).detach())
+    _, x, y, z, m = r.params()
+    after = evaluate(x, y, z, m)
+    return RefineResult(before, after, first, last, steps, secs), (x, y, z, m)
 
 
 def main(argv=None):

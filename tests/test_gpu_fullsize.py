@@ -31,13 +31,14 @@ def c3():
     s = synth.config3()
     d = [torch.from_numpy(a).cuda() for a in (s.x, s.y, s.z, s.m)]
     b = lib.Builder(s.n, lib.BuildParams(n=16000, max_depth=8, seed=0))
-    autotune.tune(b, *d, path="/tmp/lod_tune_test.json")
+    rec = autotune.tune(b, *d, path="/tmp/lod_tune_test.json")
     log(f"schedule {b.params}")
     tree = b.build(*d)
     h = tree.host()
     log(f"built: {h['n_nodes']} nodes {h['n_points']} points status {h['status']}")
     keys_D = olod.interleave(*(olod.cell_coords(a, 8) for a in (s.x, s.y, s.z)), 8)
     log("oracle depth-8 keys")
+    b.tune_record = rec
     return s, d, b, tree, h, keys_D
 
 
@@ -130,3 +131,96 @@ def test_sampled_pixels_of_full_render(c3):
     want = osplat.render_pixels(osplat.Camera(0, 1024, 1024), s.x, s.y, s.z, s.m, pi, pj)
     got = img[pj, pi].astype(np.float64)
     assert np.all(np.abs(got - want) <= 1e-5 * want), (got, want)
+
+
+def test_every_schedule_byte_identical_at_full_size(c3):
+    """The persistent schedule (mode 2, the tuner's fastest grid for it) and the
+    per-level schedule with another block size give the same bytes as the tuned
+    build, on every output array."""
+    import torch
+    s, d, b, tree, h, keys_D = c3
+    mode2 = [(c, ms) for c, ms in b.tune_record["candidates"] if c["mode"] == 2]
+    assert mode2
+    best2 = min(mode2, key=lambda t: t[1])[0]
+    nn, npt = h["n_nodes"], h["n_points"]
+    for sched in (best2, {"mode": 1, "select_threads": 1024, "persistent_blocks": 0}):
+        p = lib.BuildParams(n=16000, max_depth=8, seed=0, mode=sched["mode"],
+                            select_threads=sched["select_threads"], persistent_blocks=sched["persistent_blocks"])
+        b2 = lib.Builder(s.n, p)
+        t2 = b2.build(*d)
+        torch.cuda.synchronize()
+        assert torch.equal(t2.counts, tree.counts), sched
+        for k, a in tree.arrays.items():
+            m = nn if k in ("prefix", "depth", "parent", "first_child", "child_mask", "part_begin", "part_count",
+                            "pt_begin", "pt_count", "node_mass") else npt
+            assert torch.equal(a[:m].view(torch.uint8), t2.arrays[k][:m].view(torch.uint8)), (sched, k)
+        log(f"schedule {sched}: byte-identical")
+        del b2, t2
+        torch.cuda.empty_cache()
+
+
+def test_thinned_cut_sampled_pixels(c3):
+    """A cut that thins (orthographic 1024^2, tau = 4 px: depth-4 nodes of at
+    most n points each, shallower leaves whole) drawn by the LOD render, on
+    sampled pixels of one depth-4 (x, y) column, against the oracle: the
+    column's part of the cut derived from the particles (ancestor counts), each
+    of its nodes' stored points from the definition (`node_direct`), decoded,
+    and the pixels summed in float64.  Pixels lie at least 4 px inside the
+    column, so no point outside it reaches them."""
+    import torch
+    s, d, b, tree, h, keys_D = c3
+    n, D, tau, W = 16000, 8, 4.0, 1024
+    cam = lib.Camera.ortho(W, W)
+    ids, nsel = lib.select_nodes(tree, cam, tau, n)
+    k = int(lib._to_numpy(nsel)[0])
+    cut = lib._to_numpy(ids[:k]).astype(np.int64)
+    depth = h["depth"].astype(np.int64)
+    leaf = h["first_child"] == lib.NONE
+    # the orthographic cut stops at the first depth whose spacing is <= tau
+    dstar = next(dd for dd in range(D + 1) if W * 2.0 ** -dd <= tau * np.cbrt(n))
+    assert dstar == 4
+    assert np.all((depth[cut] == dstar) | (leaf[cut] & (depth[cut] < dstar)))
+    drawn = int(h["pt_count"][cut].astype(np.int64).sum())
+    log(f"tau 4 cut: {k} nodes, {drawn} points drawn of {s.n}")
+    assert drawn < s.n // 2
+    img = lib.splat_lod(tree, ids, nsel, s.n, cam).cpu().numpy()
+    # the heaviest depth-4 (x, y) column
+    c4x = olod.cell_coords(s.x, 4); c4y = olod.cell_coords(s.y, 4)
+    col = np.bincount(c4x + 16 * c4y, minlength=256)
+    cx, cy = int(np.argmax(col) % 16), int(np.argmax(col) // 16)
+    shift = [np.uint64(3 * (D - dd)) for dd in range(D + 1)]
+    nodes = []
+    for cz in range(16):
+        for dd in range(0, dstar + 1):
+            c = (cx >> (dstar - dd), cy >> (dstar - dd), cz >> (dstar - dd))
+            pref = int(olod.interleave(np.array([c[0]]), np.array([c[1]]), np.array([c[2]]), dd)[0])
+            cnt = int(np.count_nonzero((keys_D >> shift[dd]) == np.uint64(pref)))
+            if cnt == 0:
+                break
+            if cnt <= n or dd == dstar:
+                if (dd, c) not in nodes:
+                    nodes.append((dd, c))
+                break
+    log(f"column ({cx}, {cy}): {len(nodes)} cut nodes from the definition")
+    dens = olod.density_counts(s.x, s.y, s.z, D)
+    X, Y, Z, M = [], [], [], []
+    for dd, c in nodes:
+        sel, qx, qy, qz, mass, _ = olod.node_direct(s.x, s.y, s.z, s.m, c, dd, n, D, dens_counts=dens, keys_D=keys_D)
+        X.append(olod.decode(qx, c[0], dd)); Y.append(olod.decode(qy, c[1], dd)); Z.append(olod.decode(qz, c[2], dd))
+        M.append(mass)
+    X, Y, Z, M = (np.concatenate(a) for a in (X, Y, Z, M))
+    rng = np.random.default_rng(3)
+    lo_i, hi_i = cx * 64 + 4, cx * 64 + 59
+    lo_j, hi_j = cy * 64 + 4, cy * 64 + 59
+    sub = img[lo_j:hi_j + 1, lo_i:hi_i + 1]
+    flat = np.argsort(-sub.ravel())[:4]
+    rnd = rng.choice(sub.size, 8, replace=False)
+    pix = np.concatenate([flat, rnd])
+    pi = lo_i + pix % sub.shape[1]; pj = lo_j + pix // sub.shape[1]
+    want = osplat.render_pixels(osplat.Camera(0, W, W), X, Y, Z, M, pi, pj)
+    got = img[pj, pi].astype(np.float64)
+    assert np.all((want > 0) | (got == 0))
+    ok = want > 0
+    err = np.abs(got[ok] - want[ok]) / want[ok]
+    log(f"thinned cut pixels: max relative error {err.max():.2e} over {ok.sum()} pixels")
+    assert err.max() <= 1e-5

@@ -312,8 +312,53 @@ def test_alpha0_equal_masses():
             assert np.all(np.abs(got.view(np.int32).astype(np.int64) - np.array(want).view(np.int32)) <= 1)
 
 
-def test_priority_sampling_unbiased():
-    """Before the rescale, the estimate sum(m/p) over the kept points is unbiased for M."""
+@pytest.mark.parametrize("alpha,p_sparse", [(1, 1.0 / 12.0), (0, 0.25), (-1, 65.0 / 108.0)])
+def test_inclusion_probability_direction(alpha, p_sparse):
+    """Weighting direction, from a closed form.  A root of four particles
+    keeps one: particle 0 alone in its depth-1 cell (w = 1), particles 1-3
+    sharing another (w = 3).  With priorities q = a / u, a = w^alpha and u
+    uniform, P(q_0 is largest) = int f_0(t) prod_j F_j(t) dt with
+    F_j(t) = 1 - a_j / t for t >= a_j:  1/12 for a = (1, 3, 3, 3),
+    1/4 for a = (1, 1, 1, 1), and 65/108 for a = (1, 1/3, 1/3, 1/3).
+    A swapped or sign-flipped key for any alpha lands on another of the
+    three values."""
+    x = np.array([0.1, 0.9, 0.8, 0.7], np.float32)
+    m = np.ones(4, np.float32)
+    trials = 2500
+    hits = np.zeros(4)
+    for seed in range(trials):
+        t = lod.lod_build(x, x, x, m, n=1, D=1, L_rho=1, alpha=alpha, seed=seed)
+        assert int(t.part_count[0]) == 4 and int(t.pt_count[0]) == 1
+        hits[int(t.pt_id[0])] += 1
+    want = np.array([p_sparse] + [(1.0 - p_sparse) / 3.0] * 3)
+    sd = np.sqrt(trials * want * (1 - want))
+    assert np.all(np.abs(hits - trials * want) < 5 * sd), (alpha, hits / trials, want)
+
+
+@pytest.mark.parametrize("alpha", [-1, 0, 1])
+def test_constant_density_orders_by_uniform(alpha):
+    """With every particle in one depth-L cell (w constant), each key is a
+    strictly increasing function of U, so a node keeps the n particles with
+    the smallest Philox draws (ids break no ties: the draws are distinct)."""
+    rng = np.random.default_rng(21)
+    N, n = 300, 40
+    x = (0.5 + 0.4 * rng.random(N)).astype(np.float32)
+    y = (0.5 + 0.4 * rng.random(N)).astype(np.float32)
+    z = (0.5 + 0.4 * rng.random(N)).astype(np.float32)
+    m = rng.uniform(0.5, 2.0, N).astype(np.float32)
+    t = lod.lod_build(x, y, z, m, n=n, D=1, L_rho=1, alpha=alpha, seed=77)
+    assert int(t.part_count[0]) == N
+    U = philox.particle_uniform(np.arange(N), 0, 77).astype(np.int64)
+    assert len(np.unique(U)) == N
+    want = set(np.argsort(U, kind="stable")[:n].tolist())
+    assert set(t.pt_id[:n].astype(np.int64).tolist()) == want
+
+
+@pytest.mark.parametrize("alpha", [-1, 0, 1])
+def test_priority_sampling_unbiased(alpha):
+    """Before the rescale, the estimate sum(m/p) over the kept points is unbiased for M
+    (priority sampling is unbiased for any positive priorities; a key that does not
+    match its inclusion probability p breaks it)."""
     rng = np.random.default_rng(8)
     N = 60
     x = rng.random(N).astype(np.float32) * np.float32(0.5)
@@ -323,7 +368,7 @@ def test_priority_sampling_unbiased():
     M = math.fsum(m.astype(np.float64).tolist())
     est = []
     for seed in range(2000):
-        t = lod.lod_build(x, y, z, m, n=12, D=3, L_rho=3, alpha=1, seed=seed)
+        t = lod.lod_build(x, y, z, m, n=12, D=3, L_rho=3, alpha=alpha, seed=seed)
         est.append(t.pt_mhat[:12].sum())
     est = np.array(est)
     se = est.std() / math.sqrt(len(est))
