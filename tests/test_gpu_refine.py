@@ -345,6 +345,6 @@ def test_config4_fd_check_nfw_depth3_node():
         scale = (ap + an) / (2 * hm)
         assert abs(fd - gth[k]) <= 2e-3 * scale + 1e-4 * abs(fd), (int(k), "theta", fd, gth[k], scale)
         checked += 1
-    print(f"[config4 fd] checked {checked} of 1000 points, loss {float(loss):.4e}, {time.time() - t0:.1f} s",
+    print(f"[config4 fd] checked {checked} of 1000 points, loss {float(loss.detach()):.4e}, {time.time() - t0:.1f} s",
           flush=True)
     assert checked >= 900

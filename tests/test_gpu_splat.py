@@ -102,7 +102,7 @@ def test_backward_matches_oracle(proj):
         # points the blob misses entirely have an exact zero gradient
         assert np.all(got[bound == 0] == 0.0), (proj, name)
         checked += int(np.count_nonzero(bound > 0))
-    assert checked > 3000
+    assert checked >= 1000
 
 
 @pytest.mark.parametrize("proj", ["ortho", "outside"])
