@@ -260,6 +260,27 @@ lod_status splat_render_backward(const float *x, const float *y, const float *z,
                                  float *grad_m, float *grad_x, float *grad_y,
                                  float *grad_z, lod_stream_t stream);
 
+/* ---- allocation-free splat --------------------------------------------- */
+
+/* Bytes of the device array that splat_render_noalloc uses as its workspace
+ * (one array per device, held until the process ends). */
+#define LOD_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): splat_render with
+ * its workspace taken from a fixed 64 MiB device array inside the library
+ * instead of a caller buffer.  Same arguments, image and bits as
+ * splat_render.  Allocates nothing (no hipMalloc, no library allocation);
+ * the first call on a device looks up that device's array address.
+ * LOD_ECAPACITY, with nothing enqueued, when splat_plan(count, cam, sp)
+ * exceeds LOD_NOALLOC_SCRATCH_BYTES (about 1.2 M points at 1024x1024 with
+ * the default blob).  All calls on one device share its array: calls that
+ * overlap in time on one device (several streams or host threads) race and
+ * must be serialised by the caller. */
+lod_status splat_render_noalloc(const float *x, const float *y, const float *z, const float *m,
+                                uint64_t count, const lod_camera *cam, const splat_params *sp,
+                                float *image, lod_stream_t stream);
+
 /* ---- schedule autotuning ------------------------------------------------ */
 
 /* Time lod_build on this input for each candidate schedule (mode 1 and 2,

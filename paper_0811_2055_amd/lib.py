@@ -22,7 +22,7 @@ NONE = 0xFFFFFFFF
 EXPORTS = [
     "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
     "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
-    "lod_decode_plan", "lod_decode", "lod_autotune",
+    "lod_decode_plan", "lod_decode", "lod_autotune", "splat_render_noalloc",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -93,6 +93,8 @@ def load():
                                      C.POINTER(SplatParamsC), P, C.c_size_t, P, P]
     lib.splat_render_backward.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(CameraC),
                                           C.POINTER(SplatParamsC), P, P, P, P, P, P]
+    lib.splat_render_noalloc.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC),
+                                         P, P]
     lib.lod_decode_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
     lib.lod_decode.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
     lib.lod_autotune.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_size_t, C.POINTER(TreeC),
@@ -417,6 +419,22 @@ def splat(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, workspace=None,
     camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
     _check(lib.splat_render(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp),
                             _ptr(workspace), workspace.numel(), _ptr(img), _stream()), "splat_render")
+    return img
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def splat_noalloc(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, out=None):
+    """splat_render with the library's fixed device scratch array as workspace
+    (no device allocation inside the call; `out` may be preallocated)."""
+    import torch
+    lib = load()
+    N = int(x.numel())
+    img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=x.device)
+    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    _check(lib.splat_render_noalloc(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp), _ptr(img),
+                                    _stream()), "splat_render_noalloc")
     return img
 
 
