@@ -37,33 +37,14 @@ KERNEL_BYTES = {
 }
 
 
-def selection_bytes(h, n):
-    """Algorithmic bytes of one build's per-level selection launches, which
-    also copy the leaves' particles to their stored points.
-
-    Per selecting node: every candidate read once (6 B per entry of a
-    selecting child's list: position and key bin; 2 B key bin per particle of
-    a leaf child or of the node's own range), its n stored points gathered
-    (id 4, codes 6, w 4, m 4) and written (14 B), its list of n+1 entries
-    written (6 B each).  Per
-    particle of a leaf holding at most n: 20 B read (key, id, fraction, mass)
-    and 14 B written.
-    """
-    import numpy as np
-    NONE = 0xFFFFFFFF
-    cnt = h["part_count"].astype(np.int64)
-    fc = h["first_child"].astype(np.int64)
-    par = h["parent"].astype(np.int64)
-    sel = cnt > n
-    has_parent = par != NONE
-    child_of_sel = np.zeros(cnt.size, dtype=bool)
-    child_of_sel[has_parent] = sel[par[has_parent]]
-    lists = int(np.count_nonzero(child_of_sel & sel))
-    ranges = int(cnt[child_of_sel & ~sel].sum()) + int(cnt[sel & (fc == NONE)].sum())
-    n_sel = int(np.count_nonzero(sel))
-    leaf_particles = int(cnt[(fc == NONE) & ~sel].sum())
-    return (6.0 * (n + 1) * lists + 2.0 * ranges + (18.0 + 14.0) * n * n_sel + 6.0 * (n + 1) * n_sel
-            + 34.0 * leaf_particles)
+def selection_bytes(N, S):
+    """The per-level selection launches' share of the build's compulsory bytes
+    B_alg = 48 N + 14 S: the positions read again in Morton order for the
+    node-relative quantisation (12 B per particle; the masses' 4 B are the
+    leaf-mass pass's share) and every stored point written once (14 B:
+    id 4, three 16-bit codes 6, mass 4).  Candidate re-reads, list traffic and
+    gathers are the design's own and are not counted."""
+    return 12.0 * N + 14.0 * S
 
 
 KERNEL_SOURCES = ["paper_0811_2055_amd/csrc/lod_build.hip", "paper_0811_2055_amd/csrc/lod_splat.hip",
@@ -100,17 +81,36 @@ def workload(name: str, count: int | None):
         N = count or 150_000_000
         return synth.config3(N), dict(n=16000, D=8, W=1024, H=1024, label=(
             f"Soneira-Peebles {N} particles (8 levels, eta 4, lambda 1.9, seed 3), n=16000, D=8, "
-            f"alpha=+1, ortho 1024x1024 splat sigma 1px, cut tau 1px"))
+            f"ortho 1024x1024 splat sigma 1px, cut tau 1px"))
     if name == "c2":
         s = synth.config2()
         return s, dict(n=16000, D=8, W=1024, H=1024, label=(
-            "NFW 16,777,216 particles (500 haloes + 20% uniform, seed 2), n=16000, D=8, alpha=+1, "
-            "ortho 1024x1024 splat sigma 1px, cut tau 1px"))
+            "NFW 16,777,216 particles (500 haloes + 20% uniform, seed 2), n=16000, D=8, "
+            "perspective 1024x1024 splat (FOV 60 deg, exterior camera) sigma 1px, cut tau 1px"))
     if name == "c1":
         s = synth.config1()
         return s, dict(n=4096, D=4, W=256, H=256, label=(
-            "Plummer mix 262,144 particles (seed 0), n=4096, D=4, alpha=+1, ortho 256x256 splat, cut tau 1px"))
+            "Plummer mix 262,144 particles (seed 0), n=4096, D=4, ortho 256x256 splat, cut tau 1px"))
     raise SystemExit(f"unknown workload {name}")
+
+
+def views(name: str, cfg):
+    """(label, camera) pairs: orthographic for c1 and c3; for c2 one exterior
+    camera at (0.5, 0.5, -0.9) looking at the box centre and three seeded
+    interior cameras (positions uniform in [0.2, 0.8]^3, looking at a seeded
+    point), FOV 60 degrees."""
+    import numpy as np
+    from paper_0811_2055_amd import lib
+    W, H = cfg["W"], cfg["H"]
+    if name != "c2":
+        return [("ortho", lib.Camera.ortho(W, H))]
+    out = [("exterior", lib.Camera.look_at((0.5, 0.5, -0.9), (0.5, 0.5, 0.5), W, H, 60.0))]
+    rng = np.random.default_rng(18)
+    for i in range(3):
+        pos = tuple(float(a) for a in rng.uniform(0.2, 0.8, 3))
+        tgt = tuple(float(a) for a in rng.uniform(0.0, 1.0, 3))
+        out.append((f"interior{i}", lib.Camera.look_at(pos, tgt, W, H, 60.0, near=1e-4)))
+    return out
 
 
 def image_errors(lod_img, full_img):
@@ -129,22 +129,69 @@ def image_errors(lod_img, full_img):
     return dict(E_log=e_log, E_tone=e_tone, E_L1=e_l1)
 
 
-def cpu_baseline(snap, cfg, sample: int):
-    """Time the CPU oracle (build + cut + LOD render) on the first `sample` particles."""
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
+def cpu_baseline(snap, cfg, sample: int, alpha: int, repeats: int):
+    """Time the CPU oracle (build + cut + LOD render, numpy, one thread) on the
+    first `sample` particles; median of `repeats` runs."""
+    import statistics
     from oracle import cut as ocut
     from oracle import lod as olod
     from oracle import splat as osplat
     sub = snap.subset(min(sample, snap.n))
-    t0 = time.perf_counter()
-    tr = olod.lod_build(sub.x, sub.y, sub.z, sub.m, n=cfg["n"], D=cfg["D"], alpha=1, seed=0)
-    cam = osplat.Camera(0, cfg["W"], cfg["H"])
-    c = ocut.select(tr, cam, 1.0, cfg["n"])
-    px, py, pz, pm = olod.decoded_points(tr, c)
-    osplat.render(cam, px, py, pz, pm)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        tr = olod.lod_build(sub.x, sub.y, sub.z, sub.m, n=cfg["n"], D=cfg["D"], alpha=alpha, seed=0)
+        cam = osplat.Camera(0, cfg["W"], cfg["H"])
+        c = ocut.select(tr, cam, 1.0, cfg["n"])
+        px, py, pz, pm = olod.decoded_points(tr, c)
+        osplat.render(cam, px, py, pz, pm)
+        times.append(time.perf_counter() - t0)
+    dt = statistics.median(times)
+    model, avail = host_cpu()
+    whole = "all" if sub.n == snap.n else f"the first {sub.n:,} of {snap.n:,}"
     return {"value": sub.n / dt / 1e6, "unit": "Mparticles/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {sub.n:,} particles of the same (shuffled) snapshot, same n and D; "
-                       f"numpy oracle build + cut + LOD render, single thread, {dt:.1f} s")}
+            "sample": (f"{whole} particles of the same (shuffled) snapshot, same n and D; numpy oracle build + "
+                       f"cut + orthographic LOD render, single thread, median of {repeats}: {dt:.1f} s"),
+            "cpu_model": model, "host_cpus_available": avail}
+
+
+def lod_sweep(tree, full_imgs, cams, taus, n, max_draw, sel_ws, lod_ws, N):
+    """For every view and tau: the cut's points drawn and the LOD-vs-full errors."""
+    import numpy as np
+    import torch
+    from paper_0811_2055_amd import lib
+    rows = []
+    pt_count = lib._to_numpy(tree.arrays["pt_count"]).astype(np.int64)
+    for (label, cam), full in zip(cams, full_imgs):
+        img = torch.empty((cam.H, cam.W), dtype=torch.float32, device=full.device)
+        for tau in taus:
+            ids, nsel = lib.select_nodes(tree, cam, tau, n, workspace=sel_ws)
+            k = int(lib._to_numpy(nsel)[0])
+            cut = lib._to_numpy(ids[:k]).astype(np.int64)
+            lib.splat_lod(tree, ids, nsel, max_draw, cam, workspace=lod_ws, out=img)
+            torch.cuda.synchronize()
+            e = image_errors(img, full)
+            rows.append({"view": label, "tau_px": tau, "nodes": k, "points_drawn": int(pt_count[cut].sum()),
+                         "drawn_frac": round(int(pt_count[cut].sum()) / N, 4),
+                         **{kk: float(f"{v:.4g}") for kk, v in e.items()}})
+    return rows
 
 
 def main():
@@ -154,15 +201,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--count", type=int, default=None, help="override the particle count (c3)")
-    ap.add_argument("--cpu-sample", type=int, default=5_000_000)
+    ap.add_argument("--alpha", type=int, default=1, choices=[-1, 0, 1], help="density exponent")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="particles the CPU oracle is timed on (default: all of c1 and c2, 5M of c3)")
     ap.add_argument("--mode", type=int, default=1, choices=[0, 1, 2],
                     help="selection schedule: 0 per-node launches, 1 per-level launches, 2 one persistent launch")
     ap.add_argument("--select-threads", type=int, default=512, help="threads per node block in the selection")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default selection schedule")
-    ap.add_argument("--compare-modes", action="store_true",
-                    help="also time one build in each selection schedule")
+    ap.add_argument("--no-compare-modes", action="store_true",
+                    help="skip timing one build in each selection schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-render", action="store_true")
+    ap.add_argument("--taus", default="1,2,4,8", help="cut thresholds (px) of the LOD-vs-full sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter calibration)")
     ap.add_argument("--profile-steps", type=int, default=None,
@@ -171,6 +221,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py runs on exactly one GPU: this build has no multi-GPU path "
                  "(the sharding design is described in DESIGN.md); use --gpus 1")
+
+    import statistics
 
     import numpy as np
     import torch
@@ -183,17 +235,18 @@ def main():
     log(f"[bench] workload generated: {snap.n} particles in {time.perf_counter() - t0:.1f} s")
     x, y, z, m = (torch.from_numpy(a).to(dev) for a in (snap.x, snap.y, snap.z, snap.m))
     N = snap.n
-    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=args.mode,
+    params = lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=args.alpha, seed=0, mode=args.mode,
                              select_threads=args.select_threads)
     builder = lib.Builder(N, params, dev)
-    cam = lib.Camera.ortho(cfg["W"], cfg["H"])
+    cams = views(args.workload, cfg)
+    cam = cams[0][1]
     tree = builder.tree
     sel_ws_bytes = lib.C.c_size_t()
     lib.load().lod_select_plan(tree.node_capacity, lib.C.byref(sel_ws_bytes))
     sel_ws = torch.empty(max(sel_ws_bytes.value, 256), dtype=torch.uint8, device=dev)
     max_draw = N          # a cut never draws more points than particles
-    lod_ws = torch.empty(lib.splat_lod_workspace_bytes(tree.node_capacity, max_draw, cam), dtype=torch.uint8,
-                         device=dev)
+    lod_ws = torch.empty(max(lib.splat_lod_workspace_bytes(tree.node_capacity, max_draw, c) for _, c in cams),
+                         dtype=torch.uint8, device=dev)
     lod_img = torch.empty((cfg["H"], cfg["W"]), dtype=torch.float32, device=dev)
     log(f"[bench] workspace {builder.ws_bytes / 1e9:.2f} GB, tree caps {tree.node_capacity} nodes "
         f"{tree.point_capacity} points, splat ws {lod_ws.numel() / 1e9:.2f} GB")
@@ -231,16 +284,22 @@ def main():
         raise SystemExit(f"build status word {h['status']}")
     log(f"[bench] warmup done: {h['n_nodes']} nodes, {h['n_points']} stored points")
 
+    # the timed region: exactly K steps between two synchronisations, plus an
+    # event pair around every step (all on the stream the library launches on)
     stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(args.steps):
+    for a, b in ev:
+        a.record(stream)
         step()
+        b.record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / args.steps
-    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step")
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step (median {statistics.median(step_ms):.3f})")
 
     # per-kernel timing over a second timed region with every launch bracketed by events
     with lib.trace() as tr:
@@ -253,24 +312,25 @@ def main():
         builder.build(x, y, z, m)
     for name, _ in tb.records:
         build_kernels.add(name)
-    # build wall time on the stream (the density kernel overlaps the tree
-    # construction on a second stream, so kernel times do not add up to it)
-    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # build wall time on the stream, per build (the density kernel overlaps the
+    # tree construction on a second stream, so kernel times do not add up to it)
+    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    b0.record(stream)
-    for _ in range(args.steps):
+    for a, b in bev:
+        a.record(stream)
         builder.build(x, y, z, m)
-    b1.record(stream)
+        b.record(stream)
     torch.cuda.synchronize()
-    build_ms = b0.elapsed_time(b1) / args.steps
+    build_runs = [a.elapsed_time(b) for a, b in bev]
+    build_ms = statistics.median(build_runs)
+    S = h["n_points"]
     dom = max(per_step.items(), key=lambda kv: kv[1][1])
     dom_name, (dom_launches, dom_ms_step) = dom
     dom_avg = summ[dom_name][1] / summ[dom_name][0]
     per_unit = KERNEL_BYTES.get(dom_name)
     if dom_name == "k_select_level" and builder.params.mode == 1:
-        # one launch per level: the per-launch figure is the build's total over its launches
-        launch_bytes = selection_bytes(h, cfg["n"]) / dom_launches
-        per_unit = launch_bytes / N
+        # one launch per level: the per-launch figure is the build's share over its launches
+        per_unit = selection_bytes(N, S) / dom_launches / N
     if per_unit is not None:
         achieved = per_unit * N / (dom_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -296,7 +356,6 @@ def main():
     roof["copy_measured_GBs"] = round(copy_gbs, 1)
     if roof.get("achieved") is not None:
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
-    S = h["n_points"]
     b_alg = 48.0 * N + 14.0 * S
     build_frac = b_alg / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
 
@@ -307,39 +366,42 @@ def main():
 
     extra = {}
     if not args.no_full_render:
-        full_ws = torch.empty(lib.splat_workspace_bytes(N, cam), dtype=torch.uint8, device=dev)
-        full = lib.splat(x, y, z, m, cam, workspace=full_ws)
+        full_ws = torch.empty(max(lib.splat_workspace_bytes(N, c) for _, c in cams), dtype=torch.uint8, device=dev)
+        fulls = [lib.splat(x, y, z, m, c, workspace=full_ws) for _, c in cams]
         torch.cuda.synchronize()
         f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         f0.record(stream)
         reps = 3
         for _ in range(reps):
-            lib.splat(x, y, z, m, cam, workspace=full_ws, out=full)
+            lib.splat(x, y, z, m, cam, workspace=full_ws, out=fulls[0])
         f1.record(stream)
         torch.cuda.synchronize()
         full_ms = f0.elapsed_time(f1) / reps
         extra["splat_full_ms"] = round(full_ms, 3)
         extra["splat_full_Mpts_s"] = round(N / full_ms / 1e3, 1)
-        step()
-        torch.cuda.synchronize()
-        extra.update({k: float(f"{v:.4g}") for k, v in image_errors(lod_img, full).items()})
         del full_ws
+        taus = [float(t) for t in args.taus.split(",")]
+        sweep = lod_sweep(tree, fulls, cams, taus, cfg["n"], max_draw, sel_ws, lod_ws, N)
+        first = next(r for r in sweep if r["view"] == cams[0][0] and r["tau_px"] == 1.0) \
+            if 1.0 in taus else sweep[0]
+        extra.update({kk: first[kk] for kk in ("E_log", "E_tone", "E_L1")})
+        extra["lod_vs_full"] = sweep
+        del fulls
 
-    if args.compare_modes:
+    if not args.no_compare_modes:
         by_mode = {}
         for md in (0, 1, 2):
-            bm = lib.Builder(N, lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=1, seed=0, mode=md), dev)
+            bm = lib.Builder(N, lib.BuildParams(n=cfg["n"], max_depth=cfg["D"], alpha=args.alpha, seed=0,
+                                                mode=md), dev)
             bm.build(x, y, z, m)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            bm.build(x, y, z, m)
-            torch.cuda.synchronize()
-            by_mode[str(md)] = round((time.perf_counter() - t0) * 1e3, 3)
-            if md == 1:
-                with lib.trace() as tl:
-                    bm.build(x, y, z, m)
-                extra["select_ms_by_level_per_level_schedule"] = [
-                    round(ms, 4) for name, ms in tl.records if name in ("k_select_level", "k_sel_output")]
+            runs = []
+            for _ in range(1 if md == 0 else 5):
+                t0 = time.perf_counter()
+                bm.build(x, y, z, m)
+                torch.cuda.synchronize()
+                runs.append((time.perf_counter() - t0) * 1e3)
+            by_mode[str(md)] = round(statistics.median(runs), 3)
             hm = bm.tree.host()
             for key in ("pt_id", "qx", "qy", "qz", "pt_mass", "prefix", "part_count"):
                 if not np.array_equal(hm[key], h[key]):
@@ -347,6 +409,9 @@ def main():
             del bm
             torch.cuda.empty_cache()
         extra["build_ms_by_schedule"] = by_mode
+        extra["build_schedules"] = ("0: one selection launch per node (host-synchronised), 1: one launch per "
+                                    "level, 2: one persistent launch; default grids, wall time with a "
+                                    "synchronisation, median of 5 (mode 0: one run); outputs byte-identical")
         log(f"[bench] build ms by schedule: {by_mode}")
 
     splat_ms = sum(t for k, (c, t) in per_step.items() if k not in build_kernels)
@@ -358,20 +423,23 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_median": round(statistics.median(step_ms), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32/u64 keys, f64 masses, f32 splat",
         "data": "synthetic",
         "config": {"workload": cfg["label"], "particles": N, "n": cfg["n"], "max_depth": cfg["D"],
-                   "image": f"{cfg['W']}x{cfg['H']}", "parallelism": "single GPU"},
+                   "alpha": args.alpha, "image": f"{cfg['W']}x{cfg['H']}", "parallelism": "single GPU"},
         "roofline": roof,
         "schedule": tuned or {"mode": builder.params.mode, "select_threads": builder.params.select_threads,
                               "persistent_blocks": builder.params.persistent_blocks},
         "build_ms": round(build_ms, 4),
+        "build_ms_runs": "median of %d event-timed builds" % len(build_runs),
         "build_Mparticles_s": round(N / build_ms / 1e3, 1),
         "build_B_alg_GB": round(b_alg / 1e9, 3),
         "build_frac_hbm_B_alg": round(build_frac, 4),
+        "build_frac_copy_B_alg": round(b_alg / (build_ms * 1e-3) / 1e9 / copy_gbs, 4),
         "stored_points": S,
         "nodes": h["n_nodes"],
         "lod_points_drawn": drawn,
@@ -382,8 +450,9 @@ def main():
     }
     out.update(extra)
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(snap, cfg, args.cpu_sample)
+        sample = args.cpu_sample or (5_000_000 if args.workload == "c3" else N)
+        log(f"[bench] timing the CPU oracle on {sample} particles")
+        out["cpu_baseline"] = cpu_baseline(snap, cfg, sample, args.alpha, 3 if sample <= 1_000_000 else 1)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
