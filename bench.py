@@ -388,6 +388,40 @@ def main():
         extra["lod_vs_full"] = sweep
         del fulls
 
+    # ID highlighting (the paper claims no cost for testing each drawn point
+    # against up to a million selected ids) and the radial cubic blob: the
+    # timed step's LOD render, plain versus highlighted versus cubic
+    def timed(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return statistics.median(ts)
+    ids1, nsel1 = lib.select_nodes(tree, cam, 1.0, cfg["n"], workspace=sel_ws)
+    hl_ids = np.random.default_rng(7).choice(N, min(1_000_000, N), replace=False)
+    bits = lib.highlight_bits(hl_ids, N, dev)
+    hl_img = torch.empty_like(lod_img)
+    lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, bits, N, workspace=lod_ws, out=lod_img, out_hl=hl_img)
+    plain_ms = timed(lambda: lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=lod_ws, out=lod_img))
+    hl_ms = timed(lambda: lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, bits, N, workspace=lod_ws,
+                                                  out=lod_img, out_hl=hl_img))
+    extra["highlight"] = {"selected_ids": int(len(hl_ids)), "lod_render_ms": round(plain_ms, 4),
+                          "lod_render_highlight_ms": round(hl_ms, 4),
+                          "penalty_frac": round(hl_ms / plain_ms - 1.0, 4),
+                          "highlighted_mass_frac": round(float(hl_img.double().sum() / lod_img.double().sum()), 4)}
+    cub = lib.Blob.cubic(h_px=1.5)
+    cub_ws = torch.empty(lib.splat_lod_workspace_bytes(tree.node_capacity, max_draw, cam, blob=cub),
+                         dtype=torch.uint8, device=dev)
+    cub_ms = timed(lambda: lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=cub_ws, out=lod_img, blob=cub))
+    extra["cubic_blob"] = {"h_px": 1.5, "lod_render_ms": round(cub_ms, 4),
+                           "Mpts_s": round(drawn / cub_ms / 1e3, 1)}
+    del cub_ws, bits, hl_img
+    log(f"[bench] highlight {extra['highlight']}, cubic {extra['cubic_blob']}")
+
     if not args.no_compare_modes:
         by_mode = {}
         for md in (0, 1, 2):

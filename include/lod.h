@@ -147,12 +147,27 @@ typedef struct {
   float F, near_z;
 } lod_camera;
 
-/* Gaussian blob of standard deviation sigma_px pixels, truncated to the
- * square |ox|,|oy| <= radius_sigmas * sigma_px, normalised by 1/(2 pi s^2).
- * sigma_px in (0, 8], radius_sigmas in (0, 6]. */
+/* Blob kinds (rendering paragraph: every point drawn as a smeared blob; the
+ * paper names a radial cubic function). */
+#define LOD_BLOB_GAUSSIAN 0u
+#define LOD_BLOB_CUBIC 1u
+
+/* blob = LOD_BLOB_GAUSSIAN: a Gaussian of standard deviation sigma_px
+ * pixels, truncated to the square |ox|,|oy| <= radius_sigmas * sigma_px,
+ * normalised by 1/(2 pi s^2); sigma_px in (0, 8], radius_sigmas in (0, 6].
+ * blob = LOD_BLOB_CUBIC: the compact cubic spline W(r; h) = 40/(7 pi h^2)
+ * w(r/h), w(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q < 1), 0
+ * beyond; a pixel takes a point iff ox^2 + oy^2 < h^2 (the squares of the
+ * float32 offsets summed in float64).  Radius h: h_px pixels in (0, 16]
+ * when h_world is 0; with a perspective camera and h_world > 0 the
+ * projected world radius fl(fl(F h_world) / zc), clamped to [1, 16] pixels.
+ * sigma_px and radius_sigmas are ignored for the cubic blob. */
 typedef struct {
   float sigma_px;
   float radius_sigmas;
+  uint32_t blob;
+  float h_px;
+  float h_world;
 } splat_params;
 
 /* ---- level-of-detail build ------------------------------------------- */
@@ -206,7 +221,8 @@ lod_status lod_select(const lod_tree *tree, const lod_camera *cam, float tau_px,
 
 /* ---- additive point splat (rendering paragraph) ----------------------- */
 
-/* Workspace bytes for splatting up to max_points points with cam/sp. */
+/* Workspace bytes for splatting up to max_points points with cam/sp, by
+ * splat_render or splat_render_aux. */
 lod_status splat_plan(uint64_t max_points, const lod_camera *cam, const splat_params *sp,
                       size_t *workspace_bytes);
 
@@ -220,8 +236,17 @@ lod_status splat_render(const float *x, const float *y, const float *z, const fl
                         void *workspace, size_t workspace_bytes, float *image,
                         lod_stream_t stream);
 
-/* Workspace bytes for splat_render_lod on a tree of node_capacity nodes
- * drawing at most max_points points. */
+/* Second image channel: image_aux[j*W + i] = sum_k m_k a_k W_k(i, j) for a
+ * per-point attribute a (device float32 [count]), e.g. a colour value or a
+ * 0/1 selection; image as splat_render.  Same blobs, binning and sums as
+ * splat_render (the rendering paragraph's per-point properties).  workspace
+ * as sized by splat_plan. */
+lod_status splat_render_aux(const float *x, const float *y, const float *z, const float *m, const float *aux,
+                            uint64_t count, const lod_camera *cam, const splat_params *sp, void *workspace,
+                            size_t workspace_bytes, float *image, float *image_aux, lod_stream_t stream);
+
+/* Workspace bytes for splat_render_lod and splat_render_lod_highlight on a
+ * tree of node_capacity nodes drawing at most max_points points. */
 lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,
                           const splat_params *sp, size_t *workspace_bytes);
 
@@ -234,6 +259,19 @@ lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids,
                             const lod_camera *cam, const splat_params *sp,
                             void *workspace, size_t workspace_bytes, float *image,
                             lod_stream_t stream);
+
+/* ID highlighting (highlighting paragraph: points whose id is in a list of
+ * up to a million selected ids, tested as each point is drawn).  As
+ * splat_render_lod, plus image_hl (device float32 [H*W]) = the same render
+ * restricted to stored points whose pt_id has its bit set in the bitset
+ * `bits` (device uint32 [ceil(n_bits/32)], bit i of word i/32 = id i; ids
+ * >= n_bits are not highlighted).  The membership test runs inside the
+ * binning pass. */
+lod_status splat_render_lod_highlight(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                                      uint64_t max_points, const lod_camera *cam, const splat_params *sp,
+                                      const uint32_t *bits, uint64_t n_bits, void *workspace,
+                                      size_t workspace_bytes, float *image, float *image_hl,
+                                      lod_stream_t stream);
 
 /* Workspace bytes for lod_decode on a tree of node_capacity nodes. */
 lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes);

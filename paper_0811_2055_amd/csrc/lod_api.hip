@@ -41,8 +41,19 @@ lod_status check_inputs(const lod_input *in, const lod_params *p) {
 bool check_camera(const lod_camera *c, const splat_params *sp) {
   if (!c || !sp) return false;
   if (c->projection > 1 || c->W == 0 || c->H == 0 || c->W > 16384 || c->H > 16384) return false;
-  if (!(sp->sigma_px > 0.0f && sp->sigma_px <= 8.0f)) return false;
-  if (!(sp->radius_sigmas > 0.0f && sp->radius_sigmas <= 6.0f)) return false;
+  if (sp->blob == LOD_BLOB_GAUSSIAN) {
+    if (!(sp->sigma_px > 0.0f && sp->sigma_px <= 8.0f)) return false;
+    if (!(sp->radius_sigmas > 0.0f && sp->radius_sigmas <= 6.0f)) return false;
+  } else if (sp->blob == LOD_BLOB_CUBIC) {
+    if (sp->h_world != 0.0f) {
+      if (!(sp->h_world > 0.0f) || !std::isfinite(sp->h_world) || c->projection != 1) return false;
+      if (!std::isfinite(c->F * sp->h_world)) return false;
+    } else if (!(sp->h_px > 0.0f && sp->h_px <= lodh::BLOB_H_MAX)) {
+      return false;
+    }
+  } else {
+    return false;
+  }
   if (c->projection == 1) {
     if (!(c->near_z > 0.0f) || !std::isfinite(c->F) || !(c->F > 0.0f)) return false;
     for (int i = 0; i < 3; ++i)
@@ -135,7 +146,7 @@ lod_status lod_select(const lod_tree *tree, const lod_camera *cam, float tau_px,
                       lod_stream_t stream) {
   if (!tree_arrays_ok(tree) || !cam || !node_ids || !n_selected || !workspace) return LOD_EINVAL;
   if (n < 1 || !(tau_px > 0.0f) || !std::isfinite(tau_px) || cap == 0) return LOD_EINVAL;
-  splat_params dummy{1.0f, 3.0f};
+  splat_params dummy{1.0f, 3.0f, LOD_BLOB_GAUSSIAN, 0.0f, 0.0f};
   if (!check_camera(cam, &dummy)) return LOD_EINVAL;
   if (workspace_bytes < lodh::cut_workspace(tree->node_capacity)) return LOD_ENOMEM;
   return lodh::launch_cut(*tree, *cam, tau_px, n, node_ids, cap, n_selected, workspace, (hipStream_t)stream);
@@ -144,37 +155,69 @@ lod_status lod_select(const lod_tree *tree, const lod_camera *cam, float tau_px,
 lod_status splat_plan(uint64_t max_points, const lod_camera *cam, const splat_params *sp, size_t *workspace_bytes) {
   if (!workspace_bytes || !check_camera(cam, sp)) return LOD_EINVAL;
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(max_points, *cam, *sp, L);
+  lod_status s = lodh::splat_layout(max_points, *cam, *sp, L, true);   // covers both forms
   if (s != LOD_OK) return s;
   *workspace_bytes = L.total;
   return LOD_OK;
 }
 
-lod_status splat_render(const float *x, const float *y, const float *z, const float *m, uint64_t count,
-                        const lod_camera *cam, const splat_params *sp, void *workspace, size_t workspace_bytes,
-                        float *image, lod_stream_t stream) {
+static lod_status splat_common(const float *x, const float *y, const float *z, const float *m, const float *aux,
+                               uint64_t count, const lod_camera *cam, const splat_params *sp, void *workspace,
+                               size_t workspace_bytes, float *image, float *image_aux, lod_stream_t stream) {
   if (!check_camera(cam, sp) || !image || !workspace) return LOD_EINVAL;
   if (count && (!x || !y || !z || !m)) return LOD_EINVAL;
   if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(count, *cam, *sp, L);
+  lod_status s = lodh::splat_layout(count, *cam, *sp, L, image_aux != nullptr);
   if (s != LOD_OK) return s;
   if (workspace_bytes < L.total) return LOD_ENOMEM;
-  return lodh::launch_splat(x, y, z, m, count, *cam, *sp, workspace, L, image, (hipStream_t)stream);
+  return lodh::launch_splat(x, y, z, m, aux, count, *cam, *sp, workspace, L, image, image_aux, (hipStream_t)stream);
 }
 
-lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
-                            uint64_t max_points, const lod_camera *cam, const splat_params *sp, void *workspace,
-                            size_t workspace_bytes, float *image, lod_stream_t stream) {
+lod_status splat_render(const float *x, const float *y, const float *z, const float *m, uint64_t count,
+                        const lod_camera *cam, const splat_params *sp, void *workspace, size_t workspace_bytes,
+                        float *image, lod_stream_t stream) {
+  return splat_common(x, y, z, m, nullptr, count, cam, sp, workspace, workspace_bytes, image, nullptr, stream);
+}
+
+lod_status splat_render_aux(const float *x, const float *y, const float *z, const float *m, const float *aux,
+                            uint64_t count, const lod_camera *cam, const splat_params *sp, void *workspace,
+                            size_t workspace_bytes, float *image, float *image_aux, lod_stream_t stream) {
+  if (!image_aux || (count && !aux)) return LOD_EINVAL;
+  return splat_common(x, y, z, m, aux, count, cam, sp, workspace, workspace_bytes, image, image_aux, stream);
+}
+
+static lod_status splat_lod_common(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                                   uint64_t max_points, const lod_camera *cam, const splat_params *sp,
+                                   const uint32_t *bits, uint64_t n_bits, void *workspace, size_t workspace_bytes,
+                                   float *image, float *image_hl, lod_stream_t stream) {
   if (!tree_arrays_ok(tree) || !node_ids || !n_ids || !check_camera(cam, sp) || !image || !workspace)
     return LOD_EINVAL;
   if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
   lodh::LodDrawLayout D = lodh::lod_draw_layout(tree->node_capacity, max_points);
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L);
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, image_hl != nullptr);
   if (s != LOD_OK) return s;
   if (workspace_bytes < D.total + L.total) return LOD_ENOMEM;
-  return lodh::launch_splat_lod(*tree, node_ids, n_ids, workspace, D, *cam, *sp, L, image, (hipStream_t)stream);
+  return lodh::launch_splat_lod(*tree, node_ids, n_ids, workspace, D, *cam, *sp, L, bits, n_bits, image, image_hl,
+                                (hipStream_t)stream);
+}
+
+lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                            uint64_t max_points, const lod_camera *cam, const splat_params *sp, void *workspace,
+                            size_t workspace_bytes, float *image, lod_stream_t stream) {
+  return splat_lod_common(tree, node_ids, n_ids, max_points, cam, sp, nullptr, 0, workspace, workspace_bytes, image,
+                          nullptr, stream);
+}
+
+lod_status splat_render_lod_highlight(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                                      uint64_t max_points, const lod_camera *cam, const splat_params *sp,
+                                      const uint32_t *bits, uint64_t n_bits, void *workspace,
+                                      size_t workspace_bytes, float *image, float *image_hl,
+                                      lod_stream_t stream) {
+  if (!bits || n_bits == 0 || !image_hl) return LOD_EINVAL;
+  return splat_lod_common(tree, node_ids, n_ids, max_points, cam, sp, bits, n_bits, workspace, workspace_bytes, image,
+                          image_hl, stream);
 }
 
 lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,
@@ -182,7 +225,7 @@ lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod
   if (!workspace_bytes || !check_camera(cam, sp)) return LOD_EINVAL;
   lodh::LodDrawLayout D = lodh::lod_draw_layout(node_capacity, max_points);
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L);
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, true);   // covers both forms
   if (s != LOD_OK) return s;
   *workspace_bytes = D.total + L.total;
   return LOD_OK;
@@ -292,6 +335,6 @@ const char *lod_status_string(lod_status s) {
   return "unknown status";
 }
 
-const char *lod_version(void) { return "liblod 0.1 gfx950"; }
+const char *lod_version(void) { return "liblod 0.2 gfx950"; }
 
 }  // extern "C"

@@ -34,8 +34,9 @@ struct SplatLayout {
   uint32_t tiles_x, tiles_y, n_tiles;
   uint32_t units, chunks;            // binning units (waves), 64 per chunk
   uint64_t max_points, max_pairs, max_slices;
+  bool aux;                          // an attribute channel is drawn
   size_t tile_count, tile_off, ucount, pchunk, slice_off, scan_tmp, counters;
-  size_t rec, partial, slice_table;   // rec: (u, v, m) float32 records of the (point, tile) pairs
+  size_t rec, partial, partial_aux, slice_table;   // rec: float32 records of the (point, tile) pairs
   size_t total;
 };
 
@@ -43,12 +44,20 @@ constexpr int SPLAT_TS = 16;           // tile edge in pixels
 constexpr uint32_t SPLAT_MAX_TILES = 8192;
 constexpr uint32_t SPLAT_SLICE = 2048; // points per accumulation slice
 constexpr uint32_t SPLAT_MAX_CHUNKS = 64;
+constexpr float BLOB_H_MIN = 1.0f;     // cubic blob: clamp of a projected world radius, pixels
+constexpr float BLOB_H_MAX = 16.0f;
+
+// The largest pixel radius a blob of these parameters can take.
+inline float blob_max_radius(const splat_params &sp) {
+  if (sp.blob == LOD_BLOB_CUBIC) return sp.h_world > 0.0f ? BLOB_H_MAX : sp.h_px;
+  return sp.radius_sigmas * sp.sigma_px;
+}
 
 lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_params &sp,
-                        SplatLayout &L);
-lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, uint64_t count,
-                        const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L, float *image,
-                        hipStream_t st);
+                        SplatLayout &L, bool aux);
+lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, const float *aux,
+                        uint64_t count, const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L,
+                        float *image, float *image_aux, hipStream_t st);
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m,
                                  uint64_t count, const lod_camera &cam, const splat_params &sp,
                                  const float *grad, float *gm, float *gx, float *gy, float *gz,
@@ -63,7 +72,8 @@ struct LodDrawLayout {
 LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points);
 lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
                             const LodDrawLayout &D, const lod_camera &cam, const splat_params &sp,
-                            const SplatLayout &L, float *image, hipStream_t st);
+                            const SplatLayout &L, const uint32_t *hl_bits, uint64_t hl_nbits, float *image,
+                            float *image_hl, hipStream_t st);
 size_t decode_workspace(uint64_t node_capacity);
 lod_status launch_decode(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
                          float *x, float *y, float *z, float *m, uint64_t *n_points, void *ws, hipStream_t st);

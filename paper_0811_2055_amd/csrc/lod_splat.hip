@@ -45,6 +45,10 @@ struct Cam {
   int narrow;       // 1 when a blob covers fewer than 8 pixels per axis (R < 3.98)
   float kexp2;      // -log2(e) / (2 sigma^2): Gaussian factor = exp2(o^2 kexp2)
   uint32_t tiles_x, tiles_y;
+  uint32_t blob;    // LOD_BLOB_GAUSSIAN or LOD_BLOB_CUBIC
+  float hpx;        // cubic: fixed pixel radius (when Fhw == 0)
+  float Fhw;        // cubic, perspective world size: fl(F h_world), else 0
+  float hmax;       // largest pixel radius a blob can take (binning window)
 };
 
 Cam make_cam(const lod_camera &c, const splat_params &sp, const lodh::SplatLayout *L) {
@@ -65,6 +69,11 @@ Cam make_cam(const lod_camera &c, const splat_params &sp, const lodh::SplatLayou
   k.narrow = (double)k.R < 3.98 ? 1 : 0;
   k.kexp2 = (float)(-1.4426950408889634 / (2.0 * s64 * s64));
   if (L) { k.tiles_x = L->tiles_x; k.tiles_y = L->tiles_y; }
+  k.blob = sp.blob;
+  k.hpx = sp.h_px;
+  k.Fhw = (sp.blob == LOD_BLOB_CUBIC && sp.h_world > 0.0f) ? c.F * sp.h_world : 0.0f;
+  k.hmax = lodh::blob_max_radius(sp);
+  if (sp.blob == LOD_BLOB_CUBIC) k.win = (int)std::ceil((double)k.hmax) + 2;
   return k;
 }
 
@@ -161,8 +170,11 @@ struct RawSrc {
                                           float &pz, float &pm) const {
       px = s.x[a.k]; py = s.y[a.k]; pz = s.z[a.k]; pm = s.m[a.k];
     }
+    // the point's attribute (second image channel)
+    __device__ __forceinline__ float attr(const RawSrc &s, const Addr &a) const { return s.aux[a.k]; }
   };
   __device__ uint64_t count() const { return n; }
+  const float *aux = nullptr;
 };
 
 // The stored points of a list of tree nodes, decoded on the fly.  offs is the
@@ -240,36 +252,71 @@ struct TreeSrc {
       py = decode_coord(a.cy, qy, a.d);
       pz = decode_coord(a.cz, qz, a.d);
     }
+    // 1 when the point's id is set in the highlight bitset, else 0
+    __device__ __forceinline__ float attr(const TreeSrc &s, const Addr &a) const {
+      const uint32_t id = s.t.pt_id[a.sidx];
+      const uint64_t wi = min((uint64_t)(id >> 5), s.hl_words - 1);
+      const uint32_t word = s.hl_bits[wi];
+      return ((uint64_t)id < s.hl_nbits && ((word >> (id & 31u)) & 1u)) ? 1.0f : 0.0f;
+    }
   };
   __device__ uint64_t count() const { return *total; }
+  const uint32_t *hl_bits = nullptr;   // highlight bitset (bit id set = highlighted)
+  uint64_t hl_nbits = 0, hl_words = 1;
 };
 
-// One point's screen position and tile rectangle (ntx = nty = 0: not drawn).
+// One point's screen position, pixel radius (cubic blob), attribute and tile
+// rectangle (ntx = nty = 0: not drawn).
 struct Blob {
-  float u, v, m;
+  float u, v, m, h, a;
   int tx0, ty0, ntx, nty;
 };
+
+// Pair records of the binned (point, tile) pairs, one type per render form:
+// Gaussian (u, v, m) is float3; the others carry the attribute and / or the
+// cubic blob's pixel radius.
+struct RecGA { float u, v, m, a; };        // Gaussian + attribute
+struct RecC { float u, v, m, h; };         // cubic
+struct RecCA { float u, v, m, h, a; };     // cubic + attribute
+__device__ __forceinline__ void rec_put(float3 *r, uint64_t i, const Blob &b) { r[i] = make_float3(b.u, b.v, b.m); }
+__device__ __forceinline__ void rec_put(RecGA *r, uint64_t i, const Blob &b) { r[i] = RecGA{b.u, b.v, b.m, b.a}; }
+__device__ __forceinline__ void rec_put(RecC *r, uint64_t i, const Blob &b) { r[i] = RecC{b.u, b.v, b.m, b.h}; }
+__device__ __forceinline__ void rec_put(RecCA *r, uint64_t i, const Blob &b) { r[i] = RecCA{b.u, b.v, b.m, b.h, b.a}; }
+template <class R> struct RecInfo { static constexpr bool aux = false; static constexpr bool cubic = false; };
+template <> struct RecInfo<RecGA> { static constexpr bool aux = true; static constexpr bool cubic = false; };
+template <> struct RecInfo<RecC> { static constexpr bool aux = false; static constexpr bool cubic = true; };
+template <> struct RecInfo<RecCA> { static constexpr bool aux = true; static constexpr bool cubic = true; };
 
 // Pixels [lo, hi] (clipped to [0, size)) that contain every pixel a blob at
 // screen coordinate t can cover: the float32 offset test |t - (i + 1/2)| <= R
 // is decided to within 2^-8 for |t| < 2^15 (the camera limits), so a margin
 // of 1/100 pixel makes the range conservative.  A tile this admits without a
 // covered pixel only adds a pair whose rows are zero in the accumulation.
-__device__ __forceinline__ bool cover_range(const Cam &c, float t, uint32_t size, int &lo, int &hi) {
-  const float lim = c.R + 4.0f;
+__device__ __forceinline__ bool cover_range(float R, float t, uint32_t size, int &lo, int &hi) {
+  const float lim = R + 4.0f;
   if (!(t > -lim && t < (float)size + lim)) return false;
-  lo = max((int)ceilf(t - 0.5f - c.R - 0.01f), 0);
-  hi = min((int)floorf(t - 0.5f + c.R + 0.01f), (int)size - 1);
+  lo = max((int)ceilf(t - 0.5f - R - 0.01f), 0);
+  hi = min((int)floorf(t - 0.5f + R + 0.01f), (int)size - 1);
   return lo <= hi;
 }
 
-__device__ __forceinline__ Blob make_blob(const Cam &c, bool valid, float px, float py, float pz, float pm) {
-  Blob b{0.0f, 0.0f, pm, 0, 0, 0, 0};
+// Pixel radius of a cubic blob at camera depth zc: the fixed radius, or the
+// projected world radius fl(fl(F h_world) / zc) clamped to [1, 16] pixels.
+__device__ __forceinline__ float cubic_radius(const Cam &c, float zc) {
+  if (c.Fhw > 0.0f) return fminf(fmaxf(__fdiv_rn(c.Fhw, zc), lodh::BLOB_H_MIN), lodh::BLOB_H_MAX);
+  return c.hpx;
+}
+
+__device__ __forceinline__ Blob make_blob(const Cam &c, bool valid, float px, float py, float pz, float pm,
+                                          float pa = 0.0f) {
+  Blob b{0.0f, 0.0f, pm, 0.0f, pa, 0, 0, 0, 0};
   if (!valid) return b;
   float xc, yc, zc;
   if (!project(c, px, py, pz, b.u, b.v, xc, yc, zc)) return b;
+  const float R = c.blob == LOD_BLOB_CUBIC ? cubic_radius(c, zc) : c.R;
+  b.h = R;
   int i0, i1, j0, j1;
-  if (!cover_range(c, b.u, c.W, i0, i1) || !cover_range(c, b.v, c.H, j0, j1)) return b;
+  if (!cover_range(R, b.u, c.W, i0, i1) || !cover_range(R, b.v, c.H, j0, j1)) return b;
   b.tx0 = i0 / TS; b.ty0 = j0 / TS;
   b.ntx = i1 / TS - b.tx0 + 1;
   b.nty = j1 / TS - b.ty0 + 1;
@@ -290,8 +337,8 @@ __device__ __forceinline__ void lds_count_add(uint16_t *lc, uint32_t t, uint32_t
 // not the method, decides the ranks.  Counting adds to LDS without reading
 // back (16-bit counters are added in their 32-bit word; a unit's counts stay
 // below 2^16, so no carry crosses the halves).
-template <bool FILL, class CT>
-__device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *lc, float3 *__restrict__ rec,
+template <bool FILL, class CT, class RecT>
+__device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *lc, RecT *__restrict__ rec,
                                           const Blob &bl) {
   const int lane = threadIdx.x & (WAVE - 1);
   uint64_t pending = __ballot(has);
@@ -307,7 +354,7 @@ __device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *l
       const uint32_t old = (uint32_t)lc[tl];
       const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
-      if (mine) rec[old + rank] = make_float3(bl.u, bl.v, bl.m);
+      if (mine) rec_put(rec, old + rank, bl);
       if (lane == leader) lc[tl] = (CT)(old + cnt);
     } else {
       if (lane == leader) lds_count_add(lc, t, cnt);   // the leader's own tile (t == tl)
@@ -327,7 +374,7 @@ __device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *l
   if (FILL) {
     const uint32_t old = rest ? (uint32_t)lc[t] : 0u;
     if (rest && below == 0) lc[t] = (CT)(old + cnt);
-    if (rest) rec[old + below] = make_float3(bl.u, bl.v, bl.m);
+    if (rest) rec_put(rec, old + below, bl);
   } else if (rest && below == 0) {
     lds_count_add(lc, t, cnt);
   }
@@ -335,9 +382,9 @@ __device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *l
 
 // Points [u0 per, min(n, (u0 + g) per)) with per = ceil(n / units): g
 // consecutive units of the partition.
-template <class Src, bool FILL, class CT>
+template <class Src, bool FILL, class CT, class RecT>
 __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, uint32_t u0, uint32_t g,
-                                         int nbits, CT *lc, float3 *__restrict__ rec) {
+                                         int nbits, CT *lc, RecT *__restrict__ rec) {
   const int lane = threadIdx.x;
   const uint64_t n = src.count();
   const uint64_t per = (n + units - 1) / units;
@@ -353,16 +400,17 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
       ad[r] = cur.resolve(src, k, k < e);
       cur.end_round(src);
     }
-    float px[BR], py[BR], pz[BR], pm[BR];
+    float px[BR], py[BR], pz[BR], pm[BR], pa[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const uint64_t k = k0 + (uint64_t)r * WAVE + lane;
       cur.fetch(src, ad[r], k < e, px[r], py[r], pz[r], pm[r]);
+      pa[r] = (FILL && RecInfo<RecT>::aux) ? cur.attr(src, ad[r]) : 0.0f;
     }
     Blob blobs[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r)
-      blobs[r] = make_blob(c, k0 + (uint64_t)r * WAVE + lane < e, px[r], py[r], pz[r], pm[r]);
+      blobs[r] = make_blob(c, k0 + (uint64_t)r * WAVE + lane < e, px[r], py[r], pz[r], pm[r], pa[r]);
     // pairs in the order (round, tile row, tile column, lane)
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
@@ -371,7 +419,7 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
         for (int dx = 0; __ballot(dy < bl.nty && dx < bl.ntx); ++dx) {
           const bool has = dy < bl.nty && dx < bl.ntx;
           const uint32_t t = has ? (uint32_t)((bl.ty0 + dy) * (int)c.tiles_x + bl.tx0 + dx) : 0u;
-          emit_tile<FILL, CT>(t, has, nbits, lc, rec, bl);
+          emit_tile<FILL, CT, RecT>(t, has, nbits, lc, rec, bl);
         }
       }
     }
@@ -389,7 +437,7 @@ __global__ __launch_bounds__(BW) void k_bin_count(Src src, Cam c, uint32_t units
   const uint32_t nt = c.tiles_x * c.tiles_y;
   for (uint32_t i = threadIdx.x; i < nt; i += BW) lc[i] = 0;
   __syncthreads();
-  bin_unit<Src, false, CT>(src, c, units, blockIdx.x, 1, nbits, lc, nullptr);
+  bin_unit<Src, false, CT, float3>(src, c, units, blockIdx.x, 1, nbits, lc, (float3 *)nullptr);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nt; i += BW) ucount[(uint64_t)blockIdx.x * nt + i] = lc[i];
 }
@@ -432,12 +480,12 @@ __global__ void k_bin_chunkscan(uint32_t *__restrict__ pchunk, uint32_t nt, uint
 // units in its chunk).  The pair count (tile_off[nt]) is checked against the
 // record capacity once: past it nothing is written and the status word says
 // so.
-template <class Src>
+template <class Src, class RecT>
 __global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units, uint32_t g, int nbits,
                                                  const uint32_t *__restrict__ ucount,
                                                  const uint32_t *__restrict__ pchunk,
                                                  const uint32_t *__restrict__ tile_off,
-                                                 float3 *__restrict__ rec, uint64_t max_pairs, uint64_t *status) {
+                                                 RecT *__restrict__ rec, uint64_t max_pairs, uint64_t *status) {
   extern __shared__ uint32_t lc[];
   const uint32_t nt = c.tiles_x * c.tiles_y;
   if (tile_off[nt] > max_pairs) {
@@ -449,7 +497,7 @@ __global__ __launch_bounds__(BW) void k_bin_fill(Src src, Cam c, uint32_t units,
   for (uint32_t i = threadIdx.x; i < nt; i += BW)
     lc[i] = tile_off[i] + pchunk[(uint64_t)ch * nt + i] + ucount[(uint64_t)u0 * nt + i];
   __syncthreads();
-  bin_unit<Src, true, uint32_t>(src, c, units, u0, g, nbits, lc, rec);
+  bin_unit<Src, true, uint32_t, RecT>(src, c, units, u0, g, nbits, lc, rec);
 }
 
 // slices per tile
@@ -491,16 +539,31 @@ __device__ __forceinline__ void neumaier(float &s, float &c, float x) {
 // wave complete in order, so the waves of a block run the chunks without
 // block barriers; at the end of the slice the four wave sums of each pixel
 // are folded in wave order.  No atomics: the image is bit-reproducible.
+// Pair record loads (the attribute of records that carry none is 0).
+__device__ __forceinline__ void load_rec(const float3 *r, uint64_t q, float &u, float &v, float &m, float &a) {
+  const float3 t = r[q];
+  u = t.x; v = t.y; m = t.z; a = 0.0f;
+}
+__device__ __forceinline__ void load_rec(const RecGA *r, uint64_t q, float &u, float &v, float &m, float &a) {
+  const float4 t = reinterpret_cast<const float4 *>(r)[q];
+  u = t.x; v = t.y; m = t.z; a = t.w;
+}
+
 constexpr int GXS = TS + 1;          // padded row: conflict-free phase-A writes
 typedef float float4v __attribute__((ext_vector_type(4)));
+template <class RecT>
 __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ table,
                                                    const uint32_t *__restrict__ slice_off, uint32_t nt,
-                                                   const float3 *__restrict__ rec, Cam c,
-                                                   float *__restrict__ partial, uint64_t max_slices,
-                                                   uint64_t max_pairs) {
+                                                   const RecT *__restrict__ rec, Cam c,
+                                                   float *__restrict__ partial, float *__restrict__ partial_aux,
+                                                   uint64_t max_slices, uint64_t max_pairs) {
+  constexpr bool AUX = RecInfo<RecT>::aux;
+  constexpr int PA = AUX ? PT : 1;
   __shared__ float gx[PT][GXS];
   __shared__ float gy[PT][GXS];
+  __shared__ float gya[PA][GXS];        // attribute channel: rows weighted by m a
   __shared__ float part[4][TS * TS];   // the waves' slice sums
+  __shared__ float parta[AUX ? 4 : 1][AUX ? TS * TS : 1];
   const uint32_t total_slices = (uint32_t)min((uint64_t)slice_off[nt], max_slices);
   const int grp = threadIdx.x / 64;                 // point group of phase B
   const int col = threadIdx.x % TS;                 // pixel column of phase B
@@ -512,17 +575,19 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
   int pwx = 0, pwy = 0;
   if (c.narrow) {
 #pragma unroll
-    for (int e = 0; e < TS; ++e) { gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f; }
+    for (int e = 0; e < TS; ++e) {
+      gx[threadIdx.x][e] = 0.0f; gy[threadIdx.x][e] = 0.0f;
+      if (AUX) gya[threadIdx.x][e] = 0.0f;
+    }
   }
   // pair records are loaded one chunk ahead, across slice boundaries too
   // (clamped indices: every load is issued unconditionally)
   const uint64_t last = max_pairs - 1;
   uint2 sd = table[blockIdx.x];
-  float nu, nv, nm;
+  float nu, nv, nm, na = 0.0f;
   {
     const uint64_t q = min((uint64_t)sd.x + threadIdx.x, last);
-    const float3 r = rec[q];
-    nu = r.x; nv = r.y; nm = r.z;
+    load_rec(rec, q, nu, nv, nm, na);
   }
   for (uint32_t sl = blockIdx.x; sl < total_slices; sl += gridDim.x) {
     const uint32_t t = sd.y & 0xFFFFu;
@@ -532,16 +597,17 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
     const uint2 nsd = table[min(nsl, total_slices - 1)];
     const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
     float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f}, c4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float s4a[4] = {0.0f, 0.0f, 0.0f, 0.0f}, c4a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
       const bool have = c0 + threadIdx.x < pe;
       // lanes past the slice hold whatever the clamped prefetch read: zero them
       // so that the 0/1 masking below multiplies finite values only
       const float u = have ? nu : 0.0f, v = have ? nv : 0.0f, m = have ? nm : 0.0f;
+      const float pa = have ? na : 0.0f;
       {
         const uint64_t q = (c0 + PT < pe) ? c0 + PT + threadIdx.x : (uint64_t)nsd.x + threadIdx.x;
         const uint64_t qc = min(q, last);
-        const float3 r = rec[qc];
-        nu = r.x; nv = r.y; nm = r.z;
+        load_rec(rec, qc, nu, nv, nm, na);
       }
       // phase A: rows are zero outside the truncation square.  A pixel is
       // covered when its float32 offset fl(t - (i + 1/2)) lies in [-R, R],
@@ -552,6 +618,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
       // mass 0.
       const float R = c.R;
       const float w = m * c.norm;
+      const float wa = (m * pa) * c.norm;
       if (c.narrow) {
         // fewer than 8 covered pixels per axis: clear the previous window,
         // then write an 8-wide window from a lower bound of the run's first
@@ -560,7 +627,10 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
         const int lx = (int)ceilf(u - 0.5f - R - 0.01f), ly = (int)ceilf(v - 0.5f - R - 0.01f);
         const int wx = min(max(lx - tx0, 0), TS - 8), wy = min(max(ly - ty0, 0), TS - 8);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) { gx[threadIdx.x][pwx + e] = 0.0f; gy[threadIdx.x][pwy + e] = 0.0f; }
+        for (int e = 0; e < 8; ++e) {
+          gx[threadIdx.x][pwx + e] = 0.0f; gy[threadIdx.x][pwy + e] = 0.0f;
+          if (AUX) gya[threadIdx.x][pwy + e] = 0.0f;
+        }
         pwx = wx; pwy = wy;
         // pixel centres i + 1/2 are small half-integers: adding q to the
         // first one is exact.  Away from the image's low edges (tile origin
@@ -593,6 +663,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
           gx[threadIdx.x][wx + q] = fabsf(ox) <= R ? ex : 0.0f;
           gy[threadIdx.x][wy + q] = fabsf(oy) <= R ? w * ey : 0.0f;
+          if (AUX) gya[threadIdx.x][wy + q] = fabsf(oy) <= R ? wa * ey : 0.0f;
         }
       } else {
         const float cx0 = (float)tx0 + 0.5f, cy0 = (float)ty0 + 0.5f;
@@ -604,6 +675,7 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
           const float ey = __builtin_amdgcn_exp2f((oy * oy) * c.kexp2);
           gx[threadIdx.x][e] = fabsf(ox) <= R ? ex : 0.0f;
           gy[threadIdx.x][e] = fabsf(oy) <= R ? w * ey : 0.0f;
+          if (AUX) gya[threadIdx.x][e] = fabsf(oy) <= R ? wa * ey : 0.0f;
         }
       }
       // the rows of this wave's points were written by this wave
@@ -628,6 +700,18 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
       for (int st = 0; st < 16; ++st) acc4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st], acc4, 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) neumaier(s4[i], c4[i], acc4[i]);
+      if (AUX) {
+        float4v acc4a = {0.0f, 0.0f, 0.0f, 0.0f};
+        float aa[16];
+#pragma unroll
+        for (int st = 0; st < 16; ++st) aa[st] = gya[kb + st * 4 + ln / 16][ln % 16];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+          acc4a = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[st], bv[st], acc4a, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) neumaier(s4a[i], c4a[i], acc4a[i]);
+      }
       // the next chunk rewrites this wave's rows after its reads above
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -635,11 +719,21 @@ __global__ __launch_bounds__(PT) void k_accumulate(const uint2 *__restrict__ tab
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) part[grp][(row0 + i) * TS + col] = s4[i] + c4[i];
+    if (AUX) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) parta[grp][(row0 + i) * TS + col] = s4a[i] + c4a[i];
+    }
     __syncthreads();
     float s = 0.0f, cc = 0.0f;
 #pragma unroll
     for (int g = 0; g < 4; ++g) neumaier(s, cc, part[g][threadIdx.x]);
     partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cc;
+    if (AUX) {
+      float sa = 0.0f, ca = 0.0f;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) neumaier(sa, ca, parta[g][threadIdx.x]);
+      partial_aux[(uint64_t)sl * (TS * TS) + threadIdx.x] = sa + ca;
+    }
     sd = nsd;
     __syncthreads();
   }
@@ -656,6 +750,162 @@ __global__ __launch_bounds__(PT) void k_finalize(const uint32_t *__restrict__ sl
     const int i = (int)(t % c.tiles_x) * TS + (threadIdx.x % TS);
     const int j = (int)(t / c.tiles_x) * TS + (threadIdx.x / TS);
     if (i < (int)c.W && j < (int)c.H) image[(uint64_t)j * c.W + i] = s + cc;
+  }
+}
+
+// --- radial cubic blob -------------------------------------------------------------
+//
+// The compact cubic spline of smoothed-particle hydrodynamics, normalised in
+// two dimensions: W(r; h) = 40 / (7 pi h^2) w(r / h), w(q) = 1 - 6 q^2 + 6 q^3
+// (q <= 1/2), 2 (1 - q)^3 (1/2 < q < 1), 0 beyond.  A pixel takes a point iff
+// fl64(ox^2) + fl64(oy^2) < h^2 in float64 (both squares of the float32
+// offsets are exact there).  The value is evaluated in float64: near the rim
+// w ~ 2 (1 - q)^3 needs 1 - q to far better than float32's relative 6e-8 for
+// the pixel's 1e-5 bound, so q = sqrt(r^2) / h is formed in float64 and the
+// product m W is rounded once to float32 before the compensated sum.
+constexpr double kCubicNorm = 40.0 / (7.0 * 3.14159265358979323846);
+
+__device__ __forceinline__ double cubic_w(double q) {
+  return q <= 0.5 ? (1.0 - 6.0 * q * q) + 6.0 * q * q * q : 2.0 * ((1.0 - q) * (1.0 - q)) * (1.0 - q);
+}
+// w'(q) / q, finite at q = 0
+__device__ __forceinline__ double cubic_dw_over_q(double q) {
+  return q <= 0.5 ? -12.0 + 18.0 * q : -6.0 * ((1.0 - q) * (1.0 - q)) / q;
+}
+
+__device__ __forceinline__ void load_rec(const RecC *r, uint64_t q, float &u, float &v, float &m, float &h,
+                                         float &a) {
+  const float4 t = reinterpret_cast<const float4 *>(r)[q];
+  u = t.x; v = t.y; m = t.z; h = t.w; a = 0.0f;
+}
+__device__ __forceinline__ void load_rec(const RecCA *r, uint64_t q, float &u, float &v, float &m, float &h,
+                                         float &a) {
+  const RecCA t = r[q];
+  u = t.u; v = t.v; m = t.m; h = t.h; a = t.a;
+}
+
+// One block per slice (as the Gaussian accumulation); the spline is not
+// separable, so thread p owns pixel p of the 16x16 tile and gathers.  The
+// slice's records are staged in LDS 256 at a time; each wave runs through
+// them in order and skips a record whose blob misses its four pixel rows
+// (a wave-uniform test), so every pixel adds its contributions in record
+// order: the image is bit-reproducible.
+template <class RecT>
+__global__ __launch_bounds__(PT) void k_accumulate_cubic(const uint2 *__restrict__ table,
+                                                         const uint32_t *__restrict__ slice_off, uint32_t nt,
+                                                         const RecT *__restrict__ rec, Cam c,
+                                                         float *__restrict__ partial,
+                                                         float *__restrict__ partial_aux, uint64_t max_slices,
+                                                         uint64_t max_pairs) {
+  constexpr bool AUX = RecInfo<RecT>::aux;
+  __shared__ float su[PT], sv[PT], sm[PT], sh[PT];
+  __shared__ float sa[AUX ? PT : 1];
+  const uint32_t total_slices = (uint32_t)min((uint64_t)slice_off[nt], max_slices);
+  if (blockIdx.x >= total_slices) return;
+  const int px = threadIdx.x % TS, py = threadIdx.x / TS;
+  const int wrow0 = (threadIdx.x / WAVE) * 4;      // a wave's first pixel row within the tile
+  for (uint32_t sl = blockIdx.x; sl < total_slices; sl += gridDim.x) {
+    const uint2 sd = table[sl];
+    const uint32_t t = sd.y & 0xFFFFu;
+    const uint64_t pb = sd.x;
+    const uint64_t pe = min(pb + (sd.y >> 16), max_pairs);
+    const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
+    const float cx = (float)(tx0 + px) + 0.5f, cy = (float)(ty0 + py) + 0.5f;   // exact pixel centres
+    const float rlo = (float)(ty0 + wrow0) + 0.5f, rhi = rlo + 3.0f;
+    float s = 0.0f, cs = 0.0f, s_a = 0.0f, c_a = 0.0f;
+    for (uint64_t c0 = pb; c0 < pe; c0 += PT) {
+      __syncthreads();                               // the previous chunk has been read
+      if (c0 + threadIdx.x < pe) {
+        float u, v, m, h, a;
+        load_rec(rec, c0 + threadIdx.x, u, v, m, h, a);
+        su[threadIdx.x] = u; sv[threadIdx.x] = v; sm[threadIdx.x] = m; sh[threadIdx.x] = h;
+        if (AUX) sa[threadIdx.x] = a;
+      }
+      __syncthreads();
+      const int nrec = (int)min((uint64_t)PT, pe - c0);
+      for (int k = 0; k < nrec; ++k) {
+        const float v = sv[k], h = sh[k];
+        // the blob covers |oy| < h: skip when it misses all four row centres
+        if (v + h + 0.01f < rlo || v - h - 0.01f > rhi) continue;
+        const float u = su[k];
+        const float ox = u - cx, oy = v - cy;
+        const float r2f = ox * ox + oy * oy;
+        if (!(r2f < (h * h) * 1.001f)) continue;   // surely outside (float32 pre-test with margin)
+        const double h64 = (double)h;
+        const double hh = h64 * h64;
+        const double r2 = (double)ox * (double)ox + (double)oy * (double)oy;
+        if (!(r2 < hh)) continue;
+        const double q = sqrt(r2) / h64;
+        const double val = (double)sm[k] * (kCubicNorm / hh) * cubic_w(q);
+        neumaier(s, cs, (float)val);
+        if (AUX) neumaier(s_a, c_a, (float)(val * (double)sa[k]));
+      }
+    }
+    partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cs;
+    if (AUX) partial_aux[(uint64_t)sl * (TS * TS) + threadIdx.x] = s_a + c_a;
+  }
+}
+
+// Adjoint of the cubic blob, one thread per point over its own footprint
+// (float64 sums): dI/dm = W, dI/dox = m 40/(7 pi h^4) (w'(q)/q) ox, and with a
+// world-space size (radius not clamped) dI/dh = m 40/(7 pi h^3)
+// (-2 w - q w'(q)) with dh/dp = -(h / zc) f.
+__global__ __launch_bounds__(PT) void k_backward_cubic(const float *__restrict__ x, const float *__restrict__ y,
+                                                       const float *__restrict__ z, const float *__restrict__ m,
+                                                       uint64_t count, Cam c, const float *__restrict__ g,
+                                                       float *__restrict__ gm, float *__restrict__ gx,
+                                                       float *__restrict__ gy, float *__restrict__ gz) {
+  for (uint64_t k = (uint64_t)blockIdx.x * PT + threadIdx.x; k < count; k += (uint64_t)gridDim.x * PT) {
+    float u, v, xc, yc, zc;
+    double am = 0.0, au = 0.0, av = 0.0, ah = 0.0;
+    const bool vis = project(c, x[k], y[k], z[k], u, v, xc, yc, zc);
+    const float h = vis ? cubic_radius(c, zc) : c.hpx;
+    bool dh_live = false;
+    if (vis && c.Fhw > 0.0f) {
+      const float hp = __fdiv_rn(c.Fhw, zc);
+      dh_live = hp >= lodh::BLOB_H_MIN && hp <= lodh::BLOB_H_MAX;
+    }
+    int i0, i1, j0, j1;
+    const double mk = (double)m[k];
+    if (vis && cover_range(h, u, c.W, i0, i1) && cover_range(h, v, c.H, j0, j1)) {
+      const double h64 = (double)h, hh = h64 * h64;
+      for (int j = j0; j <= j1; ++j) {
+        const float oy = v - ((float)j + 0.5f);
+        for (int i = i0; i <= i1; ++i) {
+          const float ox = u - ((float)i + 0.5f);
+          const double r2 = (double)ox * (double)ox + (double)oy * (double)oy;
+          if (!(r2 < hh)) continue;
+          const double q = sqrt(r2) / h64;
+          const double w = cubic_w(q), dwq = cubic_dw_over_q(q);
+          const double gp = (double)g[(uint64_t)j * c.W + i];
+          am += (kCubicNorm / hh) * w * gp;
+          const double tq = mk * kCubicNorm / (hh * hh) * dwq * gp;
+          au += tq * (double)ox;
+          av += tq * (double)oy;
+          if (dh_live) ah += mk * kCubicNorm / (hh * h64) * (-2.0 * w - (q * q) * dwq) * gp;
+        }
+      }
+    }
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    if (vis) {
+      if (c.proj == 0) {
+        dx = au * (double)c.W;
+        dy = av * (double)c.H;
+      } else {
+        const double zz = (double)zc;
+        const double a = (double)c.F / zz;
+        const double bu = (double)c.F * (double)xc / (zz * zz);
+        const double bv = (double)c.F * (double)yc / (zz * zz);
+        const double dh = dh_live ? -(double)h / zz : 0.0;
+        dx = au * (a * c.rx - bu * c.fx) + av * (a * c.ux - bv * c.fx) + ah * dh * c.fx;
+        dy = au * (a * c.ry - bu * c.fy) + av * (a * c.uy - bv * c.fy) + ah * dh * c.fy;
+        dz = au * (a * c.rz - bu * c.fz) + av * (a * c.uz - bv * c.fz) + ah * dh * c.fz;
+      }
+    }
+    gm[k] = (float)am;
+    if (gx) gx[k] = (float)dx;
+    if (gy) gy[k] = (float)dy;
+    if (gz) gz[k] = (float)dz;
   }
 }
 
@@ -840,20 +1090,28 @@ namespace lodh {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_params &sp, SplatLayout &L) {
+// Bytes of one binned (point, tile) record for a render form.
+static size_t rec_bytes(const splat_params &sp, bool aux) {
+  if (sp.blob == LOD_BLOB_CUBIC) return aux ? sizeof(RecCA) : sizeof(RecC);
+  return aux ? sizeof(RecGA) : sizeof(float3);
+}
+
+lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_params &sp, SplatLayout &L,
+                        bool aux) {
   L = SplatLayout{};
   L.tiles_x = (cam.W + TS - 1) / TS;
   L.tiles_y = (cam.H + TS - 1) / TS;
   const uint64_t nt = (uint64_t)L.tiles_x * L.tiles_y;
   if (nt == 0 || nt > SPLAT_MAX_TILES) return LOD_EUNSUPPORTED;
   L.n_tiles = (uint32_t)nt;
-  const double R = (double)(sp.radius_sigmas * sp.sigma_px);
+  const double R = (double)blob_max_radius(sp);
   const uint64_t width = 2 * (uint64_t)std::ceil(R) + 3;         // pixels a blob's tile range can span
   const uint64_t tpa = std::min<uint64_t>((width + TS - 1) / TS + 1, std::max(L.tiles_x, L.tiles_y));
   L.max_points = max_points;
   L.max_pairs = std::max<uint64_t>(1, max_points * tpa * tpa);
   if (L.max_pairs >= (1ull << 32)) return LOD_EUNSUPPORTED;
   L.max_slices = nt + L.max_pairs / SPLAT_SLICE + 1;
+  L.aux = aux;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   // units: 64 per chunk, one chunk per 2^21 points (units of at most 32768
@@ -867,16 +1125,20 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   L.slice_off = take(4 * (nt + 1));
   L.scan_tmp = take(4 * scan_tmp_elems<uint32_t>(nt + 1));
   L.counters = take(64);
-  L.rec = take(12 * L.max_pairs);
+  L.rec = take(rec_bytes(sp, aux) * L.max_pairs);
   L.partial = take(4 * (size_t)TS * TS * L.max_slices);
+  L.partial_aux = aux ? take(4 * (size_t)TS * TS * L.max_slices) : L.partial;
   L.slice_table = take(8 * (size_t)L.max_slices);
   L.total = off;
   return LOD_OK;
 }
 
-template <class Src>
-static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &cam, const splat_params &sp, void *ws,
-                                   const SplatLayout &L, float *image, uint64_t *status_word, hipStream_t st) {
+// Binning, accumulation and the final slice sums for any point source and
+// record form.  image_aux receives the attribute channel (RecT carrying one).
+template <class Src, class RecT>
+static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &cam, const splat_params &sp,
+                                   void *ws, const SplatLayout &L, float *image, float *image_aux,
+                                   uint64_t *status_word, hipStream_t st) {
   char *W = (char *)ws;
   Cam c = make_cam(cam, sp, &L);
   const uint32_t nt = L.n_tiles;
@@ -888,8 +1150,9 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   uint32_t *stmp = (uint32_t *)(W + L.scan_tmp);
   uint64_t *ctr = (uint64_t *)(W + L.counters);
   uint64_t *status = status_word ? status_word : ctr;
-  float3 *rec = (float3 *)(W + L.rec);
+  RecT *rec = (RecT *)(W + L.rec);
   float *partial = (float *)(W + L.partial);
+  float *partial_aux = (float *)(W + L.partial_aux);
   int nbits = 0;
   while ((1u << nbits) < nt) ++nbits;
   fill_u32(tcount, nt + 1, 0, st);
@@ -911,8 +1174,8 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
     // fill blocks of two units when there are many (32-bit cursors take twice
     // the LDS of the 16-bit counts: fewer resident waves)
     const uint32_t g = L.units >= 4096 ? 2u : 1u;
-    LOD_LAUNCH(k_bin_fill<Src>, dim3(L.units / g), dim3(BW), lds, st, src, c, L.units, g, nbits, ucount, pchunk,
-               toff, rec, L.max_pairs, status);
+    LOD_LAUNCH((k_bin_fill<Src, RecT>), dim3(L.units / g), dim3(BW), lds, st, src, c, L.units, g, nbits, ucount,
+               pchunk, toff, rec, L.max_pairs, status);
   }
   LOD_LAUNCH(k_slice_count, dim3((nt + 255) / 256), dim3(256), 0, st, tcount, nt, soff);
   fill_u32(soff + nt, 1, 0, st);
@@ -921,18 +1184,41 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   LOD_LAUNCH(k_slice_table, dim3((nt + 255) / 256), dim3(256), 0, st, toff, tcount, soff, nt, stab, L.max_slices);
   const unsigned agrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, L.max_slices));
   if (any) {
-    LOD_LAUNCH(k_accumulate, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial,
-               L.max_slices, L.max_pairs);
+    if constexpr (RecInfo<RecT>::cubic)
+      LOD_LAUNCH(k_accumulate_cubic<RecT>, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial,
+                 partial_aux, L.max_slices, L.max_pairs);
+    else
+      LOD_LAUNCH(k_accumulate<RecT>, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial, partial_aux,
+                 L.max_slices, L.max_pairs);
   }
   LOD_LAUNCH(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial, c, image,
              L.max_slices);
+  if constexpr (RecInfo<RecT>::aux)
+    LOD_LAUNCH(k_finalize, dim3(std::min<uint32_t>(nt, 4096)), dim3(PT), 0, st, soff, nt, partial_aux, c,
+               image_aux, L.max_slices);
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
 
-lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, uint64_t count,
-                        const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L, float *image,
-                        hipStream_t st) {
-  return launch_splat_src(RawSrc{x, y, z, m, count}, count > 0, cam, sp, ws, L, image, nullptr, st);
+// Dispatch on the blob kind and on whether an attribute channel is drawn.
+template <class Src>
+static lod_status splat_any(const Src &src, bool any, const lod_camera &cam, const splat_params &sp, void *ws,
+                            const SplatLayout &L, float *image, float *image_aux, uint64_t *status_word,
+                            hipStream_t st) {
+  const bool cubic = sp.blob == LOD_BLOB_CUBIC;
+  if (L.aux) {
+    if (cubic) return launch_splat_src<Src, RecCA>(src, any, cam, sp, ws, L, image, image_aux, status_word, st);
+    return launch_splat_src<Src, RecGA>(src, any, cam, sp, ws, L, image, image_aux, status_word, st);
+  }
+  if (cubic) return launch_splat_src<Src, RecC>(src, any, cam, sp, ws, L, image, nullptr, status_word, st);
+  return launch_splat_src<Src, float3>(src, any, cam, sp, ws, L, image, nullptr, status_word, st);
+}
+
+lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, const float *aux,
+                        uint64_t count, const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L,
+                        float *image, float *image_aux, hipStream_t st) {
+  RawSrc src{x, y, z, m, count};
+  src.aux = aux;
+  return splat_any(src, count > 0, cam, sp, ws, L, image, image_aux, nullptr, st);
 }
 
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m, uint64_t count,
@@ -941,7 +1227,10 @@ lod_status launch_splat_backward(const float *x, const float *y, const float *z,
   if (!count) return LOD_OK;
   Cam c = make_cam(cam, sp, nullptr);
   const unsigned grid = (unsigned)std::min<uint64_t>(65535, (count + PT - 1) / PT);
-  LOD_LAUNCH(k_backward, dim3(grid), dim3(PT), 0, st, x, y, z, m, count, c, grad, gm, gx, gy, gz);
+  if (sp.blob == LOD_BLOB_CUBIC)
+    LOD_LAUNCH(k_backward_cubic, dim3(grid), dim3(PT), 0, st, x, y, z, m, count, c, grad, gm, gx, gy, gz);
+  else
+    LOD_LAUNCH(k_backward, dim3(grid), dim3(PT), 0, st, x, y, z, m, count, c, grad, gm, gx, gy, gz);
   return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
 
@@ -960,7 +1249,8 @@ LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points) {
 
 lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
                             const LodDrawLayout &D, const lod_camera &cam, const splat_params &sp,
-                            const SplatLayout &L, float *image, hipStream_t st) {
+                            const SplatLayout &L, const uint32_t *hl_bits, uint64_t hl_nbits, float *image,
+                            float *image_hl, hipStream_t st) {
   char *W = (char *)ws;
   uint64_t *offs = (uint64_t *)(W + D.offs);
   uint64_t *cnt = (uint64_t *)(W + D.count);
@@ -968,8 +1258,11 @@ lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, cons
   LOD_LAUNCH(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, D.max_ids, offs);
   device_scan<uint64_t>(offs, D.max_ids + 1, (uint64_t *)(W + D.scan_tmp), st);
   LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, D.max_ids, D.max_points, cnt);
-  const TreeSrc src{tree, node_ids, offs, n_ids, D.max_ids, cnt};
-  return launch_splat_src(src, true, cam, sp, W + D.total, L, image, tree.counts + 2, st);
+  TreeSrc src{tree, node_ids, offs, n_ids, D.max_ids, cnt};
+  src.hl_bits = hl_bits;
+  src.hl_nbits = hl_nbits;
+  src.hl_words = std::max<uint64_t>(1, (hl_nbits + 31) / 32);
+  return splat_any(src, true, cam, sp, W + D.total, L, image, image_hl, tree.counts + 2, st);
 }
 
 size_t decode_workspace(uint64_t node_capacity) {

@@ -53,12 +53,12 @@ lod_status splat_render_noalloc(const float *x, const float *y, const float *z, 
   if (!camera_ok(cam, sp) || !image) return LOD_EINVAL;
   if (count && (!x || !y || !z || !m)) return LOD_EINVAL;
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(count, *cam, *sp, L);
+  lod_status s = lodh::splat_layout(count, *cam, *sp, L, false);
   if (s != LOD_OK) return s;
   if (L.total > (size_t)LOD_NOALLOC_SCRATCH_BYTES) return LOD_ECAPACITY;
   void *ws = nullptr;
   if ((s = scratch_for_current_device(&ws)) != LOD_OK) return s;
-  return lodh::launch_splat(x, y, z, m, count, *cam, *sp, ws, L, image, (hipStream_t)stream);
+  return lodh::launch_splat(x, y, z, m, nullptr, count, *cam, *sp, ws, L, image, nullptr, (hipStream_t)stream);
 }
 
 }  // extern "C"

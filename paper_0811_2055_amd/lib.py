@@ -23,6 +23,7 @@ EXPORTS = [
     "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
     "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
     "lod_decode_plan", "lod_decode", "lod_autotune", "splat_render_noalloc",
+    "splat_render_aux", "splat_render_lod_highlight",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -62,7 +63,8 @@ class KernelTime(C.Structure):
 
 
 class SplatParamsC(C.Structure):
-    _fields_ = [("sigma_px", C.c_float), ("radius_sigmas", C.c_float)]
+    _fields_ = [("sigma_px", C.c_float), ("radius_sigmas", C.c_float), ("blob", C.c_uint32),
+                ("h_px", C.c_float), ("h_world", C.c_float)]
 
 
 _lib = None
@@ -95,6 +97,10 @@ def load():
                                           C.POINTER(SplatParamsC), P, P, P, P, P, P]
     lib.splat_render_noalloc.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC),
                                          P, P]
+    lib.splat_render_aux.argtypes = [P, P, P, P, P, C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC),
+                                     P, C.c_size_t, P, P, P]
+    lib.splat_render_lod_highlight.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, C.POINTER(CameraC),
+                                               C.POINTER(SplatParamsC), P, C.c_uint64, P, C.c_size_t, P, P, P]
     lib.lod_decode_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
     lib.lod_decode.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
     lib.lod_autotune.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_size_t, C.POINTER(TreeC),
@@ -190,6 +196,29 @@ class Camera:
         up = [f[1] * r[2] - f[2] * r[1], f[2] * r[0] - f[0] * r[2], f[0] * r[1] - f[1] * r[0]]
         F = (W / 2.0) / math.tan(math.radians(fov_deg) / 2.0)
         return Camera(1, W, H, tuple(pos), tuple(r), tuple(up), tuple(f), F, near)
+
+
+@dataclass
+class Blob:
+    """splat_params: kind 0 = truncated Gaussian (sigma, radius_sigmas), kind 1 =
+    radial cubic spline of radius h_px pixels, or of world radius h_world
+    (perspective cameras; projected radius clamped to [1, 16] pixels)."""
+    kind: int = 0
+    sigma: float = 1.0
+    radius_sigmas: float = 3.0
+    h_px: float = 0.0
+    h_world: float = 0.0
+
+    def c(self) -> SplatParamsC:
+        return SplatParamsC(self.sigma, self.radius_sigmas, self.kind, self.h_px, self.h_world)
+
+    @staticmethod
+    def cubic(h_px: float = 0.0, h_world: float = 0.0) -> "Blob":
+        return Blob(1, 1.0, 3.0, h_px, h_world)
+
+
+def _sp(sigma, radius_sigmas, blob):
+    return blob.c() if blob is not None else SplatParamsC(sigma, radius_sigmas, 0, 0.0, 0.0)
 
 
 @dataclass
@@ -399,71 +428,121 @@ def select_nodes(tree: Tree, cam: Camera, tau_px: float, n: int, cap: int | None
     return ids, nsel
 
 
-def splat_workspace_bytes(max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0) -> int:
+def splat_workspace_bytes(max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0, blob=None) -> int:
     lib = load()
     ws = C.c_size_t()
-    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
     _check(lib.splat_plan(int(max_points), C.byref(camc), C.byref(sp), C.byref(ws)), "splat_plan")
     return int(ws.value)
 
 
-def splat(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, workspace=None, out=None):
+def splat(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, workspace=None, out=None, blob=None):
     import torch
     lib = load()
     dev = x.device
     N = int(x.numel())
-    ws = splat_workspace_bytes(N, cam, sigma, radius_sigmas)
+    ws = splat_workspace_bytes(N, cam, sigma, radius_sigmas, blob)
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
     img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
-    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
     _check(lib.splat_render(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp),
                             _ptr(workspace), workspace.numel(), _ptr(img), _stream()), "splat_render")
     return img
 
 
+def splat_aux(x, y, z, m, aux, cam: Camera, sigma=1.0, radius_sigmas=3.0, workspace=None, blob=None):
+    """(image, attribute image) with the attribute image sum_k m_k a_k W_k."""
+    import torch
+    lib = load()
+    dev = x.device
+    N = int(x.numel())
+    ws = splat_workspace_bytes(N, cam, sigma, radius_sigmas, blob)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    img = torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    aimg = torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
+    _check(lib.splat_render_aux(_ptr(x), _ptr(y), _ptr(z), _ptr(m), _ptr(aux), N, C.byref(camc), C.byref(sp),
+                                _ptr(workspace), workspace.numel(), _ptr(img), _ptr(aimg), _stream()),
+           "splat_render_aux")
+    return img, aimg
+
+
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
-def splat_noalloc(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, out=None):
+def splat_noalloc(x, y, z, m, cam: Camera, sigma=1.0, radius_sigmas=3.0, out=None, blob=None):
     """splat_render with the library's fixed device scratch array as workspace
     (no device allocation inside the call; `out` may be preallocated)."""
     import torch
     lib = load()
     N = int(x.numel())
     img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=x.device)
-    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
     _check(lib.splat_render_noalloc(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp), _ptr(img),
                                     _stream()), "splat_render_noalloc")
     return img
 
 
-def splat_lod_workspace_bytes(node_capacity: int, max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0):
+def splat_lod_workspace_bytes(node_capacity: int, max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0,
+                              blob=None):
     lib = load()
     ws = C.c_size_t()
-    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
     _check(lib.splat_lod_plan(int(node_capacity), int(max_points), C.byref(camc), C.byref(sp), C.byref(ws)),
            "splat_lod_plan")
     return int(ws.value)
 
 
 def splat_lod(tree: Tree, node_ids, n_ids, max_points: int, cam: Camera, sigma=1.0, radius_sigmas=3.0,
-              workspace=None, out=None):
+              workspace=None, out=None, blob=None):
     import torch
     lib = load()
     dev = tree.counts.device
-    ws = splat_lod_workspace_bytes(tree.node_capacity, max_points, cam, sigma, radius_sigmas)
+    ws = splat_lod_workspace_bytes(tree.node_capacity, max_points, cam, sigma, radius_sigmas, blob)
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
     img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
-    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
     _check(lib.splat_render_lod(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points), C.byref(camc),
                                 C.byref(sp), _ptr(workspace), workspace.numel(), _ptr(img), _stream()),
            "splat_render_lod")
     return img
 
 
-def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas=3.0):
+def highlight_bits(ids, n_bits: int, device="cuda"):
+    """Device uint32 bitset over ids [0, n_bits) with the given ids set (host-side packing)."""
+    import numpy as np
+    import torch
+    words = np.zeros(max(1, (int(n_bits) + 31) // 32), dtype=np.uint32)
+    ids = np.asarray(ids, dtype=np.int64)
+    ids = ids[(ids >= 0) & (ids < n_bits)]
+    np.bitwise_or.at(words, ids >> 5, (np.uint32(1) << (ids & 31).astype(np.uint32)))
+    return torch.from_numpy(words.view(np.int32)).to(device).view(torch.uint32)
+
+
+def splat_lod_highlight(tree: Tree, node_ids, n_ids, max_points: int, cam: Camera, bits, n_bits: int, sigma=1.0,
+                        radius_sigmas=3.0, workspace=None, out=None, out_hl=None, blob=None):
+    """(image, highlight image): the LOD render and the same render of the stored
+    points whose id is set in the device bitset `bits`."""
+    import torch
+    lib = load()
+    dev = tree.counts.device
+    ws = splat_lod_workspace_bytes(tree.node_capacity, max_points, cam, sigma, radius_sigmas, blob)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    hl = out_hl if out_hl is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
+    _check(lib.splat_render_lod_highlight(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points),
+                                          C.byref(camc), C.byref(sp), _ptr(bits), int(n_bits), _ptr(workspace),
+                                          workspace.numel(), _ptr(img), _ptr(hl), _stream()),
+           "splat_render_lod_highlight")
+    return img, hl
+
+
+def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas=3.0, blob=None):
     import torch
     lib = load()
     N = int(x.numel())
@@ -472,7 +551,7 @@ def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas
     gy = torch.empty(N, dtype=torch.float32, device=x.device)
     gz = torch.empty(N, dtype=torch.float32, device=x.device)
     g = grad_image.contiguous()
-    camc, sp = cam.c(), SplatParamsC(sigma, radius_sigmas)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
     _check(lib.splat_render_backward(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp), _ptr(g),
                                      _ptr(gm), _ptr(gx), _ptr(gy), _ptr(gz), _stream()), "splat_render_backward")
     return gm, gx, gy, gz
