@@ -404,12 +404,19 @@ def main():
     ids1, nsel1 = lib.select_nodes(tree, cam, 1.0, cfg["n"], workspace=sel_ws)
     hl_ids = np.random.default_rng(7).choice(N, min(1_000_000, N), replace=False)
     bits = lib.highlight_bits(hl_ids, N, dev)
+    holder = {}
+    flags_ms = timed(lambda: holder.update(f=lib.highlight_flags(tree, bits, N)), reps=3)
+    flags = holder["f"]
     hl_img = torch.empty_like(lod_img)
-    lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, bits, N, workspace=lod_ws, out=lod_img, out_hl=hl_img)
+    hl_ws = torch.empty(lib.splat_lod_highlight_workspace_bytes(tree.node_capacity, max_draw, len(hl_ids), cam),
+                        dtype=torch.uint8, device=dev)
+    lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, flags, len(hl_ids), workspace=hl_ws, out=lod_img,
+                            out_hl=hl_img)
     plain_ms = timed(lambda: lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=lod_ws, out=lod_img))
-    hl_ms = timed(lambda: lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, bits, N, workspace=lod_ws,
-                                                  out=lod_img, out_hl=hl_img))
-    extra["highlight"] = {"selected_ids": int(len(hl_ids)), "lod_render_ms": round(plain_ms, 4),
+    hl_ms = timed(lambda: lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, flags, len(hl_ids),
+                                                  workspace=hl_ws, out=lod_img, out_hl=hl_img))
+    extra["highlight"] = {"selected_ids": int(len(hl_ids)), "flags_ms_per_list": round(flags_ms, 4),
+                          "lod_render_ms": round(plain_ms, 4),
                           "lod_render_highlight_ms": round(hl_ms, 4),
                           "penalty_frac": round(hl_ms / plain_ms - 1.0, 4),
                           "highlighted_mass_frac": round(float(hl_img.double().sum() / lod_img.double().sum()), 4)}
@@ -419,7 +426,7 @@ def main():
     cub_ms = timed(lambda: lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=cub_ws, out=lod_img, blob=cub))
     extra["cubic_blob"] = {"h_px": 1.5, "lod_render_ms": round(cub_ms, 4),
                            "Mpts_s": round(drawn / cub_ms / 1e3, 1)}
-    del cub_ws, bits, hl_img
+    del cub_ws, bits, flags, hl_img, hl_ws
     log(f"[bench] highlight {extra['highlight']}, cubic {extra['cubic_blob']}")
 
     if not args.no_compare_modes:

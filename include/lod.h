@@ -245,8 +245,8 @@ lod_status splat_render_aux(const float *x, const float *y, const float *z, cons
                             uint64_t count, const lod_camera *cam, const splat_params *sp, void *workspace,
                             size_t workspace_bytes, float *image, float *image_aux, lod_stream_t stream);
 
-/* Workspace bytes for splat_render_lod and splat_render_lod_highlight on a
- * tree of node_capacity nodes drawing at most max_points points. */
+/* Workspace bytes for splat_render_lod on a tree of node_capacity nodes
+ * drawing at most max_points points. */
 lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,
                           const splat_params *sp, size_t *workspace_bytes);
 
@@ -261,17 +261,75 @@ lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids,
                             lod_stream_t stream);
 
 /* ID highlighting (highlighting paragraph: points whose id is in a list of
- * up to a million selected ids, tested as each point is drawn).  As
- * splat_render_lod, plus image_hl (device float32 [H*W]) = the same render
- * restricted to stored points whose pt_id has its bit set in the bitset
- * `bits` (device uint32 [ceil(n_bits/32)], bit i of word i/32 = id i; ids
- * >= n_bits are not highlighted).  The membership test runs inside the
- * binning pass. */
+ * up to a million selected ids, tested as each point is drawn).  The list
+ * is a bitset over ids (device uint32 [ceil(n_bits/32)], bit i of word i/32
+ * = id i; ids >= n_bits are never selected).  lod_highlight_flags turns it,
+ * once per list, into one flag bit per stored point of the tree: flags
+ * (device uint32 [2 ceil(point_capacity / 64)]) bit s of word s/32 = stored
+ * point s has a selected id (a list changes far less often than frames are
+ * drawn, and the per-point flags are read in drawing order). */
+lod_status lod_highlight_flags(const lod_tree *tree, const uint32_t *bits, uint64_t n_bits, uint32_t *flags,
+                               lod_stream_t stream);
+
+/* image as splat_render_lod; image_hl (device float32 [H*W]) = the same
+ * blobs summed over the drawn points whose flag is set.  The flag test runs
+ * inside the main render's binning pass, which stages the flagged points in
+ * drawing order; they are then drawn by a second render of at most
+ * max_highlighted points (a cut draws each particle at most once, so the
+ * number of selected ids is a bound; more sets LOD_STATUS_CAPACITY in
+ * tree->counts[2] and truncates).  Both images are bit-reproducible.
+ * workspace: splat_lod_highlight_plan. */
+lod_status splat_lod_highlight_plan(uint64_t node_capacity, uint64_t max_points, uint64_t max_highlighted,
+                                    const lod_camera *cam, const splat_params *sp, size_t *workspace_bytes);
 lod_status splat_render_lod_highlight(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
                                       uint64_t max_points, const lod_camera *cam, const splat_params *sp,
-                                      const uint32_t *bits, uint64_t n_bits, void *workspace,
-                                      size_t workspace_bytes, float *image, float *image_hl,
-                                      lod_stream_t stream);
+                                      const uint32_t *flags, uint64_t max_highlighted, void *workspace,
+                                      size_t workspace_bytes, float *image, float *image_hl, lod_stream_t stream);
+
+/* ---- time interpolation between snapshots (rendering paragraph: points
+ * carry time information; position, size and colour are interpolated for
+ * every frame) ----------------------------------------------------------- */
+
+/* One snapshot's per-particle arrays (device float32 [count]); the same
+ * index is the same particle in both snapshots.  h: world radius of the
+ * cubic blob (perspective only) or NULL; c: colour value or NULL. */
+typedef struct {
+  const float *x, *y, *z, *m, *h, *c;
+} splat_frame;
+
+/* The frame at time t in [0, 1] between snapshots a and b: every quantity
+ * (position, mass, and the radius and colour when given) is
+ * fl(q_a + fl(t fl(q_b - q_a))) in float32; image = splat_render of those
+ * points; with colours, image_color = sum m(t) c(t) W (the attribute
+ * channel of splat_render_aux).  Radii require blob = LOD_BLOB_CUBIC and a
+ * perspective camera; they replace sp->h_world per point.  workspace as
+ * sized by splat_plan. */
+lod_status splat_render_interp(const splat_frame *a, const splat_frame *b, uint64_t count, float t,
+                               const lod_camera *cam, const splat_params *sp, void *workspace,
+                               size_t workspace_bytes, float *image, float *image_color, lod_stream_t stream);
+
+/* Motion codes of a tree's stored points (quantisation paragraph: the other
+ * properties of a point are encoded like its position): for a point stored
+ * at depth d with position code Q0 = (c << 16) + q per axis and its
+ * particle's position a in the next snapshot (x_next..z_next, device
+ * float32, indexed like the build input: snapshot offset + id),
+ * dq = floor((floor(a 2^(d+16)) - Q0 + 2) / 4) clamped to int16, i.e. the
+ * motion in steps of four position quanta, two block sides either way.
+ * dqx/dqy/dqz: device int16 [point capacity]; *saturated (device uint64)
+ * receives the number of clamped components.  snap_offsets: as given to
+ * lod_build, or NULL for a single snapshot. */
+lod_status lod_encode_motion(const lod_tree *tree, const float *x_next, const float *y_next, const float *z_next,
+                             const uint64_t *snap_offsets, int16_t *dqx, int16_t *dqy, int16_t *dqz,
+                             uint64_t *saturated, lod_stream_t stream);
+
+/* splat_render_lod at frame time t in [0, 1]: each stored point is drawn at
+ * fl(p + fl(t fl(p' - p))) between its decoded position p and the position
+ * p' = the float32 nearest (2 (c 2^16 + q + 4 dq) + 1) 2^-(d+17) of its
+ * motion code.  Masses are the stored ones.  workspace: splat_lod_plan. */
+lod_status splat_render_lod_motion(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                                   uint64_t max_points, const int16_t *dqx, const int16_t *dqy, const int16_t *dqz,
+                                   float t, const lod_camera *cam, const splat_params *sp, void *workspace,
+                                   size_t workspace_bytes, float *image, lod_stream_t stream);
 
 /* Workspace bytes for lod_decode on a tree of node_capacity nodes. */
 lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes);

@@ -28,6 +28,7 @@ project's design notes and in the docstring of the function that uses it.
 Modules: ``philox`` (counter-based generator), ``lod`` (the build),
 ``splat`` (render and its adjoint), ``cut`` (view-dependent node choice),
 ``refine`` (one step of the gradient refinement of a node), ``cubic`` (the
-radial cubic blob and the attribute channel).
+radial cubic blob and the attribute channel), ``interp`` (time interpolation
+between snapshots and the motion codes of stored points).
 """
-from . import philox, lod, splat, cut, refine, cubic  # noqa: F401
+from . import philox, lod, splat, cut, refine, cubic, interp  # noqa: F401

@@ -70,12 +70,13 @@ def dw(q):
 
 
 def pixel_radius(cam: Camera, zc, h_px, h_world):
-    """(h float32 per point, clamped mask) by the pinned sequence."""
-    if h_world:
+    """(h float32 per point, clamped mask) by the pinned sequence; h_world may
+    be one radius or one per point."""
+    if np.any(np.asarray(h_world) != 0):
         if cam.projection != 1:
             raise ValueError("a world-space size needs a perspective camera")
         zs = np.asarray(zc, dtype=f32)
-        hw = f32(cam.F) * f32(h_world)
+        hw = f32(cam.F) * np.asarray(h_world, dtype=f32)
         hp = hw / np.where(zs > 0, zs, f32(1.0))
         h = np.minimum(np.maximum(hp, f32(H_MIN_PX)), f32(H_MAX_PX)).astype(f32)
         clamped = (hp < f32(H_MIN_PX)) | (hp > f32(H_MAX_PX))
@@ -86,7 +87,7 @@ def pixel_radius(cam: Camera, zc, h_px, h_world):
 def _setup(cam, x, y, z, h_px, h_world):
     x = np.asarray(x, dtype=f32)
     u, v, keep, xc, yc, zc = project(cam, x, y, z)
-    if h_world:
+    if np.any(np.asarray(h_world) != 0):
         h, clamped = pixel_radius(cam, zc, h_px, h_world)
     else:
         h = np.full(len(x), f32(h_px), dtype=f32)

@@ -187,37 +187,19 @@ lod_status splat_render_aux(const float *x, const float *y, const float *z, cons
   return splat_common(x, y, z, m, aux, count, cam, sp, workspace, workspace_bytes, image, image_aux, stream);
 }
 
-static lod_status splat_lod_common(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
-                                   uint64_t max_points, const lod_camera *cam, const splat_params *sp,
-                                   const uint32_t *bits, uint64_t n_bits, void *workspace, size_t workspace_bytes,
-                                   float *image, float *image_hl, lod_stream_t stream) {
+lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                            uint64_t max_points, const lod_camera *cam, const splat_params *sp, void *workspace,
+                            size_t workspace_bytes, float *image, lod_stream_t stream) {
   if (!tree_arrays_ok(tree) || !node_ids || !n_ids || !check_camera(cam, sp) || !image || !workspace)
     return LOD_EINVAL;
   if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
   lodh::LodDrawLayout D = lodh::lod_draw_layout(tree->node_capacity, max_points);
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, image_hl != nullptr);
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, false);
   if (s != LOD_OK) return s;
   if (workspace_bytes < D.total + L.total) return LOD_ENOMEM;
-  return lodh::launch_splat_lod(*tree, node_ids, n_ids, workspace, D, *cam, *sp, L, bits, n_bits, image, image_hl,
-                                (hipStream_t)stream);
-}
-
-lod_status splat_render_lod(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
-                            uint64_t max_points, const lod_camera *cam, const splat_params *sp, void *workspace,
-                            size_t workspace_bytes, float *image, lod_stream_t stream) {
-  return splat_lod_common(tree, node_ids, n_ids, max_points, cam, sp, nullptr, 0, workspace, workspace_bytes, image,
-                          nullptr, stream);
-}
-
-lod_status splat_render_lod_highlight(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
-                                      uint64_t max_points, const lod_camera *cam, const splat_params *sp,
-                                      const uint32_t *bits, uint64_t n_bits, void *workspace,
-                                      size_t workspace_bytes, float *image, float *image_hl,
-                                      lod_stream_t stream) {
-  if (!bits || n_bits == 0 || !image_hl) return LOD_EINVAL;
-  return splat_lod_common(tree, node_ids, n_ids, max_points, cam, sp, bits, n_bits, workspace, workspace_bytes, image,
-                          image_hl, stream);
+  return lodh::launch_splat_lod(*tree, node_ids, n_ids, workspace, D, *cam, *sp, L, nullptr, nullptr, image,
+                                nullptr, (hipStream_t)stream);
 }
 
 lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod_camera *cam,
@@ -225,10 +207,103 @@ lod_status splat_lod_plan(uint64_t node_capacity, uint64_t max_points, const lod
   if (!workspace_bytes || !check_camera(cam, sp)) return LOD_EINVAL;
   lodh::LodDrawLayout D = lodh::lod_draw_layout(node_capacity, max_points);
   lodh::SplatLayout L;
-  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, true);   // covers both forms
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, false);
   if (s != LOD_OK) return s;
   *workspace_bytes = D.total + L.total;
   return LOD_OK;
+}
+
+// Layouts of the highlighted LOD render: the plain one, then the staging and
+// the second render.
+static lod_status highlight_layouts(uint64_t node_capacity, uint64_t max_points, uint64_t max_highlighted,
+                                    const lod_camera *cam, const splat_params *sp, lodh::LodDrawLayout &D,
+                                    lodh::SplatLayout &L, lodh::HlLayout &H) {
+  D = lodh::lod_draw_layout(node_capacity, max_points);
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, false);
+  if (s != LOD_OK) return s;
+  H = lodh::hl_layout(L, max_highlighted, *cam, *sp, s);
+  return s;
+}
+
+lod_status splat_lod_highlight_plan(uint64_t node_capacity, uint64_t max_points, uint64_t max_highlighted,
+                                    const lod_camera *cam, const splat_params *sp, size_t *workspace_bytes) {
+  if (!workspace_bytes || !check_camera(cam, sp) || max_highlighted == 0) return LOD_EINVAL;
+  lodh::LodDrawLayout D;
+  lodh::SplatLayout L;
+  lodh::HlLayout H;
+  lod_status s = highlight_layouts(node_capacity, max_points, max_highlighted, cam, sp, D, L, H);
+  if (s != LOD_OK) return s;
+  *workspace_bytes = D.total + L.total + H.total;
+  return LOD_OK;
+}
+
+lod_status lod_highlight_flags(const lod_tree *tree, const uint32_t *bits, uint64_t n_bits, uint32_t *flags,
+                               lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !bits || n_bits == 0 || !flags) return LOD_EINVAL;
+  return lodh::launch_hl_flags(*tree, bits, n_bits, flags, (hipStream_t)stream);
+}
+
+lod_status splat_render_lod_highlight(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                                      uint64_t max_points, const lod_camera *cam, const splat_params *sp,
+                                      const uint32_t *flags, uint64_t max_highlighted, void *workspace,
+                                      size_t workspace_bytes, float *image, float *image_hl, lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !node_ids || !n_ids || !check_camera(cam, sp) || !image || !workspace)
+    return LOD_EINVAL;
+  if (!flags || !image_hl || max_highlighted == 0) return LOD_EINVAL;
+  if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
+  lodh::LodDrawLayout D;
+  lodh::SplatLayout L;
+  lodh::HlLayout H;
+  lod_status s = highlight_layouts(tree->node_capacity, max_points, max_highlighted, cam, sp, D, L, H);
+  if (s != LOD_OK) return s;
+  if (workspace_bytes < D.total + L.total + H.total) return LOD_ENOMEM;
+  return lodh::launch_splat_lod(*tree, node_ids, n_ids, workspace, D, *cam, *sp, L, flags, &H, image, image_hl,
+                                (hipStream_t)stream);
+}
+
+lod_status splat_render_interp(const splat_frame *a, const splat_frame *b, uint64_t count, float t,
+                               const lod_camera *cam, const splat_params *sp, void *workspace,
+                               size_t workspace_bytes, float *image, float *image_color, lod_stream_t stream) {
+  if (!a || !b || !check_camera(cam, sp) || !image || !workspace) return LOD_EINVAL;
+  if (!(t >= 0.0f && t <= 1.0f)) return LOD_EINVAL;
+  if (count && (!a->x || !a->y || !a->z || !a->m || !b->x || !b->y || !b->z || !b->m)) return LOD_EINVAL;
+  const bool sizes = a->h || b->h, colours = a->c || b->c;
+  if (sizes && (!a->h || !b->h || sp->blob != LOD_BLOB_CUBIC || cam->projection != 1)) return LOD_EINVAL;
+  if (colours != (image_color != nullptr) || (colours && (!a->c || !b->c))) return LOD_EINVAL;
+  if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
+  lodh::SplatLayout L;
+  lod_status s = lodh::splat_layout(count, *cam, *sp, L, colours);
+  if (s != LOD_OK) return s;
+  if (workspace_bytes < L.total) return LOD_ENOMEM;
+  lodh::InterpArgs ia{a->x, a->y, a->z, a->m, b->x, b->y, b->z, b->m, a->h, b->h, a->c, b->c, count, t};
+  return lodh::launch_splat_interp(ia, *cam, *sp, workspace, L, image, image_color, (hipStream_t)stream);
+}
+
+lod_status lod_encode_motion(const lod_tree *tree, const float *x_next, const float *y_next, const float *z_next,
+                             const uint64_t *snap_offsets, int16_t *dqx, int16_t *dqy, int16_t *dqz,
+                             uint64_t *saturated, lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !x_next || !y_next || !z_next || !dqx || !dqy || !dqz || !saturated)
+    return LOD_EINVAL;
+  return lodh::launch_encode_motion(*tree, x_next, y_next, z_next, snap_offsets, dqx, dqy, dqz, saturated,
+                                    (hipStream_t)stream);
+}
+
+lod_status splat_render_lod_motion(const lod_tree *tree, const uint32_t *node_ids, const uint64_t *n_ids,
+                                   uint64_t max_points, const int16_t *dqx, const int16_t *dqy, const int16_t *dqz,
+                                   float t, const lod_camera *cam, const splat_params *sp, void *workspace,
+                                   size_t workspace_bytes, float *image, lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || !node_ids || !n_ids || !dqx || !dqy || !dqz || !check_camera(cam, sp) || !image ||
+      !workspace)
+    return LOD_EINVAL;
+  if (!(t >= 0.0f && t <= 1.0f)) return LOD_EINVAL;
+  if (((uintptr_t)workspace) & 255) return LOD_EINVAL;
+  lodh::LodDrawLayout D = lodh::lod_draw_layout(tree->node_capacity, max_points);
+  lodh::SplatLayout L;
+  lod_status s = lodh::splat_layout(D.max_points, *cam, *sp, L, false);
+  if (s != LOD_OK) return s;
+  if (workspace_bytes < D.total + L.total) return LOD_ENOMEM;
+  return lodh::launch_splat_lod_motion(*tree, node_ids, n_ids, workspace, D, dqx, dqy, dqz, t, *cam, *sp, L, image,
+                                       (hipStream_t)stream);
 }
 
 lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes) {

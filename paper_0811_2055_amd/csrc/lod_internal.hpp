@@ -58,6 +58,15 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
 lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, const float *aux,
                         uint64_t count, const lod_camera &cam, const splat_params &sp, void *ws, const SplatLayout &L,
                         float *image, float *image_aux, hipStream_t st);
+// Two snapshots of the same particles and a frame time (time interpolation).
+struct InterpArgs {
+  const float *xa, *ya, *za, *ma, *xb, *yb, *zb, *mb;
+  const float *ha, *hb, *ca, *cb;
+  uint64_t count;
+  float t;
+};
+lod_status launch_splat_interp(const InterpArgs &a, const lod_camera &cam, const splat_params &sp, void *ws,
+                               const SplatLayout &L, float *image, float *image_color, hipStream_t st);
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m,
                                  uint64_t count, const lod_camera &cam, const splat_params &sp,
                                  const float *grad, float *gm, float *gx, float *gy, float *gz,
@@ -70,10 +79,30 @@ struct LodDrawLayout {
   size_t total;
 };
 LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points);
+// ID highlighting: staging of the selected drawn points (4 float arrays of
+// the main render's max_points), per-unit counts and their scan, the
+// gathered points (4 float arrays of cap) and the small render's layout.
+struct HlLayout {
+  uint64_t cap;
+  size_t stage[4], count, scan, scan_tmp, total_ctr, pts[4], splat;
+  SplatLayout L2;
+  size_t total;
+};
+HlLayout hl_layout(const SplatLayout &L, uint64_t max_highlighted, const lod_camera &cam, const splat_params &sp,
+                   lod_status &s);
+lod_status launch_hl_flags(const lod_tree &tree, const uint32_t *bits, uint64_t n_bits, uint32_t *flags,
+                           hipStream_t st);
 lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
                             const LodDrawLayout &D, const lod_camera &cam, const splat_params &sp,
-                            const SplatLayout &L, const uint32_t *hl_bits, uint64_t hl_nbits, float *image,
-                            float *image_hl, hipStream_t st);
+                            const SplatLayout &L, const uint32_t *hl_flags, const HlLayout *H,
+                            float *image, float *image_hl, hipStream_t st);
+lod_status launch_encode_motion(const lod_tree &tree, const float *xb, const float *yb, const float *zb,
+                                const uint64_t *snap_off, int16_t *dqx, int16_t *dqy, int16_t *dqz,
+                                uint64_t *saturated, hipStream_t st);
+lod_status launch_splat_lod_motion(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
+                                   const LodDrawLayout &D, const int16_t *dqx, const int16_t *dqy,
+                                   const int16_t *dqz, float t, const lod_camera &cam, const splat_params &sp,
+                                   const SplatLayout &L, float *image, hipStream_t st);
 size_t decode_workspace(uint64_t node_capacity);
 lod_status launch_decode(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
                          float *x, float *y, float *z, float *m, uint64_t *n_points, void *ws, hipStream_t st);

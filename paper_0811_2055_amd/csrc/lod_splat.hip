@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "lod.h"
@@ -147,6 +148,16 @@ __device__ __forceinline__ float decode_coord(uint32_t c, uint32_t q, int d) {
   return (float)(2u * ((c << 16) + q) + 1u) * ldexpf(1.0f, -(d + 17));
 }
 
+// float32 nearest (2 (c 2^16 + q + 4 dq) + 1) 2^-(d+17): the position a motion
+// code dq moves a stored point to (signed: a point may leave its cell)
+__device__ __forceinline__ float decode_motion(uint32_t c, uint32_t q, int dq, int d) {
+  const int64_t Q = ((int64_t)c << 16) + (int64_t)q + 4 * (int64_t)dq;
+  return (float)(2 * Q + 1) * ldexpf(1.0f, -(d + 17));
+}
+
+// fl(a + fl(t fl(b - a))): the value at frame time t in [0, 1] between a and b
+__device__ __forceinline__ float lerp_t(float a, float b, float t) { return a + t * (b - a); }
+
 // Point sources.  A wave first resolves the addresses of its next BR rounds of
 // points (resolve + end_round, in round order), then issues all their loads
 // at once (fetch), so one memory latency covers BR rounds.
@@ -172,16 +183,53 @@ struct RawSrc {
     }
     // the point's attribute (second image channel)
     __device__ __forceinline__ float attr(const RawSrc &s, const Addr &a) const { return s.aux[a.k]; }
+    __device__ __forceinline__ float wradius(const RawSrc &, const Addr &) const { return 0.0f; }
+  };
+  __device__ uint64_t count() const { return n_dev ? min(*n_dev, n) : n; }
+  const float *aux = nullptr;
+  const uint64_t *n_dev = nullptr;   // device count (at most n), when set
+};
+
+// Two snapshots of the same particles and a frame time t: every quantity is
+// fl(a + fl(t fl(b - a))); per-point world radii (cubic blob) and colours
+// are optional.
+struct InterpSrc {
+  const float *xa, *ya, *za, *ma, *xb, *yb, *zb, *mb;
+  const float *ha, *hb, *ca, *cb;   // may be null
+  uint64_t n;
+  float t;
+  struct Addr {
+    uint64_t k;
+  };
+  struct Cursor {
+    uint64_t last;
+    __device__ void begin(const InterpSrc &, uint64_t b, uint64_t e) { last = e - 1; }
+    __device__ __forceinline__ Addr resolve(const InterpSrc &, uint64_t k, bool valid) {
+      return Addr{valid ? k : last};
+    }
+    __device__ void end_round(const InterpSrc &) {}
+    __device__ __forceinline__ void fetch(const InterpSrc &s, const Addr &a, bool, float &px, float &py,
+                                          float &pz, float &pm) const {
+      const float x0 = s.xa[a.k], y0 = s.ya[a.k], z0 = s.za[a.k], m0 = s.ma[a.k];
+      const float x1 = s.xb[a.k], y1 = s.yb[a.k], z1 = s.zb[a.k], m1 = s.mb[a.k];
+      px = lerp_t(x0, x1, s.t); py = lerp_t(y0, y1, s.t); pz = lerp_t(z0, z1, s.t); pm = lerp_t(m0, m1, s.t);
+    }
+    __device__ __forceinline__ float attr(const InterpSrc &s, const Addr &a) const {
+      return lerp_t(s.ca[a.k], s.cb[a.k], s.t);
+    }
+    __device__ __forceinline__ float wradius(const InterpSrc &s, const Addr &a) const {
+      return s.ha ? lerp_t(s.ha[a.k], s.hb[a.k], s.t) : 0.0f;
+    }
   };
   __device__ uint64_t count() const { return n; }
-  const float *aux = nullptr;
 };
 
 // The stored points of a list of tree nodes, decoded on the fly.  offs is the
 // exclusive scan of the nodes' point counts; the wave keeps the node holding
 // its current point in registers and walks offs per lane when a round crosses
 // into later nodes.
-struct TreeSrc {
+template <bool MOTION>
+struct TreeSrcT {
   lod_tree t;
   const uint32_t *ids;
   const uint64_t *offs;
@@ -197,7 +245,7 @@ struct TreeSrc {
     uint64_t c, ob, oe, pb, far_c;
     uint32_t cx, cy, cz;
     int d;
-    __device__ __forceinline__ void set(const TreeSrc &s, uint64_t cc) {
+    __device__ __forceinline__ void set(const TreeSrcT &s, uint64_t cc) {
       c = cc;
       const uint32_t v = s.ids[cc];
       ob = s.offs[cc]; oe = s.offs[cc + 1];
@@ -208,7 +256,7 @@ struct TreeSrc {
       pb = s.t.pt_begin[v];
       far_c = cc;
     }
-    __device__ void begin(const TreeSrc &s, uint64_t b, uint64_t) {
+    __device__ void begin(const TreeSrcT &s, uint64_t b, uint64_t) {
       // the last node whose offset is <= b; it holds point b (b < total)
       uint64_t lo = 0, hi = min(*s.n_ids, s.max_ids);
       while (hi - lo > 1) {
@@ -217,7 +265,7 @@ struct TreeSrc {
       }
       set(s, lo);
     }
-    __device__ __forceinline__ Addr resolve(const TreeSrc &s, uint64_t k, bool valid) {
+    __device__ __forceinline__ Addr resolve(const TreeSrcT &s, uint64_t k, bool valid) {
       // invalid lanes load the cached node's first point (in bounds, unused)
       Addr a{pb, cx, cy, cz, d};
       if (!valid) return a;
@@ -237,33 +285,54 @@ struct TreeSrc {
       return a;
     }
     // move the cached node to the furthest node any lane reached
-    __device__ void end_round(const TreeSrc &s) {
+    __device__ void end_round(const TreeSrcT &s) {
       if (!__ballot(far_c != c)) return;      // every lane stayed in the cached node
       uint64_t f = far_c;
 #pragma unroll
       for (int o = 1; o < WAVE; o <<= 1) f = max(f, (uint64_t)__shfl_xor(f, o, WAVE));
       if (f != c) set(s, f);
     }
-    __device__ __forceinline__ void fetch(const TreeSrc &s, const Addr &a, bool, float &px, float &py,
+    __device__ __forceinline__ void fetch(const TreeSrcT &s, const Addr &a, bool, float &px, float &py,
                                           float &pz, float &pm) const {
       const uint32_t qx = s.t.qx[a.sidx], qy = s.t.qy[a.sidx], qz = s.t.qz[a.sidx];
       pm = s.t.pt_mass[a.sidx];
-      px = decode_coord(a.cx, qx, a.d);
-      py = decode_coord(a.cy, qy, a.d);
-      pz = decode_coord(a.cz, qz, a.d);
+      if constexpr (MOTION) {
+        // the point at frame time t between its decoded position and the
+        // position its motion code decodes to
+        const int dx = s.dqx[a.sidx], dy = s.dqy[a.sidx], dz = s.dqz[a.sidx];
+        px = lerp_t(decode_coord(a.cx, qx, a.d), decode_motion(a.cx, qx, dx, a.d), s.t_frame);
+        py = lerp_t(decode_coord(a.cy, qy, a.d), decode_motion(a.cy, qy, dy, a.d), s.t_frame);
+        pz = lerp_t(decode_coord(a.cz, qz, a.d), decode_motion(a.cz, qz, dz, a.d), s.t_frame);
+      } else {
+        px = decode_coord(a.cx, qx, a.d);
+        py = decode_coord(a.cy, qy, a.d);
+        pz = decode_coord(a.cz, qz, a.d);
+      }
     }
-    // 1 when the point's id is set in the highlight bitset, else 0
-    __device__ __forceinline__ float attr(const TreeSrc &s, const Addr &a) const {
-      const uint32_t id = s.t.pt_id[a.sidx];
-      const uint64_t wi = min((uint64_t)(id >> 5), s.hl_words - 1);
-      const uint32_t word = s.hl_bits[wi];
-      return ((uint64_t)id < s.hl_nbits && ((word >> (id & 31u)) & 1u)) ? 1.0f : 0.0f;
+    __device__ __forceinline__ float wradius(const TreeSrcT &, const Addr &) const { return 0.0f; }
+    // 1 when the stored point's highlight flag is set, else 0
+    __device__ __forceinline__ float attr(const TreeSrcT &s, const Addr &a) const {
+      return s.hl_test(a.sidx, s.hl_word(a.sidx)) ? 1.0f : 0.0f;
     }
+    __device__ __forceinline__ uint64_t point_index(const TreeSrcT &, const Addr &a) const { return a.sidx; }
   };
   __device__ uint64_t count() const { return *total; }
-  const uint32_t *hl_bits = nullptr;   // highlight bitset (bit id set = highlighted)
-  uint64_t hl_nbits = 0, hl_words = 1;
+  const uint32_t *hl_flags = nullptr;  // highlight flags, one bit per stored point
+  uint64_t hl_words = 1;
+  const int16_t *dqx = nullptr, *dqy = nullptr, *dqz = nullptr;   // motion codes (MOTION)
+  float t_frame = 0.0f;
+  // the flag word of stored point s (in bounds for any s) and its flag
+  __device__ __forceinline__ uint32_t hl_word(uint64_t sidx) const {
+    return hl_flags[min(sidx >> 5, hl_words - 1)];
+  }
+  __device__ __forceinline__ bool hl_test(uint64_t sidx, uint32_t word) const {
+    return (word >> (uint32_t)(sidx & 31u)) & 1u;
+  }
 };
+using TreeSrc = TreeSrcT<false>;
+using TreeMotionSrc = TreeSrcT<true>;
+template <class S> struct IsTree { static constexpr bool value = false; };
+template <bool M> struct IsTree<TreeSrcT<M>> { static constexpr bool value = true; };
 
 // One point's screen position, pixel radius (cubic blob), attribute and tile
 // rectangle (ntx = nty = 0: not drawn).
@@ -302,18 +371,20 @@ __device__ __forceinline__ bool cover_range(float R, float t, uint32_t size, int
 
 // Pixel radius of a cubic blob at camera depth zc: the fixed radius, or the
 // projected world radius fl(fl(F h_world) / zc) clamped to [1, 16] pixels.
-__device__ __forceinline__ float cubic_radius(const Cam &c, float zc) {
-  if (c.Fhw > 0.0f) return fminf(fmaxf(__fdiv_rn(c.Fhw, zc), lodh::BLOB_H_MIN), lodh::BLOB_H_MAX);
+// A per-point world radius hw > 0 replaces the camera's.
+__device__ __forceinline__ float cubic_radius(const Cam &c, float zc, float hw = 0.0f) {
+  const float Fhw = hw > 0.0f ? c.F * hw : c.Fhw;
+  if (Fhw > 0.0f) return fminf(fmaxf(__fdiv_rn(Fhw, zc), lodh::BLOB_H_MIN), lodh::BLOB_H_MAX);
   return c.hpx;
 }
 
 __device__ __forceinline__ Blob make_blob(const Cam &c, bool valid, float px, float py, float pz, float pm,
-                                          float pa = 0.0f) {
+                                          float pa = 0.0f, float hw = 0.0f) {
   Blob b{0.0f, 0.0f, pm, 0.0f, pa, 0, 0, 0, 0};
   if (!valid) return b;
   float xc, yc, zc;
   if (!project(c, px, py, pz, b.u, b.v, xc, yc, zc)) return b;
-  const float R = c.blob == LOD_BLOB_CUBIC ? cubic_radius(c, zc) : c.R;
+  const float R = c.blob == LOD_BLOB_CUBIC ? cubic_radius(c, zc, hw) : c.R;
   b.h = R;
   int i0, i1, j0, j1;
   if (!cover_range(R, b.u, c.W, i0, i1) || !cover_range(R, b.v, c.H, j0, j1)) return b;
@@ -380,16 +451,25 @@ __device__ __forceinline__ void emit_tile(uint32_t t, bool has, int nbits, CT *l
   }
 }
 
+// Highlight staging: the count pass writes the decoded points whose id is
+// selected to x, y, z, m at [b, b + k) of its unit's point range [b, e)
+// (sequence order), and k to count[unit].
+struct HlStage {
+  float *x, *y, *z, *m;
+  uint64_t *count, *scan;   // per unit (scan: a copy, scanned afterwards)
+};
+
 // Points [u0 per, min(n, (u0 + g) per)) with per = ceil(n / units): g
-// consecutive units of the partition.
-template <class Src, bool FILL, class CT, class RecT>
-__device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t units, uint32_t u0, uint32_t g,
-                                         int nbits, CT *lc, RecT *__restrict__ rec) {
+// consecutive units of the partition.  Returns the points staged (HL).
+template <class Src, bool FILL, class CT, class RecT, bool HL = false>
+__device__ __forceinline__ uint32_t bin_unit(const Src &src, const Cam &c, uint32_t units, uint32_t u0, uint32_t g,
+                                             int nbits, CT *lc, RecT *__restrict__ rec, HlStage hs = HlStage{}) {
   const int lane = threadIdx.x;
   const uint64_t n = src.count();
   const uint64_t per = (n + units - 1) / units;
   const uint64_t b = (uint64_t)u0 * per, e = min(n, b + (uint64_t)g * per);
-  if (b >= e) return;
+  uint32_t staged = 0;
+  if (b >= e) return 0;
   typename Src::Cursor cur;
   cur.begin(src, b, e);
   for (uint64_t k0 = b; k0 < e; k0 += (uint64_t)BR * WAVE) {
@@ -400,17 +480,42 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
       ad[r] = cur.resolve(src, k, k < e);
       cur.end_round(src);
     }
-    float px[BR], py[BR], pz[BR], pm[BR], pa[BR];
+    float px[BR], py[BR], pz[BR], pm[BR], pa[BR], ph[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const uint64_t k = k0 + (uint64_t)r * WAVE + lane;
       cur.fetch(src, ad[r], k < e, px[r], py[r], pz[r], pm[r]);
       pa[r] = (FILL && RecInfo<RecT>::aux) ? cur.attr(src, ad[r]) : 0.0f;
+      ph[r] = c.blob == LOD_BLOB_CUBIC ? cur.wradius(src, ad[r]) : 0.0f;
+    }
+    if constexpr (HL) {
+      // ID highlighting: the flag test of every drawn point, and the
+      // flagged ones staged in sequence order (wave ballot ranks).  A wave's
+      // points are mostly consecutive stored points, so its flag loads fall
+      // on one or two words.
+      uint64_t pid[BR];
+      uint32_t word[BR];
+#pragma unroll
+      for (int r = 0; r < BR; ++r) pid[r] = cur.point_index(src, ad[r]);
+#pragma unroll
+      for (int r = 0; r < BR; ++r) word[r] = src.hl_word(pid[r]);
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const bool in = k0 + (uint64_t)r * WAVE + lane < e && src.hl_test(pid[r], word[r]);
+        const uint64_t mask = __ballot(in);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        if (in) {
+          const uint64_t o = b + staged + rank;
+          hs.x[o] = px[r]; hs.y[o] = py[r]; hs.z[o] = pz[r]; hs.m[o] = pm[r];
+        }
+        staged += (uint32_t)__popcll(mask);
+      }
     }
     Blob blobs[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r)
-      blobs[r] = make_blob(c, k0 + (uint64_t)r * WAVE + lane < e, px[r], py[r], pz[r], pm[r], pa[r]);
+      blobs[r] = make_blob(c, k0 + (uint64_t)r * WAVE + lane < e, px[r], py[r], pz[r], pm[r], pa[r], ph[r]);
     // pairs in the order (round, tile row, tile column, lane)
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
@@ -424,22 +529,70 @@ __device__ __forceinline__ void bin_unit(const Src &src, const Cam &c, uint32_t 
       }
     }
   }
+  return staged;
 }
 
 // Pass 1: row u of the [U][tiles] count table.  CT = uint16_t when a unit
 // holds at most 65535 points (a point adds at most one pair per tile), which
 // halves the LDS per wave and doubles the resident waves.
-template <class Src, class CT>
+template <class Src, class CT, bool HL = false>
 __global__ __launch_bounds__(BW) void k_bin_count(Src src, Cam c, uint32_t units, int nbits,
-                                                  uint32_t *__restrict__ ucount) {
+                                                  uint32_t *__restrict__ ucount, HlStage hs = HlStage{}) {
   extern __shared__ uint32_t lds_raw[];
   CT *lc = reinterpret_cast<CT *>(lds_raw);
   const uint32_t nt = c.tiles_x * c.tiles_y;
   for (uint32_t i = threadIdx.x; i < nt; i += BW) lc[i] = 0;
   __syncthreads();
-  bin_unit<Src, false, CT, float3>(src, c, units, blockIdx.x, 1, nbits, lc, (float3 *)nullptr);
+  const uint32_t staged =
+      bin_unit<Src, false, CT, float3, HL>(src, c, units, blockIdx.x, 1, nbits, lc, (float3 *)nullptr, hs);
+  if (HL && threadIdx.x == 0) { hs.count[blockIdx.x] = staged; hs.scan[blockIdx.x] = staged; }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nt; i += BW) ucount[(uint64_t)blockIdx.x * nt + i] = lc[i];
+}
+
+// Gather the staged highlighted points into one array in unit order: unit u
+// holds count[u] points at [u per, ...) of the staging arrays and goes to
+// [off[u], ...) (off = exclusive scan of the counts, off[units] = total).
+// At most cap points are kept; more sets the capacity status bit.
+__global__ void k_hl_gather(HlStage hs, const uint64_t *__restrict__ off, const uint64_t *__restrict__ n_points,
+                            uint64_t max_points, uint32_t units, float *__restrict__ x, float *__restrict__ y,
+                            float *__restrict__ z, float *__restrict__ m, uint64_t cap,
+                            uint64_t *__restrict__ total, uint64_t *status) {
+  const uint64_t n = min(*n_points, max_points);
+  const uint64_t per = (n + units - 1) / units;
+  const uint32_t u = blockIdx.x;
+  const uint64_t b = (uint64_t)u * per, o = off[u], k = hs.count[u];
+  for (uint64_t j = threadIdx.x; j < k && o + j < cap; j += blockDim.x) {
+    x[o + j] = hs.x[b + j]; y[o + j] = hs.y[b + j]; z[o + j] = hs.z[b + j]; m[o + j] = hs.m[b + j];
+  }
+  if (u == 0 && threadIdx.x == 0) {
+    const uint64_t tot = off[units];
+    *total = min(tot, cap);
+    if (tot > cap) atomicOr((unsigned long long *)status, (unsigned long long)LOD_STATUS_CAPACITY);
+  }
+}
+
+// Highlight flags of the stored points: bit s of flags (uint32 words) is set
+// when the id of stored point s has its bit in the id bitset (ids >= n_bits
+// are not selected).  One wave codes 64 consecutive points, two words.
+__global__ void k_hl_flags(const lod_tree t, const uint32_t *__restrict__ bits, uint64_t n_bits,
+                           uint64_t cap_points, uint32_t *__restrict__ flags) {
+  const uint64_t np = min(t.counts[1], cap_points);
+  const uint64_t nwords = (n_bits + 31) >> 5;
+  const uint64_t nw = (cap_points + 63) >> 6;     // wave groups of 64 points
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; g < nw;
+       g += ((uint64_t)gridDim.x * blockDim.x) >> 6) {
+    const uint64_t sidx = g * 64 + lane;
+    bool on = false;
+    if (sidx < np) {
+      const uint32_t id = t.pt_id[sidx];
+      const uint32_t w = bits[min((uint64_t)(id >> 5), nwords - 1)];
+      on = (uint64_t)id < n_bits && ((w >> (id & 31u)) & 1u);
+    }
+    const uint64_t mask = __ballot(on);
+    if (lane == 0) reinterpret_cast<uint2 *>(flags)[g] = make_uint2((uint32_t)mask, (uint32_t)(mask >> 32));
+  }
 }
 
 // Column scans of the count table: exclusive prefix over the 64 units of each
@@ -786,10 +939,12 @@ __device__ __forceinline__ void load_rec(const RecCA *r, uint64_t q, float &u, f
 
 // One block per slice (as the Gaussian accumulation); the spline is not
 // separable, so thread p owns pixel p of the 16x16 tile and gathers.  The
-// slice's records are staged in LDS 256 at a time; each wave runs through
-// them in order and skips a record whose blob misses its four pixel rows
-// (a wave-uniform test), so every pixel adds its contributions in record
-// order: the image is bit-reproducible.
+// slice's records are staged in LDS 256 at a time (u, v, h, m as one 16-byte
+// entry, 1/h in float64 beside it); each wave runs through them in order and
+// skips a record whose blob misses its four pixel rows (a wave-uniform test),
+// so every pixel adds its contributions in record order: the image is
+// bit-reproducible.  Covered pixels form q = r / h from a float64 reciprocal
+// square root with one Newton step (relative error far below 1e-12).
 template <class RecT>
 __global__ __launch_bounds__(PT) void k_accumulate_cubic(const uint2 *__restrict__ table,
                                                          const uint32_t *__restrict__ slice_off, uint32_t nt,
@@ -798,7 +953,8 @@ __global__ __launch_bounds__(PT) void k_accumulate_cubic(const uint2 *__restrict
                                                          float *__restrict__ partial_aux, uint64_t max_slices,
                                                          uint64_t max_pairs) {
   constexpr bool AUX = RecInfo<RecT>::aux;
-  __shared__ float su[PT], sv[PT], sm[PT], sh[PT];
+  __shared__ float4 sr[PT];           // u, v, h, m
+  __shared__ double sih[PT];          // 1 / h
   __shared__ float sa[AUX ? PT : 1];
   const uint32_t total_slices = (uint32_t)min((uint64_t)slice_off[nt], max_slices);
   if (blockIdx.x >= total_slices) return;
@@ -818,16 +974,17 @@ __global__ __launch_bounds__(PT) void k_accumulate_cubic(const uint2 *__restrict
       if (c0 + threadIdx.x < pe) {
         float u, v, m, h, a;
         load_rec(rec, c0 + threadIdx.x, u, v, m, h, a);
-        su[threadIdx.x] = u; sv[threadIdx.x] = v; sm[threadIdx.x] = m; sh[threadIdx.x] = h;
+        sr[threadIdx.x] = make_float4(u, v, h, m);
+        sih[threadIdx.x] = 1.0 / (double)h;
         if (AUX) sa[threadIdx.x] = a;
       }
       __syncthreads();
       const int nrec = (int)min((uint64_t)PT, pe - c0);
       for (int k = 0; k < nrec; ++k) {
-        const float v = sv[k], h = sh[k];
+        const float4 r = sr[k];
+        const float u = r.x, v = r.y, h = r.z;
         // the blob covers |oy| < h: skip when it misses all four row centres
         if (v + h + 0.01f < rlo || v - h - 0.01f > rhi) continue;
-        const float u = su[k];
         const float ox = u - cx, oy = v - cy;
         const float r2f = ox * ox + oy * oy;
         if (!(r2f < (h * h) * 1.001f)) continue;   // surely outside (float32 pre-test with margin)
@@ -835,8 +992,13 @@ __global__ __launch_bounds__(PT) void k_accumulate_cubic(const uint2 *__restrict
         const double hh = h64 * h64;
         const double r2 = (double)ox * (double)ox + (double)oy * (double)oy;
         if (!(r2 < hh)) continue;
-        const double q = sqrt(r2) / h64;
-        const double val = (double)sm[k] * (kCubicNorm / hh) * cubic_w(q);
+        double q = 0.0;
+        if (r2 > 0.0) {
+          double y = __builtin_amdgcn_rsq(r2);
+          y = y * (1.5 - (0.5 * r2) * (y * y));     // one Newton step
+          q = (r2 * y) * sih[k];
+        }
+        const double val = (double)r.w * (kCubicNorm / hh) * cubic_w(q);
         neumaier(s, cs, (float)val);
         if (AUX) neumaier(s_a, c_a, (float)(val * (double)sa[k]));
       }
@@ -958,6 +1120,49 @@ __global__ __launch_bounds__(PT) void k_backward(const float *__restrict__ x, co
     if (gy) gy[k] = dy;
     if (gz) gz[k] = dz;
   }
+}
+
+// --- motion codes ----------------------------------------------------------------
+
+// Motion code of one coordinate: the particle's position a in the next
+// snapshot against the stored code Q0 = (c << 16) + q at depth d,
+// dq = floor((floor(a 2^(d+16)) - Q0 + 2) / 4) clamped to int16 (true when clamped).
+__device__ __forceinline__ int16_t motion_code(float a, uint32_t c, uint32_t q, int d, bool &sat) {
+  const int64_t Q1 = (int64_t)floorf(a * ldexpf(1.0f, d + 16));
+  const int64_t Q0 = ((int64_t)c << 16) + (int64_t)q;
+  const int64_t dq = (Q1 - Q0 + 2) >> 2;          // arithmetic shift: floor division by 4
+  sat = dq < -32768 || dq > 32767;
+  return (int16_t)max((int64_t)-32768, min((int64_t)32767, dq));
+}
+
+// One block per node (grid-stride over the node table); thread j codes the
+// node's stored points j, j + blockDim, ...  The next snapshot's positions
+// are indexed like the build input: snapshot offset + particle id.
+__global__ void k_encode_motion(const lod_tree t, const float *__restrict__ xb, const float *__restrict__ yb,
+                                const float *__restrict__ zb, const uint64_t *__restrict__ snap_off,
+                                uint64_t cap_nodes, int16_t *__restrict__ dqx, int16_t *__restrict__ dqy,
+                                int16_t *__restrict__ dqz, uint64_t *__restrict__ saturated) {
+  const uint64_t nn = min(t.counts[0], cap_nodes);
+  uint32_t sat_count = 0;
+  for (uint64_t v = blockIdx.x; v < nn; v += gridDim.x) {
+    const int d = t.depth[v];
+    const uint64_t pfx = t.prefix[v];
+    const uint32_t cell = d ? (uint32_t)(pfx & ((1ull << (3 * d)) - 1)) : 0u;
+    const uint32_t cx = compact3(cell), cy = compact3(cell >> 1), cz = compact3(cell >> 2);
+    const uint64_t base = snap_off ? snap_off[pfx >> (3 * d)] : 0ull;
+    const uint64_t pb = t.pt_begin[v];
+    const uint32_t pc = t.pt_count[v];
+    for (uint32_t j = threadIdx.x; j < pc; j += blockDim.x) {
+      const uint64_t sidx = pb + j;
+      const uint64_t g = base + t.pt_id[sidx];
+      bool s0, s1, s2;
+      dqx[sidx] = motion_code(xb[g], cx, t.qx[sidx], d, s0);
+      dqy[sidx] = motion_code(yb[g], cy, t.qy[sidx], d, s1);
+      dqz[sidx] = motion_code(zb[g], cz, t.qz[sidx], d, s2);
+      sat_count += (uint32_t)s0 + (uint32_t)s1 + (uint32_t)s2;
+    }
+  }
+  if (sat_count) atomicAdd((unsigned long long *)saturated, (unsigned long long)sat_count);
 }
 
 // --- LOD decode ----------------------------------------------------------------
@@ -1114,9 +1319,10 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   L.aux = aux;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-  // units: 64 per chunk, one chunk per 2^21 points (units of at most 32768
-  // points), at most 64 chunks
-  L.chunks = (uint32_t)std::min<uint64_t>(SPLAT_MAX_CHUNKS, std::max<uint64_t>(1, (max_points + (1u << 21) - 1) >> 21));
+  // units: 64 per chunk, one chunk per 2^17 points (units of at most 2048
+  // points until the 64-chunk cap: a million points are binned by 512
+  // waves; 150 M by 4096 units of at most 36.6 k points)
+  L.chunks = (uint32_t)std::min<uint64_t>(SPLAT_MAX_CHUNKS, std::max<uint64_t>(1, (max_points + (1u << 17) - 1) >> 17));
   L.units = 64 * L.chunks;
   L.tile_count = take(4 * (nt + 1));
   L.tile_off = take(4 * (nt + 1));
@@ -1138,7 +1344,7 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
 template <class Src, class RecT>
 static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &cam, const splat_params &sp,
                                    void *ws, const SplatLayout &L, float *image, float *image_aux,
-                                   uint64_t *status_word, hipStream_t st) {
+                                   uint64_t *status_word, hipStream_t st, const HlStage *hs = nullptr) {
   char *W = (char *)ws;
   Cam c = make_cam(cam, sp, &L);
   const uint32_t nt = L.n_tiles;
@@ -1159,11 +1365,27 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   if (!status_word) fill_u64(ctr, 1, 0, st);
   const size_t lds = 4 * (size_t)nt;
   if (any) {
-    if ((L.max_points + L.units - 1) / L.units <= 65535)
-      LOD_LAUNCH((k_bin_count<Src, uint16_t>), dim3(L.units), dim3(BW), 2 * (size_t)nt, st, src, c, L.units, nbits,
-                 ucount);
-    else
-      LOD_LAUNCH((k_bin_count<Src, uint32_t>), dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount);
+    const bool narrow_counts = (L.max_points + L.units - 1) / L.units <= 65535;
+    bool staged = false;
+    if constexpr (IsTree<Src>::value) {
+      if (hs) {
+        staged = true;
+        if (narrow_counts)
+          LOD_LAUNCH((k_bin_count<Src, uint16_t, true>), dim3(L.units), dim3(BW), 2 * (size_t)nt, st, src, c,
+                     L.units, nbits, ucount, *hs);
+        else
+          LOD_LAUNCH((k_bin_count<Src, uint32_t, true>), dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits,
+                     ucount, *hs);
+      }
+    }
+    if (!staged) {
+      if (narrow_counts)
+        LOD_LAUNCH((k_bin_count<Src, uint16_t>), dim3(L.units), dim3(BW), 2 * (size_t)nt, st, src, c, L.units,
+                   nbits, ucount, HlStage{});
+      else
+        LOD_LAUNCH((k_bin_count<Src, uint32_t>), dim3(L.units), dim3(BW), lds, st, src, c, L.units, nbits, ucount,
+                   HlStage{});
+    }
     LOD_LAUNCH(k_bin_colscan, dim3((nt + 255) / 256, L.chunks), dim3(256), 0, st, ucount, nt, pchunk);
     LOD_LAUNCH(k_bin_chunkscan, dim3((nt + 255) / 256), dim3(256), 0, st, pchunk, nt, L.chunks, tcount);
   }
@@ -1203,14 +1425,16 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
 template <class Src>
 static lod_status splat_any(const Src &src, bool any, const lod_camera &cam, const splat_params &sp, void *ws,
                             const SplatLayout &L, float *image, float *image_aux, uint64_t *status_word,
-                            hipStream_t st) {
+                            hipStream_t st, const HlStage *hs = nullptr) {
   const bool cubic = sp.blob == LOD_BLOB_CUBIC;
-  if (L.aux) {
-    if (cubic) return launch_splat_src<Src, RecCA>(src, any, cam, sp, ws, L, image, image_aux, status_word, st);
-    return launch_splat_src<Src, RecGA>(src, any, cam, sp, ws, L, image, image_aux, status_word, st);
+  if constexpr (!IsTree<Src>::value) {   // the LOD render draws no attribute channel
+    if (L.aux) {
+      if (cubic) return launch_splat_src<Src, RecCA>(src, any, cam, sp, ws, L, image, image_aux, status_word, st, hs);
+      return launch_splat_src<Src, RecGA>(src, any, cam, sp, ws, L, image, image_aux, status_word, st, hs);
+    }
   }
-  if (cubic) return launch_splat_src<Src, RecC>(src, any, cam, sp, ws, L, image, nullptr, status_word, st);
-  return launch_splat_src<Src, float3>(src, any, cam, sp, ws, L, image, nullptr, status_word, st);
+  if (cubic) return launch_splat_src<Src, RecC>(src, any, cam, sp, ws, L, image, nullptr, status_word, st, hs);
+  return launch_splat_src<Src, float3>(src, any, cam, sp, ws, L, image, nullptr, status_word, st, hs);
 }
 
 lod_status launch_splat(const float *x, const float *y, const float *z, const float *m, const float *aux,
@@ -1219,6 +1443,39 @@ lod_status launch_splat(const float *x, const float *y, const float *z, const fl
   RawSrc src{x, y, z, m, count};
   src.aux = aux;
   return splat_any(src, count > 0, cam, sp, ws, L, image, image_aux, nullptr, st);
+}
+
+lod_status launch_splat_interp(const InterpArgs &a, const lod_camera &cam, const splat_params &sp, void *ws,
+                               const SplatLayout &L, float *image, float *image_color, hipStream_t st) {
+  const InterpSrc src{a.xa, a.ya, a.za, a.ma, a.xb, a.yb, a.zb, a.mb, a.ha, a.hb, a.ca, a.cb, a.count, a.t};
+  return splat_any(src, a.count > 0, cam, sp, ws, L, image, image_color, nullptr, st);
+}
+
+lod_status launch_encode_motion(const lod_tree &tree, const float *xb, const float *yb, const float *zb,
+                                const uint64_t *snap_off, int16_t *dqx, int16_t *dqy, int16_t *dqz,
+                                uint64_t *saturated, hipStream_t st) {
+  fill_u64(saturated, 1, 0, st);
+  const unsigned g = (unsigned)std::min<uint64_t>(16384, std::max<uint64_t>(1, tree.node_capacity));
+  LOD_LAUNCH(k_encode_motion, dim3(g), dim3(256), 0, st, tree, xb, yb, zb, snap_off, tree.node_capacity, dqx, dqy,
+             dqz, saturated);
+  return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+}
+
+lod_status launch_splat_lod_motion(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
+                                   const LodDrawLayout &D, const int16_t *dqx, const int16_t *dqy,
+                                   const int16_t *dqz, float t, const lod_camera &cam, const splat_params &sp,
+                                   const SplatLayout &L, float *image, hipStream_t st) {
+  char *W = (char *)ws;
+  uint64_t *offs = (uint64_t *)(W + D.offs);
+  uint64_t *cnt = (uint64_t *)(W + D.count);
+  const unsigned g = (unsigned)std::min<uint64_t>(4096, (D.max_ids + 256) / 256);
+  LOD_LAUNCH(k_lod_counts, dim3(g), dim3(256), 0, st, tree, node_ids, n_ids, D.max_ids, offs);
+  device_scan<uint64_t>(offs, D.max_ids + 1, (uint64_t *)(W + D.scan_tmp), st);
+  LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, D.max_ids, D.max_points, cnt);
+  TreeMotionSrc src{tree, node_ids, offs, n_ids, D.max_ids, cnt};
+  src.dqx = dqx; src.dqy = dqy; src.dqz = dqz;
+  src.t_frame = t;
+  return splat_any(src, true, cam, sp, W + D.total, L, image, nullptr, tree.counts + 2, st);
 }
 
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m, uint64_t count,
@@ -1247,10 +1504,36 @@ LodDrawLayout lod_draw_layout(uint64_t node_capacity, uint64_t max_points) {
   return L;
 }
 
+HlLayout hl_layout(const SplatLayout &L, uint64_t max_highlighted, const lod_camera &cam, const splat_params &sp,
+                   lod_status &s) {
+  HlLayout H{};
+  H.cap = std::max<uint64_t>(1, max_highlighted);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  for (int a = 0; a < 4; ++a) H.stage[a] = take(4 * L.max_points);
+  H.count = take(8 * (size_t)L.units);
+  H.scan = take(8 * ((size_t)L.units + 1));
+  H.scan_tmp = take(8 * scan_tmp_elems<uint64_t>((uint64_t)L.units + 1));
+  H.total_ctr = take(64);
+  for (int a = 0; a < 4; ++a) H.pts[a] = take(4 * H.cap);
+  s = splat_layout(H.cap, cam, sp, H.L2, false);
+  H.splat = off;
+  H.total = off + H.L2.total;
+  return H;
+}
+
+lod_status launch_hl_flags(const lod_tree &tree, const uint32_t *bits, uint64_t n_bits, uint32_t *flags,
+                           hipStream_t st) {
+  const uint64_t groups = (tree.point_capacity + 63) / 64;
+  const unsigned g = (unsigned)std::min<uint64_t>(65535, std::max<uint64_t>(1, (groups + 3) / 4));
+  LOD_LAUNCH(k_hl_flags, dim3(g), dim3(256), 0, st, tree, bits, n_bits, tree.point_capacity, flags);
+  return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
+}
+
 lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, void *ws,
                             const LodDrawLayout &D, const lod_camera &cam, const splat_params &sp,
-                            const SplatLayout &L, const uint32_t *hl_bits, uint64_t hl_nbits, float *image,
-                            float *image_hl, hipStream_t st) {
+                            const SplatLayout &L, const uint32_t *hl_flags, const HlLayout *H,
+                            float *image, float *image_hl, hipStream_t st) {
   char *W = (char *)ws;
   uint64_t *offs = (uint64_t *)(W + D.offs);
   uint64_t *cnt = (uint64_t *)(W + D.count);
@@ -1259,10 +1542,27 @@ lod_status launch_splat_lod(const lod_tree &tree, const uint32_t *node_ids, cons
   device_scan<uint64_t>(offs, D.max_ids + 1, (uint64_t *)(W + D.scan_tmp), st);
   LOD_LAUNCH(k_lod_total, dim3(1), dim3(1), 0, st, tree, offs, D.max_ids, D.max_points, cnt);
   TreeSrc src{tree, node_ids, offs, n_ids, D.max_ids, cnt};
-  src.hl_bits = hl_bits;
-  src.hl_nbits = hl_nbits;
-  src.hl_words = std::max<uint64_t>(1, (hl_nbits + 31) / 32);
-  return splat_any(src, true, cam, sp, W + D.total, L, image, image_hl, tree.counts + 2, st);
+  if (!H) return splat_any(src, true, cam, sp, W + D.total, L, image, nullptr, tree.counts + 2, st);
+  // ID highlighting: the count pass of the main render tests every drawn
+  // point's flag and stages the flagged ones; they are gathered in unit
+  // order and drawn by a second, small render
+  src.hl_flags = hl_flags;
+  src.hl_words = (tree.point_capacity + 63) / 64 * 2;
+  char *HW = W + D.total + L.total;
+  HlStage hs{(float *)(HW + H->stage[0]), (float *)(HW + H->stage[1]), (float *)(HW + H->stage[2]),
+             (float *)(HW + H->stage[3]), (uint64_t *)(HW + H->count), (uint64_t *)(HW + H->scan)};
+  fill_u64(hs.scan + L.units, 1, 0, st);
+  lod_status s = splat_any(src, true, cam, sp, W + D.total, L, image, nullptr, tree.counts + 2, st, &hs);
+  if (s != LOD_OK) return s;
+  device_scan<uint64_t>(hs.scan, (uint64_t)L.units + 1, (uint64_t *)(HW + H->scan_tmp), st);
+  float *px = (float *)(HW + H->pts[0]), *py = (float *)(HW + H->pts[1]);
+  float *pz = (float *)(HW + H->pts[2]), *pm = (float *)(HW + H->pts[3]);
+  uint64_t *hl_total = (uint64_t *)(HW + H->total_ctr);
+  LOD_LAUNCH(k_hl_gather, dim3(L.units), dim3(256), 0, st, hs, (const uint64_t *)hs.scan, (const uint64_t *)cnt,
+             D.max_points, L.units, px, py, pz, pm, H->cap, hl_total, tree.counts + 2);
+  RawSrc hsrc{px, py, pz, pm, H->cap};
+  hsrc.n_dev = hl_total;
+  return splat_any(hsrc, true, cam, sp, HW + H->splat, H->L2, image_hl, nullptr, tree.counts + 2, st);
 }
 
 size_t decode_workspace(uint64_t node_capacity) {

@@ -23,7 +23,8 @@ EXPORTS = [
     "lod_build_plan", "lod_build", "lod_select_plan", "lod_select", "splat_plan",
     "splat_render", "splat_lod_plan", "splat_render_lod", "splat_render_backward",
     "lod_decode_plan", "lod_decode", "lod_autotune", "splat_render_noalloc",
-    "splat_render_aux", "splat_render_lod_highlight",
+    "splat_render_aux", "lod_highlight_flags", "splat_lod_highlight_plan", "splat_render_lod_highlight",
+    "splat_render_interp", "lod_encode_motion", "splat_render_lod_motion",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -56,6 +57,10 @@ class CameraC(C.Structure):
     _fields_ = [("projection", C.c_uint32), ("W", C.c_uint32), ("H", C.c_uint32),
                 ("pos", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3),
                 ("fwd", C.c_float * 3), ("F", C.c_float), ("near_z", C.c_float)]
+
+
+class FrameC(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "m", "h", "c")]
 
 
 class KernelTime(C.Structure):
@@ -99,8 +104,16 @@ def load():
                                          P, P]
     lib.splat_render_aux.argtypes = [P, P, P, P, P, C.c_uint64, C.POINTER(CameraC), C.POINTER(SplatParamsC),
                                      P, C.c_size_t, P, P, P]
+    lib.splat_lod_highlight_plan.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(CameraC),
+                                             C.POINTER(SplatParamsC), C.POINTER(C.c_size_t)]
+    lib.lod_highlight_flags.argtypes = [C.POINTER(TreeC), P, C.c_uint64, P, P]
     lib.splat_render_lod_highlight.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, C.POINTER(CameraC),
                                                C.POINTER(SplatParamsC), P, C.c_uint64, P, C.c_size_t, P, P, P]
+    lib.splat_render_interp.argtypes = [C.POINTER(FrameC), C.POINTER(FrameC), C.c_uint64, C.c_float,
+                                        C.POINTER(CameraC), C.POINTER(SplatParamsC), P, C.c_size_t, P, P, P]
+    lib.lod_encode_motion.argtypes = [C.POINTER(TreeC), P, P, P, P, P, P, P, P, P]
+    lib.splat_render_lod_motion.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, C.c_float,
+                                            C.POINTER(CameraC), C.POINTER(SplatParamsC), P, C.c_size_t, P, P]
     lib.lod_decode_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
     lib.lod_decode.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
     lib.lod_autotune.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_size_t, C.POINTER(TreeC),
@@ -522,10 +535,88 @@ def highlight_bits(ids, n_bits: int, device="cuda"):
     return torch.from_numpy(words.view(np.int32)).to(device).view(torch.uint32)
 
 
-def splat_lod_highlight(tree: Tree, node_ids, n_ids, max_points: int, cam: Camera, bits, n_bits: int, sigma=1.0,
-                        radius_sigmas=3.0, workspace=None, out=None, out_hl=None, blob=None):
-    """(image, highlight image): the LOD render and the same render of the stored
-    points whose id is set in the device bitset `bits`."""
+def splat_lod_highlight_workspace_bytes(node_capacity: int, max_points: int, max_highlighted: int, cam: Camera,
+                                        sigma=1.0, radius_sigmas=3.0, blob=None):
+    lib = load()
+    ws = C.c_size_t()
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
+    _check(lib.splat_lod_highlight_plan(int(node_capacity), int(max_points), int(max_highlighted), C.byref(camc),
+                                        C.byref(sp), C.byref(ws)), "splat_lod_highlight_plan")
+    return int(ws.value)
+
+
+def highlight_flags(tree: Tree, bits, n_bits: int):
+    """One flag bit per stored point of the tree (device uint32 words): set when
+    the point's id is in the id bitset `bits` of n_bits bits."""
+    import torch
+    lib = load()
+    flags = torch.zeros(2 * ((tree.point_capacity + 63) // 64), dtype=torch.int32,
+                        device=tree.counts.device).view(torch.uint32)
+    _check(lib.lod_highlight_flags(C.byref(tree.c()), _ptr(bits), int(n_bits), _ptr(flags), _stream()),
+           "lod_highlight_flags")
+    return flags
+
+
+def splat_lod_highlight(tree: Tree, node_ids, n_ids, max_points: int, cam: Camera, flags, max_highlighted: int,
+                        sigma=1.0, radius_sigmas=3.0, workspace=None, out=None, out_hl=None, blob=None):
+    """(image, highlight image): the LOD render and the same render of the drawn
+    points whose stored-point flag is set (`highlight_flags`), at most max_highlighted."""
+    import torch
+    lib = load()
+    dev = tree.counts.device
+    ws = splat_lod_highlight_workspace_bytes(tree.node_capacity, max_points, max_highlighted, cam, sigma,
+                                             radius_sigmas, blob)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    hl = out_hl if out_hl is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
+    _check(lib.splat_render_lod_highlight(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points),
+                                          C.byref(camc), C.byref(sp), _ptr(flags), int(max_highlighted),
+                                          _ptr(workspace), workspace.numel(), _ptr(img), _ptr(hl), _stream()),
+           "splat_render_lod_highlight")
+    return img, hl
+
+
+def splat_interp(A, B, t: float, cam: Camera, sigma=1.0, radius_sigmas=3.0, blob=None, hA=None, hB=None,
+                 cA=None, cB=None, workspace=None):
+    """The frame at time t between snapshots A and B (each (x, y, z, m) device
+    float32 tensors of the same particles); optional per-particle world radii
+    and colours.  Returns the image, or (image, colour image) with colours."""
+    import torch
+    lib = load()
+    dev = A[0].device
+    N = int(A[0].numel())
+    ws = splat_workspace_bytes(N, cam, sigma, radius_sigmas, blob)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+    fa = FrameC(*[_ptr(a) for a in (*A, hA, cA)])
+    fb = FrameC(*[_ptr(b) for b in (*B, hB, cB)])
+    img = torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
+    cimg = torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev) if cA is not None else None
+    camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
+    _check(lib.splat_render_interp(C.byref(fa), C.byref(fb), N, float(t), C.byref(camc), C.byref(sp),
+                                   _ptr(workspace), workspace.numel(), _ptr(img), _ptr(cimg), _stream()),
+           "splat_render_interp")
+    return (img, cimg) if cimg is not None else img
+
+
+def encode_motion(tree: Tree, xB, yB, zB, snap_offsets=None):
+    """Motion codes (dqx, dqy, dqz device int16 [point capacity]) and the
+    saturated-component count (device uint64 [1])."""
+    import torch
+    lib = load()
+    dev = tree.counts.device
+    dq = [torch.zeros(tree.point_capacity, dtype=torch.int16, device=dev) for _ in range(3)]
+    sat = torch.zeros(1, dtype=torch.uint64, device=dev)
+    _check(lib.lod_encode_motion(C.byref(tree.c()), _ptr(xB), _ptr(yB), _ptr(zB), _ptr(snap_offsets),
+                                 *[_ptr(a) for a in dq], _ptr(sat), _stream()), "lod_encode_motion")
+    return (*dq, sat)
+
+
+def splat_lod_motion(tree: Tree, node_ids, n_ids, max_points: int, motion, t: float, cam: Camera, sigma=1.0,
+                     radius_sigmas=3.0, workspace=None, out=None, blob=None):
+    """The LOD render at frame time t: stored points moved along their motion codes."""
     import torch
     lib = load()
     dev = tree.counts.device
@@ -533,13 +624,12 @@ def splat_lod_highlight(tree: Tree, node_ids, n_ids, max_points: int, cam: Camer
     if workspace is None or workspace.numel() < ws:
         workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
     img = out if out is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
-    hl = out_hl if out_hl is not None else torch.empty((cam.H, cam.W), dtype=torch.float32, device=dev)
     camc, sp = cam.c(), _sp(sigma, radius_sigmas, blob)
-    _check(lib.splat_render_lod_highlight(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points),
-                                          C.byref(camc), C.byref(sp), _ptr(bits), int(n_bits), _ptr(workspace),
-                                          workspace.numel(), _ptr(img), _ptr(hl), _stream()),
-           "splat_render_lod_highlight")
-    return img, hl
+    _check(lib.splat_render_lod_motion(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points),
+                                       *[_ptr(a) for a in motion[:3]], float(t), C.byref(camc), C.byref(sp),
+                                       _ptr(workspace), workspace.numel(), _ptr(img), _stream()),
+           "splat_render_lod_motion")
+    return img
 
 
 def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas=3.0, blob=None):

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "Snapshot", "finish", "uniform", "plummer_mix", "nfw_mix", "soneira_peebles",
     "config1", "config2", "config3", "config5_sizes", "config5_snapshot",
-    "small_clustered",
+    "small_clustered", "Attributes", "evolve",
 ]
 
 _ONE_MINUS = np.float32(1.0 - 2.0 ** -24)
@@ -203,3 +203,48 @@ def config5_sizes(n_snap: int = 128, lo: float = 5e5, hi: float = 8e6) -> np.nda
 
 def config5_snapshot(s: int, size: int) -> Snapshot:
     return soneira_peebles(int(size), 5000 + s)
+
+
+# --- a second, ID-matched snapshot (time interpolation) -----------------------
+
+@dataclass
+class Attributes:
+    """Per-particle world radius h and colour value c of one snapshot."""
+    h: np.ndarray   # float32 [N]
+    c: np.ndarray   # float32 [N], in [0, 1]
+
+
+def evolve(s: Snapshot, seed: int, step: float = 0.01, modes: int = 6, h0: float = 0.002):
+    """The next snapshot of the same particles (same ids, same masses):
+    positions moved by a smooth random flow, displacement
+    step * sum_k a_k sin(2 pi k.x + phi_k) per axis (unit wave vectors k with
+    integer components up to 3, amplitudes a_k ~ N(0, 1/modes)), plus
+    isotropic noise of 0.05 step; clipped into [0, 1 - 2^-24].  Also per-particle
+    world radii (h0 (1 + U) at A, times 1 + 0.4 (U' - 1/2) at B) and colours
+    (speed of the flow at each position, scaled to [0, 1]).
+    Returns (snapshot B, attributes A, attributes B)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks = rng.integers(-3, 4, (modes, 3)).astype(np.float64)
+    ks[np.all(ks == 0, axis=1)] = (1.0, 0.0, 0.0)
+    amp = rng.standard_normal((modes, 3)) / math.sqrt(modes)
+    ph = rng.random(modes) * 2 * math.pi
+
+    def flow(x, y, z):
+        v = np.zeros((x.shape[0], 3))
+        for k in range(modes):
+            arg = 2 * math.pi * (ks[k, 0] * x + ks[k, 1] * y + ks[k, 2] * z) + ph[k]
+            v += np.sin(arg)[:, None] * amp[k][None, :]
+        return v
+
+    xa, ya, za = (a.astype(np.float64) for a in (s.x, s.y, s.z))
+    va = flow(xa, ya, za)
+    d = step * va + 0.05 * step * rng.standard_normal((s.n, 3))
+    hi = 1.0 - 2.0 ** -24
+    nb = [np.clip(a + d[:, i], 0.0, hi).astype(np.float32) for i, a in enumerate((xa, ya, za))]
+    vb = flow(*(b.astype(np.float64) for b in nb))
+    sa = np.sqrt((va * va).sum(axis=1)); sb = np.sqrt((vb * vb).sum(axis=1))
+    top = max(float(sa.max(initial=0.0)), float(sb.max(initial=0.0)), 1e-30)
+    ha = (h0 * (1.0 + rng.random(s.n))).astype(np.float32)
+    hb = (ha.astype(np.float64) * (1.0 + 0.4 * (rng.random(s.n) - 0.5))).astype(np.float32)
+    B = Snapshot(nb[0], nb[1], nb[2], s.m.copy())
+    return B, Attributes(ha, (sa / top).astype(np.float32)), Attributes(hb, (sb / top).astype(np.float32))

@@ -173,9 +173,12 @@ def _tree(s, n, D, seed=0):
 
 @pytest.mark.parametrize("blob", ["gauss", "cubic"])
 def test_lod_highlight_matches_oracle(blob):
-    """ID highlighting in the LOD render: the first image equals the plain LOD
-    render bit for bit; the highlight image equals the oracle's render of the
-    cut's decoded points whose id is in the set (ids past n_bits never are)."""
+    """ID highlighting in the LOD render: the per-point flags are the
+    membership of each stored point's id (ids past n_bits never are); the
+    first image equals the plain LOD render bit for bit; the highlight image
+    equals the oracle's render of the cut's decoded points whose id is in the
+    set, twice in a row bit for bit; a cap below the selected count sets the
+    capacity status bit."""
     import torch
     s = synth.small_clustered(60000, 406)
     n = 300
@@ -186,11 +189,17 @@ def test_lod_highlight_matches_oracle(blob):
     bits = lib.highlight_bits(chosen, n_bits)
     member = np.zeros(s.n, dtype=bool)
     member[chosen[chosen < n_bits]] = True
+    flags = lib.highlight_flags(tree, bits, n_bits)
+    # the flags: bit s set iff stored point s has a selected id
+    fl = lib._to_numpy(flags).astype(np.uint64)
+    S = ref.n_points
+    got_bits = ((fl[np.arange(S) >> 5] >> (np.arange(S) & 31).astype(np.uint64)) & np.uint64(1)).astype(bool)
+    assert np.array_equal(got_bits, member[ref.pt_id.astype(np.int64)])
     b = lib.Blob.cubic(h_px=1.7) if blob == "cubic" else None
     for name, cam, ocam in _cams(160, 160)[:3]:
         ids, nsel = lib.select_nodes(tree, cam, 1.0, n)
         want_ids = ocut.select(ref, ocam, 1.0, n)
-        img, hl = lib.splat_lod_highlight(tree, ids, nsel, tree.point_capacity, cam, bits, n_bits, blob=b)
+        img, hl = lib.splat_lod_highlight(tree, ids, nsel, tree.point_capacity, cam, flags, len(chosen), blob=b)
         plain = lib.splat_lod(tree, ids, nsel, tree.point_capacity, cam, blob=b)
         assert torch.equal(img.view(torch.int32), plain.view(torch.int32)), (blob, name)
         px, py, pz, pm = olod.decoded_points(ref, want_ids)
@@ -206,3 +215,12 @@ def test_lod_highlight_matches_oracle(blob):
               flush=True)
         assert zeros_ok and err <= TOL, (blob, name, err)
         assert on.any()
+        _, hl2 = lib.splat_lod_highlight(tree, ids, nsel, tree.point_capacity, cam, flags, len(chosen), blob=b)
+        assert torch.equal(hl.view(torch.int32), hl2.view(torch.int32))
+    # a cap below the number of highlighted drawn points: flagged, not overrun
+    k = int(on.sum())
+    assert k > 2
+    lib.splat_lod_highlight(tree, ids, nsel, tree.point_capacity, cam, flags, k // 2, blob=b)
+    st = int(lib._to_numpy(tree.counts)[2])
+    assert st & lib.STATUS_CAPACITY
+    tree.counts[2] = 0
