@@ -377,6 +377,74 @@ lod_status splat_render_noalloc(const float *x, const float *y, const float *z, 
                                 uint64_t count, const lod_camera *cam, const splat_params *sp,
                                 float *image, lod_stream_t stream);
 
+/* ---- block store and view-dependent streaming (the IO paragraphs: only
+ * the data a view needs is loaded, from a spatially indexed store, at the
+ * rate of an ordinary link; the CPU decides which blocks to load and draw) */
+
+/* Write a built tree to the file `path` (host call; synchronises `stream`).
+ * Format (little endian): a 64-byte header (magic "LODSTOR1", version 1,
+ * n, node and point counts, section offsets), the node table (prefix,
+ * depth, parent, first_child, child_mask, part_begin, part_count, pt_count,
+ * node_mass, block offset; each array 8-byte aligned), then one block per
+ * node in node order: pt_id u32[k], qx, qy, qz u16[k], pt_mass f32[k]
+ * (14 bytes per stored point).  n: the build's points per node.
+ * LOD_EINVAL when the tree's status word is not 0 or the file cannot be
+ * written. */
+lod_status lod_store_save(const lod_tree *tree, uint32_t n, const char *path, lod_stream_t stream);
+
+/* Node count, stored point count and n of a store file. */
+lod_status lod_store_read_info(const char *path, uint64_t *n_nodes, uint64_t *n_points, uint32_t *n);
+
+typedef struct lod_streamer lod_streamer;
+
+/* Per-frame report of lod_streamer_frame. */
+typedef struct {
+  uint64_t bytes_loaded;    /* block bytes read and copied this frame */
+  uint32_t nodes_loaded, nodes_evicted, nodes_drawn;
+  uint32_t groups_waiting;  /* candidate groups left for later frames */
+  uint64_t points_drawn;
+  uint64_t resident_nodes;
+  double decide_ms;         /* host: the choice of loads and evictions */
+  double io_ms;             /* host: reading the loaded blocks from the store */
+  double upload_ms;         /* copies to the device and the draw list, synchronised */
+} lod_stream_stats;
+
+/* Open a store for streaming into the caller's device arrays `view` (a
+ * lod_tree: node arrays of at least the store's node count, point arrays of
+ * at least pool_slots * n entries, counts[3]).  The node table is copied
+ * once; the point arrays form a pool of pool_slots slots of n points; the
+ * roots are loaded now and never evicted (LOD_ECAPACITY when they do not
+ * fit).  After each frame, view->pt_begin holds the slot offsets of the
+ * resident nodes, so splat_render_lod(view, draw list) draws the frame.
+ * The streamer allocates pinned host staging, no device memory. */
+lod_status lod_streamer_open(const char *path, uint32_t pool_slots, lod_tree *view, lod_streamer **out);
+
+/* One frame.  The link carries budget_bytes per frame: a credit grows by
+ * that each frame and unused credit carries over, up to budget_bytes plus
+ * one full group (8 n blocks).  From the roots, a visited node is descended
+ * into when the camera wants more detail there (lod_select's test with
+ * tau_px) and all its children are resident; the children of visited nodes
+ * that want more detail form candidate groups, taken by priority (camera
+ * inside the parent's cube, then larger projected spacing of the parent,
+ * then smaller parent index); a group costs the blocks of its non-resident
+ * children and loading stops at the first group that does not fit the
+ * credit.  Slots are freed by evicting resident non-root nodes with no
+ * resident children, not visited this frame and not children of a node
+ * visited this frame that wants more detail, least recently visited first
+ * (ties: larger index first); loading stops when none is left.  The frame
+ * then draws the visit repeated over the new residency: the visited nodes
+ * not descended into, ascending, written to draw_ids (device uint32, at
+ * least the node count) and their number to *n_draw (device uint64).
+ * Loaded and evicted node ids go to the optional host arrays (up to their
+ * caps).  Synchronises `stream` (the staging buffers are reused). */
+lod_status lod_streamer_frame(lod_streamer *s, const lod_camera *cam, float tau_px, uint64_t budget_bytes,
+                              uint32_t *draw_ids, uint64_t *n_draw, lod_stream_stats *stats, uint32_t *loaded_ids,
+                              uint32_t loaded_cap, uint32_t *evicted_ids, uint32_t evicted_cap,
+                              lod_stream_t stream);
+
+/* Close the store and release the streamer's host buffers. */
+lod_status lod_streamer_close(lod_streamer *s);
+
 /* ---- schedule autotuning ------------------------------------------------ */
 
 /* Time lod_build on this input for each candidate schedule (mode 1 and 2,

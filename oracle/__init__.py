@@ -29,6 +29,7 @@ Modules: ``philox`` (counter-based generator), ``lod`` (the build),
 ``splat`` (render and its adjoint), ``cut`` (view-dependent node choice),
 ``refine`` (one step of the gradient refinement of a node), ``cubic`` (the
 radial cubic blob and the attribute channel), ``interp`` (time interpolation
-between snapshots and the motion codes of stored points).
+between snapshots and the motion codes of stored points), ``stream`` (block
+store loading policy under a byte budget).
 """
-from . import philox, lod, splat, cut, refine, cubic, interp  # noqa: F401
+from . import philox, lod, splat, cut, refine, cubic, interp, stream  # noqa: F401

@@ -25,6 +25,7 @@ EXPORTS = [
     "lod_decode_plan", "lod_decode", "lod_autotune", "splat_render_noalloc",
     "splat_render_aux", "lod_highlight_flags", "splat_lod_highlight_plan", "splat_render_lod_highlight",
     "splat_render_interp", "lod_encode_motion", "splat_render_lod_motion",
+    "lod_store_save", "lod_store_read_info", "lod_streamer_open", "lod_streamer_frame", "lod_streamer_close",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -61,6 +62,13 @@ class CameraC(C.Structure):
 
 class FrameC(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "m", "h", "c")]
+
+
+class StreamStats(C.Structure):
+    _fields_ = [("bytes_loaded", C.c_uint64), ("nodes_loaded", C.c_uint32), ("nodes_evicted", C.c_uint32),
+                ("nodes_drawn", C.c_uint32), ("groups_waiting", C.c_uint32), ("points_drawn", C.c_uint64),
+                ("resident_nodes", C.c_uint64), ("decide_ms", C.c_double), ("io_ms", C.c_double),
+                ("upload_ms", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -114,6 +122,13 @@ def load():
     lib.lod_encode_motion.argtypes = [C.POINTER(TreeC), P, P, P, P, P, P, P, P, P]
     lib.splat_render_lod_motion.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, C.c_float,
                                             C.POINTER(CameraC), C.POINTER(SplatParamsC), P, C.c_size_t, P, P]
+    lib.lod_store_save.argtypes = [C.POINTER(TreeC), C.c_uint32, C.c_char_p, P]
+    lib.lod_store_read_info.argtypes = [C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint32)]
+    lib.lod_streamer_open.argtypes = [C.c_char_p, C.c_uint32, C.POINTER(TreeC), C.POINTER(C.c_void_p)]
+    lib.lod_streamer_frame.argtypes = [P, C.POINTER(CameraC), C.c_float, C.c_uint64, P, P, C.POINTER(StreamStats),
+                                       C.POINTER(C.c_uint32), C.c_uint32, C.POINTER(C.c_uint32), C.c_uint32, P]
+    lib.lod_streamer_close.argtypes = [P]
     lib.lod_decode_plan.argtypes = [C.c_uint64, C.POINTER(C.c_size_t)]
     lib.lod_decode.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, P, P, P, C.c_size_t, P]
     lib.lod_autotune.argtypes = [C.POINTER(Input), C.POINTER(Params), P, C.c_size_t, C.POINTER(TreeC),
@@ -660,3 +675,62 @@ def decode_nodes(tree: Tree, node_ids, n_ids, max_points: int):
     _check(lib.lod_decode(C.byref(tree.c()), _ptr(node_ids), _ptr(n_ids), int(max_points), *[_ptr(t) for t in out],
                           _ptr(cnt), _ptr(work), ws.value, _stream()), "lod_decode")
     return (*out, cnt)
+
+
+# ---------------------------------------------------------------------------
+# block store and streaming
+
+def store_save(tree: Tree, n: int, path: str):
+    """Write a built tree to a block store file (synchronises)."""
+    _check(load().lod_store_save(C.byref(tree.c()), int(n), path.encode(), _stream()), "lod_store_save")
+
+
+def store_info(path: str):
+    """(node count, stored point count, n) of a store file."""
+    nn, npts, n = C.c_uint64(), C.c_uint64(), C.c_uint32()
+    _check(load().lod_store_read_info(path.encode(), C.byref(nn), C.byref(npts), C.byref(n)), "lod_store_read_info")
+    return int(nn.value), int(npts.value), int(n.value)
+
+
+class Streamer:
+    """View-dependent streaming of a block store into a device pool of
+    `slots` node slots; `frame()` returns the device draw list of the frame."""
+
+    def __init__(self, path: str, slots: int, device="cuda"):
+        import torch
+        nn, npts, n = store_info(path)
+        self.n = n
+        self.view = alloc_tree(nn, slots * n, device)
+        self.draw_ids = torch.empty(max(nn, 1), dtype=torch.uint32, device=device)
+        self.n_draw = torch.zeros(1, dtype=torch.uint64, device=device)
+        self._h = C.c_void_p()
+        _check(load().lod_streamer_open(path.encode(), int(slots), C.byref(self.view.c()), C.byref(self._h)),
+               "lod_streamer_open")
+        self.n_nodes = nn
+
+    def frame(self, cam: Camera, tau_px: float, budget_bytes: int, want_ids: bool = False):
+        """One frame; returns (draw ids device tensor, count tensor, stats dict[, loaded, evicted])."""
+        st = StreamStats()
+        cap = self.n_nodes
+        la = (C.c_uint32 * max(cap, 1))()
+        ea = (C.c_uint32 * max(cap, 1))()
+        camc = cam.c()
+        _check(load().lod_streamer_frame(self._h, C.byref(camc), float(tau_px), int(budget_bytes), _ptr(self.draw_ids),
+                                         _ptr(self.n_draw), C.byref(st), la, cap, ea, cap, _stream()),
+               "lod_streamer_frame")
+        stats = {k: getattr(st, k) for k, _ in StreamStats._fields_}
+        if want_ids:
+            return (self.draw_ids, self.n_draw, stats, [la[i] for i in range(min(st.nodes_loaded, cap))],
+                    [ea[i] for i in range(min(st.nodes_evicted, cap))])
+        return self.draw_ids, self.n_draw, stats
+
+    def close(self):
+        if self._h:
+            _check(load().lod_streamer_close(self._h), "lod_streamer_close")
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
