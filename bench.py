@@ -194,6 +194,67 @@ def lod_sweep(tree, full_imgs, cams, taus, n, max_draw, sel_ws, lod_ws, N):
     return rows
 
 
+def stream_leg(tree, N, cfg, dev, frames: int, fps: float, link_mb_s: float, slots: int):
+    """View-dependent streaming of the built tree from a block store file: a
+    camera flies from outside the box towards its densest depth-3 cell while
+    the link carries link_mb_s MB/s at fps frames per second.  Per frame: the
+    bytes loaded and the nodes drawn; every few frames the streamed render's
+    E_log against the fully resident LOD render and against the full render."""
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_0811_2055_amd import lib
+    h = tree.host()
+    path = os.path.join(tempfile.gettempdir(), f"lod_bench_{os.getpid()}.lodstore")
+    t0 = time.perf_counter()
+    lib.store_save(tree, cfg["n"], path)
+    save_s = time.perf_counter() - t0
+    file_mb = os.path.getsize(path) / 1e6
+    budget = int(link_mb_s * 1e6 / fps)
+    st = lib.Streamer(path, slots, dev)
+    dense = np.nonzero(h["depth"] == 3)[0]
+    target_v = int(dense[np.argmax(h["part_count"][dense])])
+    cell = int(h["prefix"][target_v]) & 511
+    c = [0, 0, 0]
+    for k in range(3):
+        for ax in range(3):
+            c[ax] |= ((cell >> (3 * k + ax)) & 1) << k
+    target = tuple((ci + 0.5) / 8 for ci in c)
+    start = (0.5, 0.5, -1.5)
+    W, H = cfg["W"], cfg["H"]
+    full_ws = torch.empty(lib.splat_workspace_bytes(N, lib.Camera.ortho(W, H)), dtype=torch.uint8, device=dev)
+    rows = []
+    loaded_total = 0
+    for f in range(frames):
+        a = f / max(frames - 1, 1)
+        pos = tuple(s0 + a * (t - s0) * 0.9 for s0, t in zip(start, target))
+        cam = lib.Camera.look_at(pos, target, W, H, 60.0, near=1e-4)
+        ids, nd, stats = st.frame(cam, 1.0, budget)
+        loaded_total += stats["bytes_loaded"]
+        row = {"frame": f, "MB": round(stats["bytes_loaded"] / 1e6, 3), "drawn": stats["nodes_drawn"],
+               "waiting": stats["groups_waiting"], "resident": stats["resident_nodes"],
+               "decide_ms": round(stats["decide_ms"], 3), "io_ms": round(stats["io_ms"], 3)}
+        if f % 10 == 9 or f == frames - 1:
+            img = lib.splat_lod(st.view, ids, nd, slots * cfg["n"], cam)
+            rids, rn = lib.select_nodes(tree, cam, 1.0, cfg["n"])
+            lod = lib.splat_lod(tree, rids, rn, N, cam)
+            full = lib.splat(*tree._src, cam, workspace=full_ws)
+            row["E_log_vs_resident_lod"] = round(image_errors(img, lod)["E_log"], 5)
+            row["E_log_vs_full"] = round(image_errors(img, full)["E_log"], 5)
+            row["E_log_resident_lod_vs_full"] = round(image_errors(lod, full)["E_log"], 5)
+        rows.append(row)
+        log(f"[bench] stream frame {f}: {row}")
+    st.close()
+    os.remove(path)
+    return {"store_MB": round(file_mb, 1), "store_save_s": round(save_s, 2), "link_MB_s": link_mb_s, "fps": fps,
+            "budget_MB_per_frame": round(budget / 1e6, 3), "pool_slots": slots, "frames": frames,
+            "MB_loaded_total": round(loaded_total / 1e6, 2),
+            "MB_per_frame_max": max(r["MB"] for r in rows),
+            "decide_ms_mean": round(float(np.mean([r["decide_ms"] for r in rows])), 3),
+            "io_ms_mean": round(float(np.mean([r["io_ms"] for r in rows])), 3),
+            "checkpoints": [r for r in rows if "E_log_vs_resident_lod" in r]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +276,10 @@ def main():
     ap.add_argument("--taus", default="1,2,4,8", help="cut thresholds (px) of the LOD-vs-full sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter calibration)")
+    ap.add_argument("--stream", action="store_true",
+                    help="also stream the built tree from a block store file along a camera path")
+    ap.add_argument("--stream-frames", type=int, default=60)
+    ap.add_argument("--stream-slots", type=int, default=3000)
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="only run this many plain steps (for profilers) and exit")
     args = ap.parse_args()
@@ -454,6 +519,10 @@ def main():
                                     "level, 2: one persistent launch; default grids, wall time with a "
                                     "synchronisation, median of 5 (mode 0: one run); outputs byte-identical")
         log(f"[bench] build ms by schedule: {by_mode}")
+
+    if args.stream:
+        tree._src = (x, y, z, m)
+        extra["streaming"] = stream_leg(tree, N, cfg, dev, args.stream_frames, 10.0, 100.0, args.stream_slots)
 
     splat_ms = sum(t for k, (c, t) in per_step.items() if k not in build_kernels)
     out = {

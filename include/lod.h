@@ -331,6 +331,16 @@ lod_status splat_render_lod_motion(const lod_tree *tree, const uint32_t *node_id
                                    float t, const lod_camera *cam, const splat_params *sp, void *workspace,
                                    size_t workspace_bytes, float *image, lod_stream_t stream);
 
+/* Replace the first `count` stored points of node `node` (count at most its
+ * pt_count; a refined node keeps its point count) with positions x, y, z and
+ * masses m (device float32 [count]): each coordinate is coded as
+ * min(floor(a 2^(d+16)) - (c << 16), 65535) relative to the node's cell, as
+ * the build codes it (quantisation paragraph); a position outside the cell
+ * sets LOD_STATUS_DOMAIN and is clamped to it.  For writing refined points
+ * back into a tree. */
+lod_status lod_set_node_points(const lod_tree *tree, uint32_t node, const float *x, const float *y, const float *z,
+                               const float *m, uint32_t count, lod_stream_t stream);
+
 /* Workspace bytes for lod_decode on a tree of node_capacity nodes. */
 lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes);
 

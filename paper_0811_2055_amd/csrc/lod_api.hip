@@ -306,6 +306,13 @@ lod_status splat_render_lod_motion(const lod_tree *tree, const uint32_t *node_id
                                        (hipStream_t)stream);
 }
 
+lod_status lod_set_node_points(const lod_tree *tree, uint32_t node, const float *x, const float *y, const float *z,
+                               const float *m, uint32_t count, lod_stream_t stream) {
+  if (!tree_arrays_ok(tree) || (count && (!x || !y || !z || !m))) return LOD_EINVAL;
+  if ((uint64_t)node >= tree->node_capacity) return LOD_EINVAL;
+  return lodh::launch_set_points(*tree, node, x, y, z, m, count, (hipStream_t)stream);
+}
+
 lod_status lod_decode_plan(uint64_t node_capacity, size_t *workspace_bytes) {
   if (!workspace_bytes) return LOD_EINVAL;
   *workspace_bytes = lodh::decode_workspace(node_capacity);

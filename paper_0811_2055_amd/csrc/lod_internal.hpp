@@ -103,6 +103,8 @@ lod_status launch_splat_lod_motion(const lod_tree &tree, const uint32_t *node_id
                                    const LodDrawLayout &D, const int16_t *dqx, const int16_t *dqy,
                                    const int16_t *dqz, float t, const lod_camera &cam, const splat_params &sp,
                                    const SplatLayout &L, float *image, hipStream_t st);
+lod_status launch_set_points(const lod_tree &tree, uint32_t node, const float *x, const float *y, const float *z,
+                             const float *m, uint32_t count, hipStream_t st);
 size_t decode_workspace(uint64_t node_capacity);
 lod_status launch_decode(const lod_tree &tree, const uint32_t *node_ids, const uint64_t *n_ids, uint64_t max_points,
                          float *x, float *y, float *z, float *m, uint64_t *n_points, void *ws, hipStream_t st);

@@ -1165,6 +1165,37 @@ __global__ void k_encode_motion(const lod_tree t, const float *__restrict__ xb, 
   if (sat_count) atomicAdd((unsigned long long *)saturated, (unsigned long long)sat_count);
 }
 
+// --- writing a node's points back (refinement) ---------------------------------
+
+// Stored points of node v replaced by count positions and masses (count <=
+// the node's pt_count): codes q = min(floor(a 2^(d+16)) - (c << 16), 65535)
+// relative to the node's cell (positions outside the cell set the domain
+// status bit and are clamped), masses as given.
+__global__ void k_set_points(const lod_tree t, uint32_t v, const float *__restrict__ x, const float *__restrict__ y,
+                             const float *__restrict__ z, const float *__restrict__ m, uint32_t count) {
+  if ((uint64_t)v >= t.counts[0]) return;
+  const int d = t.depth[v];
+  const uint64_t pfx = t.prefix[v];
+  const uint32_t cell = d ? (uint32_t)(pfx & ((1ull << (3 * d)) - 1)) : 0u;
+  const uint32_t c3[3] = {compact3(cell), compact3(cell >> 1), compact3(cell >> 2)};
+  const uint64_t pb = t.pt_begin[v];
+  const uint32_t k = min(count, t.pt_count[v]);
+  const float scale = ldexpf(1.0f, d + 16);
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
+    const float a[3] = {x[j], y[j], z[j]};
+    uint16_t q[3];
+    bool out = false;
+    for (int ax = 0; ax < 3; ++ax) {
+      const int64_t Q = (int64_t)floorf(a[ax] * scale) - ((int64_t)c3[ax] << 16);
+      out |= !(Q >= 0 && Q <= 65535 + 1) || !(a[ax] >= 0.0f);
+      q[ax] = (uint16_t)max((int64_t)0, min((int64_t)65535, Q));
+    }
+    if (out) atomicOr((unsigned long long *)&t.counts[2], (unsigned long long)LOD_STATUS_DOMAIN);
+    t.qx[pb + j] = q[0]; t.qy[pb + j] = q[1]; t.qz[pb + j] = q[2];
+    t.pt_mass[pb + j] = m[j];
+  }
+}
+
 // --- LOD decode ----------------------------------------------------------------
 
 __global__ void k_lod_counts(const lod_tree t, const uint32_t *__restrict__ ids, const uint64_t *__restrict__ n_ids,
@@ -1476,6 +1507,14 @@ lod_status launch_splat_lod_motion(const lod_tree &tree, const uint32_t *node_id
   src.dqx = dqx; src.dqy = dqy; src.dqz = dqz;
   src.t_frame = t;
   return splat_any(src, true, cam, sp, W + D.total, L, image, nullptr, tree.counts + 2, st);
+}
+
+lod_status launch_set_points(const lod_tree &tree, uint32_t node, const float *x, const float *y, const float *z,
+                             const float *m, uint32_t count, hipStream_t st) {
+  if (!count) return LOD_OK;
+  const unsigned g = (unsigned)std::min<uint64_t>(1024, (count + 255) / 256);
+  LOD_LAUNCH(k_set_points, dim3(g), dim3(256), 0, st, tree, node, x, y, z, m, count);
+  return hipGetLastError() == hipSuccess ? LOD_OK : LOD_EDEVICE;
 }
 
 lod_status launch_splat_backward(const float *x, const float *y, const float *z, const float *m, uint64_t count,

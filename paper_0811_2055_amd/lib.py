@@ -26,6 +26,7 @@ EXPORTS = [
     "splat_render_aux", "lod_highlight_flags", "splat_lod_highlight_plan", "splat_render_lod_highlight",
     "splat_render_interp", "lod_encode_motion", "splat_render_lod_motion",
     "lod_store_save", "lod_store_read_info", "lod_streamer_open", "lod_streamer_frame", "lod_streamer_close",
+    "lod_set_node_points",
     "lod_workspace_view", "lod_trace_begin", "lod_trace_end", "lod_status_string", "lod_version",
 ]
 
@@ -122,6 +123,7 @@ def load():
     lib.lod_encode_motion.argtypes = [C.POINTER(TreeC), P, P, P, P, P, P, P, P, P]
     lib.splat_render_lod_motion.argtypes = [C.POINTER(TreeC), P, P, C.c_uint64, P, P, P, C.c_float,
                                             C.POINTER(CameraC), C.POINTER(SplatParamsC), P, C.c_size_t, P, P]
+    lib.lod_set_node_points.argtypes = [C.POINTER(TreeC), C.c_uint32, P, P, P, P, C.c_uint32, P]
     lib.lod_store_save.argtypes = [C.POINTER(TreeC), C.c_uint32, C.c_char_p, P]
     lib.lod_store_read_info.argtypes = [C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                         C.POINTER(C.c_uint32)]
@@ -660,6 +662,12 @@ def splat_backward(x, y, z, m, grad_image, cam: Camera, sigma=1.0, radius_sigmas
     _check(lib.splat_render_backward(_ptr(x), _ptr(y), _ptr(z), _ptr(m), N, C.byref(camc), C.byref(sp), _ptr(g),
                                      _ptr(gm), _ptr(gx), _ptr(gy), _ptr(gz), _stream()), "splat_render_backward")
     return gm, gx, gy, gz
+
+
+def set_node_points(tree: Tree, node: int, x, y, z, m):
+    """Write positions and masses (device float32) back as the node's stored points."""
+    _check(load().lod_set_node_points(C.byref(tree.c()), int(node), _ptr(x), _ptr(y), _ptr(z), _ptr(m),
+                                      int(x.numel()), _stream()), "lod_set_node_points")
 
 
 def decode_nodes(tree: Tree, node_ids, n_ids, max_points: int):

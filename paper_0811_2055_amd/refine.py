@@ -154,15 +154,35 @@ def refine_node(px, py, pz, pm, full, lo, side: float, node_mass: float, train_c
     return RefineResult(before, after, first, last, steps, secs), (x, y, z, m)
 
 
+def exterior_views(side: float, n: int, count: int, seed: int, W: int = 1024, H: int = 1024, spacing: float = 0.75,
+                   fov_deg: float = 60.0):
+    """Cameras on seeded random directions around the box centre at the distance
+    where a node of this side has the given projected point spacing, looking at
+    the centre (the cut then draws nodes of that side there)."""
+    rng = np.random.default_rng(seed)
+    F = (W / 2.0) / math.tan(math.radians(fov_deg) / 2.0)
+    dist = F * side / (n ** (1.0 / 3.0) * spacing)
+    cams = []
+    for _ in range(count):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        pos = tuple(float(0.5 + dist * e) for e in d)
+        up = (0.0, 1.0, 0.0) if abs(d[1]) < 0.9 else (1.0, 0.0, 0.0)
+        cams.append(lib.Camera.look_at(pos, (0.5, 0.5, 0.5), W, H, fov_deg, up_hint=up, near=1e-4))
+    return cams
+
+
 def main(argv=None):
-    """Refine the first K depth-3 internal nodes of the NFW 16.7M-particle tree
-    (n = 16000, max depth 8) against their full particle sets; prints JSON."""
+    """Refine the depth-3 internal nodes of the NFW 16.7M-particle tree (n =
+    16000, max depth 8) against their full particle sets, write the refined
+    points back into the tree, and compare the plain and the refined tree's
+    LOD renders with the full render in the same views; prints JSON lines."""
     import argparse
     import json
     import os
     import sys
     ap = argparse.ArgumentParser()
-    ap.add_argument("--nodes", type=int, default=4)
+    ap.add_argument("--nodes", type=int, default=0, help="refine only the first K depth-3 nodes (0: all)")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--size", type=int, default=1024)
@@ -176,42 +196,81 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     d = [torch.from_numpy(a).to(dev) for a in (snap.x, snap.y, snap.z, snap.m)]
     n = 16000
+    # build throughput: one launch per node (plain) against one launch per level
+    build_ms = {}
+    for mode in (0, 1):
+        bm = lib.Builder(snap.n, lib.BuildParams(n=n, max_depth=8, seed=0, mode=mode), dev)
+        bm.build(*d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bm.build(*d)
+        torch.cuda.synchronize()
+        build_ms[mode] = (time.perf_counter() - t0) * 1e3
+        del bm
     b = lib.Builder(snap.n, lib.BuildParams(n=n, max_depth=8, seed=0), dev)
     tree = b.build(*d)
     h = tree.host()
     order = b.view(1, torch.uint32).view(torch.int32).long()
     cand = [v for v in range(h["n_nodes"]) if h["depth"][v] == 3 and h["first_child"][v] != lib.NONE]
+    if args.nodes:
+        cand = cand[:args.nodes]
+    # the plain tree's LOD renders against the full render, before any write-back
+    side3 = 2.0 ** -3
+    cams = exterior_views(side3, n, 8, seed=200, W=args.size, H=args.size)
+    fulls = [lib.splat(*d, c) for c in cams]
+
+    def lod_errors():
+        errs = []
+        for c, f in zip(cams, fulls):
+            ids, nsel = lib.select_nodes(tree, c, 1.0, n)
+            img = lib.splat_lod(tree, ids, nsel, snap.n, c)
+            errs.append(e_log(img, f))
+        return errs
+    plain = lod_errors()
+    print(json.dumps({"plain_tree_E_log": plain, "depth3_nodes": len(cand)}), flush=True)
     results = []
-    for v in cand[:args.nodes]:
+    t_all = time.perf_counter()
+    for v in cand:
         cell = int(h["prefix"][v]) & ((1 << 9) - 1)
         cx = cy = cz = 0
         for k in range(3):
             cx |= ((cell >> (3 * k)) & 1) << k
             cy |= ((cell >> (3 * k + 1)) & 1) << k
             cz |= ((cell >> (3 * k + 2)) & 1) << k
-        side = 2.0 ** -3
-        lo = [cx * side, cy * side, cz * side]
+        lo = [cx * side3, cy * side3, cz * side3]
         ids = torch.tensor([v], dtype=torch.int32, device=dev).view(torch.uint32)
         nid = torch.tensor([1], dtype=torch.int64, device=dev).view(torch.uint64)
         px, py, pz, pm, _ = lib.decode_nodes(tree, ids, nid, n)
         pb, pc = int(h["part_begin"][v]), int(h["part_count"][v])
         members = order[pb:pb + pc]
         full = [a[members].contiguous() for a in d]
-        centre = [l + side / 2 for l in lo]
-        train = node_views(centre, side, n, args.views, seed=0, W=args.size, H=args.size)
-        test = node_views(centre, side, n, args.views, seed=100, W=args.size, H=args.size)
-        res, _ = refine_node(px, py, pz, pm, full, lo, side, float(h["node_mass"][v]), train, test,
-                             steps=args.steps)
+        centre = [l + side3 / 2 for l in lo]
+        train = node_views(centre, side3, n, args.views, seed=0, W=args.size, H=args.size)
+        test = node_views(centre, side3, n, args.views, seed=100, W=args.size, H=args.size)
+        res, (x, y, z, m) = refine_node(px, py, pz, pm, full, lo, side3, float(h["node_mass"][v]), train, test,
+                                        steps=args.steps)
+        lib.set_node_points(tree, v, x, y, z, m)
         rec = {"node": v, "particles": pc, "points": n, **res.__dict__}
         results.append(rec)
         print(json.dumps(rec), flush=True)
-    eb = float(np.mean([r["e_log_before"] for r in results]))
-    ea = float(np.mean([r["e_log_after"] for r in results]))
-    secs = float(np.mean([r["seconds"] for r in results]))
-    print(json.dumps({"summary": "depth-3 node refinement", "nodes": len(results),
-                      "E_log_heldout_before": eb, "E_log_heldout_after": ea,
-                      "seconds_per_node": secs, "steps": args.steps, "views": args.views,
-                      "image": f"{args.size}x{args.size}"}), flush=True)
+    secs_all = time.perf_counter() - t_all
+    st = tree.host()["status"]
+    refined = lod_errors()
+    eb = float(np.mean([r["e_log_before"] for r in results])) if results else 0.0
+    ea = float(np.mean([r["e_log_after"] for r in results])) if results else 0.0
+    print(json.dumps({"summary": "depth-3 node refinement, NFW 16,777,216 particles, n=16000, D=8",
+                      "nodes": len(results), "steps": args.steps, "views": args.views,
+                      "image": f"{args.size}x{args.size}",
+                      "E_log_heldout_node_views_before": eb, "E_log_heldout_node_views_after": ea,
+                      "seconds_all_nodes": round(secs_all, 2),
+                      "tree_views": "8 exterior perspective views, depth-3 spacing 0.75 px, cut tau 1 px",
+                      "E_log_tree_views_plain": float(np.mean(plain)),
+                      "E_log_tree_views_refined": float(np.mean(refined)),
+                      "E_log_tree_views_plain_each": [round(e, 5) for e in plain],
+                      "E_log_tree_views_refined_each": [round(e, 5) for e in refined],
+                      "build_ms_per_node_schedule": round(build_ms[0], 2),
+                      "build_ms_per_level_schedule": round(build_ms[1], 2),
+                      "status_after_write_back": int(st)}), flush=True)
 
 
 if __name__ == "__main__":

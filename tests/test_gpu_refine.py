@@ -348,3 +348,38 @@ def test_config4_fd_check_nfw_depth3_node():
     print(f"[config4 fd] checked {checked} of 1000 points, loss {float(loss.detach()):.4e}, {time.time() - t0:.1f} s",
           flush=True)
     assert checked >= 900
+
+
+def test_set_node_points_codes_like_the_build():
+    """Writing a node's points back codes them as the build does: decoded points
+    re-code to the same codes (depths up to 5 decode exactly), moved points get
+    the oracle's codes of their new positions, and a point outside the node's
+    cell sets the domain status bit."""
+    import torch
+    s = synth.small_clustered(20000, 85)
+    n, D = 150, 5
+    ref = olod.lod_build(s.x, s.y, s.z, s.m, n=n, D=D, seed=2)
+    tree = lib.build(*to_dev(s), lib.BuildParams(n=n, max_depth=D, seed=2))
+    v = next(i for i in range(ref.n_nodes) if int(ref.depth[i]) == 2 and int(ref.part_count[i]) > n)
+    ids = torch.tensor([v], dtype=torch.int32).cuda().view(torch.uint32)
+    nid = torch.tensor([1], dtype=torch.int64).cuda().view(torch.uint64)
+    x, y, z, m, _ = lib.decode_nodes(tree, ids, nid, n)
+    lib.set_node_points(tree, v, x, y, z, m)
+    h = tree.host()
+    pb = int(ref.pt_begin[v])
+    for k in ("qx", "qy", "qz"):
+        assert np.array_equal(h[k][pb:pb + n], getattr(ref, k)[pb:pb + n])
+    (cx, cy, cz), d = olod.node_origin(ref, v)
+    side = 2.0 ** -d
+    rng = np.random.default_rng(3)
+    nx, ny, nz = ((c * side + side * rng.random(n)).astype(np.float32) for c in (cx, cy, cz))
+    nm = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    lib.set_node_points(tree, v, *[torch.from_numpy(a).cuda() for a in (nx, ny, nz, nm)])
+    h = tree.host()
+    assert h["status"] == 0
+    for k, a, c in (("qx", nx, cx), ("qy", ny, cy), ("qz", nz, cz)):
+        assert np.array_equal(h[k][pb:pb + n], olod.quantise(a, c, d))
+    assert np.array_equal(h["pt_mass"][pb:pb + n], nm)
+    nx[0] = np.float32(cx * side - 0.01)
+    lib.set_node_points(tree, v, *[torch.from_numpy(a).cuda() for a in (nx, ny, nz, nm)])
+    assert tree.host()["status"] & lib.STATUS_DOMAIN
