@@ -945,6 +945,7 @@ constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
 constexpr int ILP = 8;        // list entries in flight per thread in the candidate passes
 constexpr int SILP = 8;       // candidates per lane per wave step
+constexpr int CILP = 8;       // candidates per lane per step of the compaction pass of list nodes
 constexpr int OILP = 4;       // list entries per thread per step of the output pass
 constexpr int FILP = 2;       // candidates per lane per step of the fused pass of range-only nodes
 constexpr int QCAP = 2048;    // bin-b0 candidates queued in LDS by the collect pass
@@ -954,10 +955,13 @@ static_assert(2 * HT <= KBINS, "the table lives in the histogram's storage");
 __device__ __forceinline__ uint32_t ht_slot(uint32_t p) { return (p * 2654435761u) >> 22; }   // HT = 2^10
 static_assert(HT == 1024, "ht_slot takes the top 10 bits");
 
-// A list entry packs a sorted position (low 32 bits) and its key bin (next 16).
+// A list entry is a sorted position, its key bin and the candidate's density
+// weight and mass (so that the parent's output pass reads them in list order
+// instead of gathering them from the sorted arrays).
 struct SelArgs {
   uint32_t *lpos;             // top-(n+1) lists by selecting rank: sorted positions
   uint16_t *lkb;              // and their key bins (a separate array: the counting passes read only these)
+  uint2 *lwm;                 // and (w, mass bits)
   uint32_t n_minus_1;         // N - 1
   double *mhat;               // float64 mass scratch, one row of n per block
   uint32_t *src;              // source of each list entry, one row of n+1 per block
@@ -1013,22 +1017,23 @@ __device__ __forceinline__ void wave_part(uint32_t L, uint32_t w, uint32_t W, ui
   hi = min(L, lo + P);
 }
 
-// Loads SILP candidates (sorted position, key bin) of a wave step; indices
+// Loads NL candidates (sorted position, key bin) of a wave step; indices
 // are clamped into the part, so every load is issued unconditionally.
+template <int NL>
 __device__ __forceinline__ void load_step(const Segs &g, int k, const SelArgs &sa, const Sorted &s, uint32_t j0,
-                                          uint32_t hi, uint32_t (&pos)[SILP], uint32_t (&kb)[SILP]) {
+                                          uint32_t hi, uint32_t (&pos)[NL], uint32_t (&kb)[NL]) {
   const uint32_t lane = threadIdx.x & (WAVE - 1);
   const uint64_t base = g.base[k];
   if (g.is_list[k]) {
 #pragma unroll
-    for (int u = 0; u < SILP; ++u) {
+    for (int u = 0; u < NL; ++u) {
       const uint64_t i = base + min(j0 + u * WAVE + lane, hi - 1);
       pos[u] = entry_pos(sa, i);
       kb[u] = sa.lkb[i];
     }
   } else {
 #pragma unroll
-    for (int u = 0; u < SILP; ++u) {
+    for (int u = 0; u < NL; ++u) {
       const uint64_t p = base + min(j0 + u * WAVE + lane, hi - 1);
       pos[u] = (uint32_t)p;
       kb[u] = s.kb[p];
@@ -1340,6 +1345,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const bool out_ok = a.counts[1] <= a.point_cap;
   uint32_t *out_pos = sa.lpos + (uint64_t)t.sel_idx[v] * (n + 1);
   uint16_t *out_kb = sa.lkb + (uint64_t)t.sel_idx[v] * (n + 1);
+  uint2 *out_wm = sa.lwm + (uint64_t)t.sel_idx[v] * (n + 1);
   double *mrow = sa.mhat + (uint64_t)blockIdx.x * n;
   uint32_t *srow = sa.src + (uint64_t)blockIdx.x * (n + 1);
   const uint64_t ob = t.pt_begin[v];
@@ -1392,6 +1398,7 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
           if (tk && o <= n) {
             out_pos[o] = pp[u];
             out_kb[o] = (uint16_t)kbv[u];
+            out_wm[o] = make_uint2(wv[u], __float_as_uint(mm[u]));
             if (out_ok && pp[u] != pt) {
               const uint32_t j = o - (pp[u] > pt ? 1u : 0u);
               const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
@@ -1408,11 +1415,11 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
       uint32_t lo, hi;
       wave_part(g.len[k], w, W, lo, hi);
       uint32_t run = pcnt[k * W + w];
-      for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * SILP) {
-        uint32_t pos[SILP], kb[SILP];
-        load_step(g, k, sa, s, j0, hi, pos, kb);
+      for (uint32_t j0 = lo; j0 < hi; j0 += WAVE * CILP) {
+        uint32_t pos[CILP], kb[CILP];
+        load_step<CILP>(g, k, sa, s, j0, hi, pos, kb);
 #pragma unroll
-        for (int u = 0; u < SILP; ++u) {
+        for (int u = 0; u < CILP; ++u) {
           bool tk = j0 + u * WAVE + lane < hi && kb[u] <= b0;
           if (tk && kb[u] == b0) tk = taken_b0(pos[u]);
           const uint64_t bal = __ballot(tk);
@@ -1421,67 +1428,70 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
           if (tk && o <= n) {
             out_pos[o] = pos[u];
             out_kb[o] = (uint16_t)kb[u];
-            // a list entry other than the child's witness is one of the child's
-            // stored points: record where (segment, index among its points)
+            // an entry of a child's list: record where (segment, index in the
+            // child's list), so that the output pass reads it in list order
             uint32_t src = NONE;
-            if (g.is_list[k] && pos[u] != g.cwit[k] && n < (1u << 24)) {
-              const uint32_t jc = j0 + u * WAVE + lane;
-              src = ((uint32_t)k << 24) | (jc - (pos[u] > g.cwit[k] ? 1u : 0u));
-            }
+            if (g.is_list[k] && n < (1u << 24)) src = ((uint32_t)k << 24) | (j0 + u * WAVE + lane);
             srow[o] = src;
           }
         }
       }
     }
     __syncthreads();
-    // output pass over the list (every lane busy): the stored points and their
-    // unscaled float64 masses, kept in this block's scratch row
-    if (out_ok) {
-      for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * OILP) {
-        uint32_t pos[OILP], src[OILP];
+    // output pass over the list (every lane busy): the list's (w, mass) and
+    // the stored points with their unscaled float64 masses, kept in this
+    // block's scratch row
+    for (uint32_t j0 = threadIdx.x; j0 <= n; j0 += BS * OILP) {
+      uint32_t pos[OILP], src[OILP];
 #pragma unroll
-        for (int u = 0; u < OILP; ++u) {
-          const uint32_t jl = min(j0 + u * BS, n);
-          pos[u] = min(out_pos[jl], sa.n_minus_1);
-          src[u] = srow[jl];
-        }
-        // entries from a child's list take id and codes from the child's stored
-        // point (contiguous reads; each code gains the child's octant bit on
-        // top); the others are gathered from the sorted arrays.  Every lane
-        // issues both sets of loads at clamped addresses (the unused set hits
-        // one cached line) and the mass inputs.
-        PointIn q[OILP];
-        uint32_t cid[OILP], cq[OILP][3], wv[OILP];
-        float mm[OILP];
+      for (int u = 0; u < OILP; ++u) {
+        const uint32_t jl = min(j0 + u * BS, n);
+        pos[u] = min(out_pos[jl], sa.n_minus_1);
+        src[u] = srow[jl];
+      }
+      // An entry of a child's list takes (w, mass) from that list and, unless
+      // it is the child's witness, id and codes from the child's stored point
+      // (contiguous reads; each code gains the child's octant bit on top).
+      // The others are gathered from the sorted arrays.  Every lane issues
+      // both sets of loads at clamped addresses (the unused set hits one
+      // cached line).
+      PointIn q[OILP];
+      uint32_t cid[OILP], cq[OILP][3];
+      uint2 wm[OILP], lw[OILP];
+      bool cp[OILP];
 #pragma unroll
-        for (int u = 0; u < OILP; ++u) {
-          const bool fc = src[u] != NONE;
-          const uint32_t kk = fc ? src[u] >> 24 : 0u;
-          const uint64_t ci = fc ? g.cob[kk] + (src[u] & 0xFFFFFFu) : 0u;
-          q[u] = read_point(s, fc ? pt : pos[u]);
-          cid[u] = t.pt_id[ci];
-          cq[u][0] = t.qx[ci]; cq[u][1] = t.qy[ci]; cq[u][2] = t.qz[ci];
-          wv[u] = s.w[pos[u]];
-          mm[u] = s.m[pos[u]];
-        }
+      for (int u = 0; u < OILP; ++u) {
+        const bool fl = src[u] != NONE;
+        const uint32_t kk = fl ? src[u] >> 24 : 0u;
+        const uint32_t ic = src[u] & 0xFFFFFFu;
+        cp[u] = fl && pos[u] != g.cwit[kk];
+        const uint64_t ci = cp[u] ? g.cob[kk] + ic - (pos[u] > g.cwit[kk] ? 1u : 0u) : 0u;
+        q[u] = read_point(s, cp[u] ? pt : pos[u]);
+        cid[u] = t.pt_id[ci];
+        cq[u][0] = t.qx[ci]; cq[u][1] = t.qy[ci]; cq[u][2] = t.qz[ci];
+        lw[u] = sa.lwm[fl ? g.base[kk] + ic : 0u];
+        wm[u] = make_uint2(s.w[fl ? pt : pos[u]], __float_as_uint(s.m[fl ? pt : pos[u]]));
+      }
 #pragma unroll
-        for (int u = 0; u < OILP; ++u) {
-          const uint32_t jl = j0 + u * BS;
-          if (jl > n || pos[u] == pt) continue;
-          const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
-          const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
-          if (src[u] != NONE) {
-            const uint32_t oc = g.coct[src[u] >> 24];
-            t.pt_id[ob + j] = cid[u];
-            t.qx[ob + j] = (uint16_t)((cq[u][0] >> 1) | ((oc & 1u) << 15));
-            t.qy[ob + j] = (uint16_t)((cq[u][1] >> 1) | (((oc >> 1) & 1u) << 15));
-            t.qz[ob + j] = (uint16_t)((cq[u][2] >> 1) | (((oc >> 2) & 1u) << 15));
-          } else {
-            store_point_pos(a, t, q[u], ob + j, d);
-          }
-          mrow[j] = mhat;
-          acc += mhat;
+      for (int u = 0; u < OILP; ++u) {
+        const uint32_t jl = j0 + u * BS;
+        if (jl > n) continue;
+        const uint2 e = src[u] != NONE ? lw[u] : wm[u];
+        out_wm[jl] = e;
+        if (!out_ok || pos[u] == pt) continue;
+        const uint32_t j = jl - (pos[u] > pt ? 1u : 0u);
+        const double mhat = (double)__uint_as_float(e.y) / fmin(1.0, weight_pow(e.x, a.alpha) / tau);
+        if (cp[u]) {
+          const uint32_t oc = g.coct[src[u] >> 24];
+          t.pt_id[ob + j] = cid[u];
+          t.qx[ob + j] = (uint16_t)((cq[u][0] >> 1) | ((oc & 1u) << 15));
+          t.qy[ob + j] = (uint16_t)((cq[u][1] >> 1) | (((oc >> 1) & 1u) << 15));
+          t.qz[ob + j] = (uint16_t)((cq[u][2] >> 1) | (((oc >> 2) & 1u) << 15));
+        } else {
+          store_point_pos(a, t, q[u], ob + j, d);
         }
+        mrow[j] = mhat;
+        acc += mhat;
       }
     }
   }
@@ -1581,14 +1591,47 @@ __global__ void k_bottom_write(BuildArgs a, const uint32_t *__restrict__ flag, c
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl[0] = scan[a.node_cap];   // number of starting nodes
     ctl[1] = 0;                  // ticket
+    ctl[2] = 0;                  // leaf-copy cursor
   }
 }
 
 // mode 2: one persistent launch over every selecting node of every level.
-// A block takes a starting node by ticket (deepest first), reduces it (node mass, selection,
-// output) and then, if it was the last of its parent's selecting children to
-// finish, continues with the parent; otherwise it takes the next ticket.  No
-// block ever waits for another, so the grid drains without spinning.
+// A block takes a starting node by ticket (deepest first), reduces it (node
+// mass, selection, output) and then, if it was the last of its parent's
+// selecting children to finish, continues with the parent; otherwise it takes
+// the next ticket.  Once the tickets are gone a block copies leaves, a chunk
+// of nodes at a time from a shared cursor, until none are left.  No block
+// ever waits for another, so the grid drains without spinning.  (Copying a
+// chunk between tickets, or by only part of the grid, measured slower: it
+// delays the starting nodes, and the climbs near the root gain little from
+// the bandwidth left to them.)
+//
+// The eight XCDs do not share an L2, so a hand-off between blocks needs an
+// agent-scope release by the writer (its lists, mass and witness written back
+// to memory) and an agent-scope acquire by the climber.  A release writes the
+// whole L2 of the XCD back, so a block issues one per node, from one wave,
+// once every wave's stores have completed (a workgroup barrier alone does not
+// wait for them); each wave of a climbing block acquires for itself.  A
+// starting node's inputs come from earlier launches and need no acquire.
+constexpr uint32_t LEAF_CHUNK = 8;   // nodes per leaf-copy grab
+
+// Copies the leaves among the next LEAF_CHUNK nodes of the shared cursor;
+// false once the cursor has passed every node (uniform over the block).
+__device__ __forceinline__ bool copy_leaf_chunk(const BuildArgs &a, const TreeArgs &t, const Sorted &s,
+                                                uint32_t *cursor, uint32_t &sh) {
+  const uint32_t nn = t.lvl[a.D + 1];
+  if (threadIdx.x == 0) sh = atomicAdd(cursor, LEAF_CHUNK);
+  __syncthreads();
+  const uint32_t v0 = sh;
+  __syncthreads();
+  if (v0 >= nn) return false;
+  const bool cap_ok = a.counts[1] <= a.point_cap;
+  const uint32_t v1 = min(nn, v0 + LEAF_CHUNK);
+  for (uint32_t v = v0; v < v1; ++v)
+    if (t.first_child[v] == NONE && t.part_count[v] <= a.n && cap_ok) copy_leaf_points(a, t, s, v);
+  return true;
+}
+
 __global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArgs t, Sorted s, SelArgs sa,
                                                             const uint32_t *__restrict__ bottom,
                                                             uint32_t *__restrict__ ctl) {
@@ -1604,14 +1647,15 @@ __global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArg
     __syncthreads();
     if (v == NONE) break;
     while (true) {
-      // the children's masses and lists, written by other blocks, are visible
-      // (select_node sums the node's mass from them)
-      __threadfence();
-      __syncthreads();
       select_node(a, t, s, sa, v);
-      __threadfence();
+      // publish this node's outputs before its parent can be claimed: every
+      // wave waits for its own stores (vmcnt 0: stores count there on this
+      // architecture), then one wave writes the L2 back
+      __syncthreads();
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt 0; expcnt and lgkmcnt at their maxima
       __syncthreads();
       if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const uint32_t par = t.parent[v];
         uint32_t nxt = NONE;
         if (par != NONE && atomicSub(&t.pend[par], 1u) == 1u) nxt = par;
@@ -1621,7 +1665,14 @@ __global__ __launch_bounds__(1024) void k_select_persistent(BuildArgs a, TreeArg
       v = sh_v;
       __syncthreads();
       if (v == NONE) break;
+      // every child of v has released its outputs: see them (select_node
+      // sums v's mass from its children and reads their lists)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+  }
+  // leaves read only the sorted arrays and the node table, both written by
+  // earlier launches
+  while (copy_leaf_chunk(a, t, s, &ctl[2], sh_v)) {
   }
 }
 
@@ -1706,6 +1757,7 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   // 16-byte reads of the counting passes)
   L.lpos = take(4 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
   L.lkb = take(2 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)) + 16);
+  L.lwm = take(8 * std::max<uint64_t>(1, max_sel * ((uint64_t)p.n + 1)));
   L.sel_rows = (uint32_t)std::min<uint64_t>(4096, N / ((uint64_t)p.n + 1) + n_snap + 1);
   L.mhat = take(8 * (size_t)L.sel_rows * p.n);
   L.src = take(4 * (size_t)L.sel_rows * ((uint64_t)p.n + 1));
@@ -1842,17 +1894,19 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   LOD_LAUNCH(k_ptfinish, dim3(1), dim3(1), 0, st, a, t);
 
   const unsigned node_grid = (unsigned)std::min<uint64_t>(8192, L.node_cap);
-  // the per-level schedule copies the leaves' points inside its selection launches
+  // the per-level and persistent schedules copy the leaves' points inside
+  // their selection launches
   uint32_t *leaf_ctl = p.mode == 1 ? (uint32_t *)(W + L.leafctl) : nullptr;
-  if (leaf_ctl) {
-    fill_u32(leaf_ctl, (uint64_t)L.sel_rows + 2 * (p.max_depth + 1), 0, st);
-    LOD_LAUNCH(k_leaves<false>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
-  } else {
+  if (leaf_ctl) fill_u32(leaf_ctl, (uint64_t)L.sel_rows + 2 * (p.max_depth + 1), 0, st);
+  if (p.mode == 0) {
     LOD_LAUNCH(k_leaves<true>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
+  } else {
+    LOD_LAUNCH(k_leaves<false>, dim3(node_grid), dim3(TB), 0, st, a, t, s);
   }
   if (side && hipStreamWaitEvent(st, side->join, 0) != hipSuccess) return LOD_EDEVICE;
 
-  SelArgs sa{(uint32_t *)(W + L.lpos), (uint16_t *)(W + L.lkb), (uint32_t)(N - 1), (double *)(W + L.mhat),
+  SelArgs sa{(uint32_t *)(W + L.lpos), (uint16_t *)(W + L.lkb), (uint2 *)(W + L.lwm), (uint32_t)(N - 1),
+             (double *)(W + L.mhat),
              (uint32_t *)(W + L.src)};
   const unsigned sel_threads = p.select_threads ? p.select_threads : 1024;
   // one scratch row of float64 masses per block

@@ -16,7 +16,7 @@ struct BuildLayout {
   size_t thist, scan32, scan64;
   size_t w, kb;
   size_t lvl, lsel, cs, sel_idx, sel_node, wit, pend, bflag, bscan, bottom, ctl, leafctl, emit_tot;
-  size_t lpos, lkb;
+  size_t lpos, lkb, lwm;
   uint32_t sel_rows;             // blocks of a selection launch (rows of mhat)
   size_t mhat, src;
   size_t total;
