@@ -562,13 +562,19 @@ def splat_lod_highlight_workspace_bytes(node_capacity: int, max_points: int, max
     return int(ws.value)
 
 
-def highlight_flags(tree: Tree, bits, n_bits: int):
+def highlight_flags(tree: Tree, bits, n_bits: int, out=None):
     """One flag bit per stored point of the tree (device uint32 words): set when
-    the point's id is in the id bitset `bits` of n_bits bits."""
+    the point's id is in the id bitset `bits` of n_bits bits.  `out` (uint32,
+    2 ceil(point_capacity / 64) words) is reused when given; every word is
+    written."""
     import torch
     lib = load()
-    flags = torch.zeros(2 * ((tree.point_capacity + 63) // 64), dtype=torch.int32,
-                        device=tree.counts.device).view(torch.uint32)
+    words = 2 * ((tree.point_capacity + 63) // 64)
+    if out is None:
+        out = torch.empty(words, dtype=torch.int32, device=tree.counts.device).view(torch.uint32)
+    elif out.numel() < words or out.element_size() != 4 or not out.is_contiguous():
+        raise ValueError(f"flags need {words} contiguous 32-bit words")
+    flags = out
     _check(lib.lod_highlight_flags(C.byref(tree.c()), _ptr(bits), int(n_bits), _ptr(flags), _stream()),
            "lod_highlight_flags")
     return flags

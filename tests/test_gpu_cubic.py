@@ -195,6 +195,10 @@ def test_lod_highlight_matches_oracle(blob):
     S = ref.n_points
     got_bits = ((fl[np.arange(S) >> 5] >> (np.arange(S) & 31).astype(np.uint64)) & np.uint64(1)).astype(bool)
     assert np.array_equal(got_bits, member[ref.pt_id.astype(np.int64)])
+    # a reused output buffer holding garbage: every word is rewritten
+    again = torch.full_like(flags.view(torch.int32), -1).view(torch.uint32)
+    lib.highlight_flags(tree, bits, n_bits, out=again)
+    assert torch.equal(again.view(torch.int32), flags.view(torch.int32))
     b = lib.Blob.cubic(h_px=1.7) if blob == "cubic" else None
     for name, cam, ocam in _cams(160, 160)[:3]:
         ids, nsel = lib.select_nodes(tree, cam, 1.0, n)
