@@ -426,7 +426,12 @@ typedef struct {
  * roots are loaded now and never evicted (LOD_ECAPACITY when they do not
  * fit).  After each frame, view->pt_begin holds the slot offsets of the
  * resident nodes, so splat_render_lod(view, draw list) draws the frame.
- * The streamer allocates pinned host staging, no device memory. */
+ * The streamer allocates pinned host staging, no device memory.  A file is
+ * checked before anything reaches the device: LOD_EINVAL when it cannot be
+ * read, has another magic or version, or its node table is not a tree
+ * (indices out of range, a child that does not name its parent or follow
+ * it in node order, more than n points in a node, a block past the end of the
+ * file); LOD_EDEVICE when a copy or the pinned allocation fails. */
 lod_status lod_streamer_open(const char *path, uint32_t pool_slots, lod_tree *view, lod_streamer **out);
 
 /* One frame.  The link carries budget_bytes per frame: a credit grows by

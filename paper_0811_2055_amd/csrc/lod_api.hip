@@ -99,8 +99,8 @@ lod_status lod_trace_end(lod_kernel_time *records, uint32_t cap, uint32_t *n_rec
       st = LOD_EDEVICE;
     if (records && k < cap) records[k] = lod_kernel_time{r.name, ms};
     ++k;
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   if (n_records) *n_records = k;
   delete t;
@@ -364,8 +364,9 @@ lod_status lod_autotune(const lod_input *in, lod_params *p, void *workspace, siz
   if (out->node_capacity < L.node_cap || out->point_capacity < L.point_cap) return LOD_ECAPACITY;
   hipStream_t st = (hipStream_t)stream;
   int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) != hipSuccess) return LOD_EDEVICE;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return LOD_EDEVICE;
   std::vector<lod_params> cands;
   for (uint32_t thr : {256u, 512u, 1024u}) {
     lod_params c = *p; c.mode = 1; c.select_threads = thr; c.persistent_blocks = 0;
@@ -383,19 +384,22 @@ lod_status lod_autotune(const lod_input *in, lod_params *p, void *workspace, siz
   lod_status rs = LOD_OK;
   for (const lod_params &c : cands) {
     if ((rs = lodh::launch_build(*in, c, workspace, L, *out, st)) != LOD_OK) break;   // warm-up
-    hipEventRecord(e0, st);
+    if (hipEventRecord(e0, st) != hipSuccess) { rs = LOD_EDEVICE; break; }
     for (int r = 0; r < 2 && rs == LOD_OK; ++r) rs = lodh::launch_build(*in, c, workspace, L, *out, st);
-    hipEventRecord(e1, st);
-    if (rs != LOD_OK || hipEventSynchronize(e1) != hipSuccess) { rs = rs != LOD_OK ? rs : LOD_EDEVICE; break; }
+    if (rs != LOD_OK) break;
     float t = 0.0f;
-    hipEventElapsedTime(&t, e0, e1);
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      rs = LOD_EDEVICE;
+      break;
+    }
     t *= 0.5f;
     if (cand && ms && k < cap) { cand[k] = c; ms[k] = t; }
     ++k;
     if (t < best) { best = t; bestp = c; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (n_cand) *n_cand = k;
   if (rs != LOD_OK) return rs;
   p->mode = bestp.mode;

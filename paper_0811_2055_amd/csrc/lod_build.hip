@@ -943,7 +943,6 @@ __global__ __launch_bounds__(TB) void k_leaves(BuildArgs a, TreeArgs t, Sorted s
 
 constexpr int SMALL = 512;
 constexpr int KBINS = 4096;
-constexpr int ILP = 8;        // list entries in flight per thread in the candidate passes
 constexpr int SILP = 8;       // candidates per lane per wave step
 constexpr int CILP = 8;       // candidates per lane per step of the compaction pass of list nodes
 constexpr int OILP = 4;       // list entries per thread per step of the output pass
@@ -1920,8 +1919,9 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
     device_scan<uint32_t>(bscan, L.node_cap + 1, (uint32_t *)(W + L.scan32), st);
     LOD_LAUNCH(k_bottom_write, dim3(fg), dim3(256), 0, st, a, bflag, bscan, (uint32_t *)(W + L.bottom), ctl);
     int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return LOD_EDEVICE;
     const unsigned pgrid = std::min<unsigned>(L.sel_rows, p.persistent_blocks ? p.persistent_blocks
                                                                               : (unsigned)(2 * cus));
     LOD_LAUNCH(k_select_persistent, dim3(pgrid), dim3(sel_threads), 0, st, a, t, s, sa,

@@ -122,10 +122,6 @@ __device__ __forceinline__ bool axis_range(const Cam &c, float t, uint32_t size,
   return clip_range(t, c.R, 0, (int)size - 1, lo, hi);
 }
 
-__device__ __forceinline__ uint64_t load_count(uint64_t count, const uint64_t *count_dev) {
-  return count_dev ? min(count, *count_dev) : count;
-}
-
 // --- binning -----------------------------------------------------------------
 //
 // Points are binned to 16x16 pixel tiles by a stable counting sort, so that
@@ -1344,6 +1340,8 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   const uint64_t width = 2 * (uint64_t)std::ceil(R) + 3;         // pixels a blob's tile range can span
   const uint64_t tpa = std::min<uint64_t>((width + TS - 1) / TS + 1, std::max(L.tiles_x, L.tiles_y));
   L.max_points = max_points;
+  // pair counts are 32-bit, and a point adds at least one pair
+  if (max_points >= (1ull << 32)) return LOD_EUNSUPPORTED;
   L.max_pairs = std::max<uint64_t>(1, max_points * tpa * tpa);
   if (L.max_pairs >= (1ull << 32)) return LOD_EUNSUPPORTED;
   L.max_slices = nt + L.max_pairs / SPLAT_SLICE + 1;

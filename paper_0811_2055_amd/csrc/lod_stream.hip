@@ -95,6 +95,15 @@ struct lod_streamer {
   char *staging = nullptr;        // pinned host: the frame's blocks
   size_t staging_bytes = 0;
   uint32_t *draw_host = nullptr;  // pinned host: the draw list
+
+  lod_streamer() = default;
+  lod_streamer(const lod_streamer &) = delete;
+  lod_streamer &operator=(const lod_streamer &) = delete;
+  ~lod_streamer() {
+    if (fd >= 0) close(fd);
+    if (staging) (void)hipHostFree(staging);
+    if (draw_host) (void)hipHostFree(draw_host);
+  }
 };
 
 namespace {
@@ -195,9 +204,39 @@ int64_t pick_victim(const lod_streamer &s, int64_t f) {
   return best;
 }
 
+uint64_t file_bytes(int fd) {
+  struct stat st;
+  return fstat(fd, &st) == 0 && st.st_size > 0 ? (uint64_t)st.st_size : 0;
+}
+
+// A node table read from a file is trusted only as far as this check goes:
+// every index in range, each node the parent of exactly its children (which
+// follow it: the visit terminates), at most n points per node, depths that fit
+// the 64-bit prefix, and every block inside the file.
+bool node_table_ok(const lod_streamer &s, uint64_t file_size) {
+  const uint64_t V = s.V;
+  if (s.n == 0 || V == 0 || V >= LOD_NONE) return false;
+  for (uint64_t v = 0; v < V; ++v) {
+    if (s.pt_count[v] > s.n || s.depth[v] > 21) return false;
+    if (s.parent[v] != LOD_NONE && (s.parent[v] >= v || s.depth[v] != s.depth[s.parent[v]] + 1)) return false;
+    if (s.parent[v] == LOD_NONE && s.depth[v] != 0) return false;
+    const uint32_t k = (uint32_t)__builtin_popcount(s.child_mask[v]);
+    if ((k == 0) != (s.first_child[v] == LOD_NONE)) return false;
+    if (k) {
+      const uint64_t c0 = s.first_child[v];
+      if (c0 <= v || c0 + k > V) return false;
+      for (uint32_t i = 0; i < k; ++i)
+        if (s.parent[c0 + i] != v) return false;
+    }
+    const uint64_t b = s.block_off[v], bytes = kBlockBytes * s.pt_count[v];
+    if (b > file_size || bytes > file_size - b) return false;
+  }
+  return true;
+}
+
 lod_status ensure_staging(lod_streamer &s, size_t bytes) {
   if (bytes <= s.staging_bytes) return LOD_OK;
-  if (s.staging) hipHostFree(s.staging);
+  if (s.staging) (void)hipHostFree(s.staging);
   s.staging = nullptr;
   s.staging_bytes = 0;
   if (hipHostMalloc((void **)&s.staging, bytes) != hipSuccess) return LOD_EDEVICE;
@@ -292,8 +331,7 @@ lod_status lod_streamer_open(const char *path, uint32_t pool_slots, lod_tree *vi
     return LOD_EINVAL;
   lod_streamer *s = new lod_streamer();
   auto fail = [&](lod_status st) {
-    if (s->fd >= 0) close(s->fd);
-    delete s;
+    delete s;   // closes the file and frees the pinned buffers
     return st;
   };
   s->fd = open(path, O_RDONLY);
@@ -318,6 +356,7 @@ lod_status lod_streamer_open(const char *path, uint32_t pool_slots, lod_tree *vi
     if (!read_all(s->fd, arrs[i], sizes[i], off)) return fail(LOD_EINVAL);
     off = align8(off + sizes[i]);
   }
+  if (!node_table_ok(*s, file_bytes(s->fd))) return fail(LOD_EINVAL);
   s->resident.assign(V, 0);
   s->used.assign(V, -1);
   s->wanted.assign(V, -1);
@@ -503,9 +542,6 @@ lod_status lod_streamer_frame(lod_streamer *s, const lod_camera *cam, float tau_
 
 lod_status lod_streamer_close(lod_streamer *s) {
   if (!s) return LOD_EINVAL;
-  if (s->fd >= 0) close(s->fd);
-  if (s->staging) hipHostFree(s->staging);
-  if (s->draw_host) hipHostFree(s->draw_host);
   delete s;
   return LOD_OK;
 }

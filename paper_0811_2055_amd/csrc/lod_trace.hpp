@@ -27,14 +27,20 @@ struct TraceScope {
   TraceScope(const char *name, hipStream_t s) : t(current_trace()), idx(0), st(s) {
     if (!t) return;
     TraceRec r{name, nullptr, nullptr};
-    hipEventCreate(&r.a);
-    hipEventCreate(&r.b);
-    hipEventRecord(r.a, st);
+    // a launch whose events cannot be made or recorded is left out of the trace
+    if (hipEventCreate(&r.a) != hipSuccess) { t = nullptr; return; }
+    if (hipEventCreate(&r.b) != hipSuccess || hipEventRecord(r.a, st) != hipSuccess) {
+      (void)hipEventDestroy(r.a);
+      if (r.b) (void)hipEventDestroy(r.b);
+      t = nullptr;
+      return;
+    }
     idx = t->recs.size();
     t->recs.push_back(r);
   }
   ~TraceScope() {
-    if (t) hipEventRecord(t->recs[idx].b, st);
+    // a failed record shows up as a failed elapsed-time query in lod_trace_end
+    if (t) (void)hipEventRecord(t->recs[idx].b, st);
   }
 };
 

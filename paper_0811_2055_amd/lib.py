@@ -283,6 +283,65 @@ class Tree:
         return out
 
 
+TREE_FILE_FORMAT = "lodtree-npz-1"
+_NODE_KEYS = ("prefix", "depth", "parent", "first_child", "child_mask", "part_begin", "part_count", "pt_begin",
+              "pt_count", "node_mass")
+_POINT_KEYS = ("pt_id", "qx", "qy", "qz", "pt_mass")
+
+
+def save_tree(tree: Tree, path: str, n: int = 0):
+    """Write a built tree to a .npz file: the used part of every node and
+    point array, the counts and the capacities (numpy.savez, no pickled
+    objects).  n: the build's points per node, kept for the reader.  A tree
+    whose status word is not 0 is refused (its outputs are undefined)."""
+    import numpy as np
+    h = tree.host()
+    if h["status"] != 0:
+        raise ValueError(f"tree status {h['status']:#x}: the build reported an error")
+    np.savez(path, format=np.array(TREE_FILE_FORMAT), n_nodes=np.uint64(h["n_nodes"]),
+             n_points=np.uint64(h["n_points"]), node_capacity=np.uint64(tree.node_capacity),
+             point_capacity=np.uint64(tree.point_capacity), n=np.uint32(n),
+             **{k: h[k] for k in _NODE_KEYS + _POINT_KEYS})
+
+
+def _from_numpy(a, dtype, device):
+    import numpy as np
+    import torch
+    signed = {np.dtype(np.uint64): np.int64, np.dtype(np.uint32): np.int32, np.dtype(np.uint16): np.int16}
+    if a.dtype in signed:
+        return torch.from_numpy(np.ascontiguousarray(a).view(signed[a.dtype])).to(device).view(dtype)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def load_tree(path: str, device="cuda", node_capacity: int | None = None, point_capacity: int | None = None):
+    """Read a tree written by save_tree into newly allocated arrays on
+    `device` (capacities: the saved ones unless given larger).  Returns
+    (tree, n).  Slots past the node count get pt_count 0 and pt_begin equal to
+    the point count, as the build leaves them."""
+    import numpy as np
+    import torch
+    with np.load(path, allow_pickle=False) as f:
+        if "format" not in f.files or str(f["format"]) != TREE_FILE_FORMAT:
+            raise ValueError(f"{path} is not a tree file")
+        V, S = int(f["n_nodes"]), int(f["n_points"])
+        nc = max(V, 1, int(node_capacity or f["node_capacity"]))
+        pc = max(S, 1, int(point_capacity or f["point_capacity"]))
+        tree = alloc_tree(nc, pc, device)
+        for keys, count in ((_NODE_KEYS, V), (_POINT_KEYS, S)):
+            for k in keys:
+                a = f[k]
+                dst = tree.arrays[k]
+                if a.shape != (count,) or a.dtype.itemsize != dst.element_size():
+                    raise ValueError(f"{path}: array {k} has shape {a.shape} and dtype {a.dtype}")
+                if count:
+                    dst[:count].copy_(_from_numpy(a, dst.dtype, device))
+        n = int(f["n"])
+    tree.arrays["pt_count"][V:].zero_()
+    tree.arrays["pt_begin"][V:].fill_(S)
+    tree.counts.copy_(_from_numpy(np.array([V, S, 0], dtype=np.uint64), torch.uint64, device))
+    return tree, n
+
+
 def _to_numpy(t):
     import numpy as np
     import torch

@@ -124,6 +124,51 @@ class NodeRefiner:
             return z, z, 0
         return st["exp_avg"], st["exp_avg_sq"], int(st["step"])
 
+    # -- checkpoints ----------------------------------------------------------
+    # The parameters (theta, x, y, z), each one's Adam moments and step count,
+    # as numpy arrays; a refiner built on the same node and views continues
+    # from them bit for bit.  Stored with numpy.savez (no pickled objects).
+    CHECKPOINT_FORMAT = "lodrefine-npz-1"
+    _NAMES = ("theta", "x", "y", "z")
+
+    def state(self) -> dict:
+        out = {"format": np.array(self.CHECKPOINT_FORMAT)}
+        for name, t in zip(self._NAMES, [self.theta] + self.xs):
+            ea, es, k = self.adam_state(t)
+            out[name] = t.detach().cpu().numpy()
+            out[name + "_exp_avg"] = ea.detach().cpu().numpy()
+            out[name + "_exp_avg_sq"] = es.detach().cpu().numpy()
+            out[name + "_step"] = np.array(k, dtype=np.int64)
+        return out
+
+    def load_state(self, st: dict):
+        if str(st.get("format", "")) != self.CHECKPOINT_FORMAT:
+            raise ValueError("not a node-refinement checkpoint")
+        tensors = [self.theta] + self.xs
+        for name, t in zip(self._NAMES, tensors):
+            if tuple(st[name].shape) != tuple(t.shape):
+                raise ValueError(f"checkpoint {name} has shape {st[name].shape}, the node {tuple(t.shape)}")
+        with torch.no_grad():
+            for name, t in zip(self._NAMES, tensors):
+                t.copy_(torch.from_numpy(st[name]).to(t.device))
+        sd = self.opt.state_dict()
+        state = {}
+        for i, (name, t) in enumerate(zip(self._NAMES, tensors)):
+            k = int(st[name + "_step"])
+            if k == 0:
+                continue
+            state[i] = {"step": torch.tensor(float(k), dtype=torch.float32),
+                        "exp_avg": torch.from_numpy(st[name + "_exp_avg"]).to(t.device),
+                        "exp_avg_sq": torch.from_numpy(st[name + "_exp_avg_sq"]).to(t.device)}
+        self.opt.load_state_dict({"state": state, "param_groups": sd["param_groups"]})
+
+    def save(self, path: str):
+        np.savez(path, **self.state())
+
+    def load(self, path: str):
+        with np.load(path, allow_pickle=False) as f:
+            self.load_state({k: f[k] for k in f.files})
+
 
 def refine_node(px, py, pz, pm, full, lo, side: float, node_mass: float, train_cams, test_cams,
                 steps: int = 200, lr_mass: float = 1e-2, lr_pos_frac: float = 1e-3, sigma: float = 1.0):

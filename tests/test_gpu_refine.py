@@ -383,3 +383,36 @@ def test_set_node_points_codes_like_the_build():
     nx[0] = np.float32(cx * side - 0.01)
     lib.set_node_points(tree, v, *[torch.from_numpy(a).cuda() for a in (nx, ny, nz, nm)])
     assert tree.host()["status"] & lib.STATUS_DOMAIN
+
+
+def test_refinement_checkpoint_resumes_bit_for_bit(tmp_path):
+    """A refinement run saved after three steps and resumed in a new refiner
+    (same node, same views) takes the next two steps exactly as the run that
+    went on without stopping: parameters, Adam moments and step counts."""
+    import torch
+    from paper_0811_2055_amd import refine
+    s = synth.small_clustered(30000, 84)
+    n = 400
+    (px, py, pz, pm), full, members, lo, side, M = _node_setup(s, n, 4, 6, 1)
+    centre = [l + side / 2 for l in lo]
+    cams = refine.node_views(centre, side, n, 2, seed=0, W=96, H=96)
+    a = refine.NodeRefiner(px, py, pz, pm, full, lo, side, M, cams)
+    for _ in range(3):
+        a.step()
+    path = str(tmp_path / "node.npz")
+    a.save(path)
+    la = [a.step() for _ in range(2)]
+    b = refine.NodeRefiner(px, py, pz, pm, full, lo, side, M, cams)
+    b.load(path)
+    lb = [b.step() for _ in range(2)]
+    assert la == lb
+    for ta, tb in zip([a.theta] + a.xs, [b.theta] + b.xs):
+        assert torch.equal(ta.detach(), tb.detach())
+        ea, sa, ka = a.adam_state(ta)
+        eb, sb, kb = b.adam_state(tb)
+        assert ka == kb == 5 and torch.equal(ea, eb) and torch.equal(sa, sb)
+    # a checkpoint of another node is refused
+    c = refine.NodeRefiner(px[:10], py[:10], pz[:10], pm[:10], full, lo, side, M, cams)
+    with pytest.raises(ValueError):
+        c.load(path)
+
