@@ -410,11 +410,15 @@ __device__ __forceinline__ uint64_t block_incl_scan_op(uint64_t v, uint64_t *tmp
 // run's start is the largest run-start position at or before an element, its
 // end the smallest run-end position after it; both come from a thread-local
 // pass plus a block scan, and runs crossing the tile edge are closed by a
-// binary search over the sorted keys.
+// binary search over the sorted keys.  The LDS arrays hold word i at
+// i + i/16: blocked accesses (thread t at 16 t + k) would otherwise put a
+// wave's lanes on four banks.
+constexpr int DPAD = (TILE + 2) / 16 + 1;
+__device__ __forceinline__ int dpad(int i) { return i + (i >> 4); }
 __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__restrict__ skey,
                                                 const uint32_t *__restrict__ sidx,
                                                 uint32_t *__restrict__ w_out, uint16_t *__restrict__ kb_out) {
-  __shared__ uint32_t cell[TILE + 2];     // cell[i+1] = cell of element base+i
+  __shared__ uint32_t cell[TILE + 2 + DPAD];   // cell[dpad(i+1)] = cell of element base+i
   __shared__ uint64_t tmp[TB / WAVE + 1];
   __shared__ uint64_t incl_max[TB];
   __shared__ uint64_t rev_min[TB];
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
       const int i = j * TB + (int)threadIdx.x;
       const int64_t e = (int64_t)base + i - 1;
       if (i < TILE + 2)
-        cell[i] = (e >= 0 && (uint64_t)e < N && i <= (int)tile_n + 1) ? (kc[j] >> sh) : 0xFFFFFFFFu;
+        cell[dpad(i)] = (e >= 0 && (uint64_t)e < N && i <= (int)tile_n + 1) ? (kc[j] >> sh) : 0xFFFFFFFFu;
     }
   }
   __syncthreads();
@@ -446,8 +450,8 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
   if (threadIdx.x == 0) {
     // runs crossing the tile edges: galloping search outward from the edge
     uint64_t s0 = base;
-    if (has_prev && cell[0] == cell[1]) {
-      const uint32_t c = cell[1];
+    if (has_prev && cell[dpad(0)] == cell[dpad(1)]) {
+      const uint32_t c = cell[dpad(1)];
       uint64_t right = base, step = 1, lo = 0;
       while (true) {
         if (right < step) { lo = 0; break; }
@@ -465,8 +469,8 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
     }
     first_start = s0;
     uint64_t e0 = base + tile_n;
-    if (has_next && cell[tile_n] == cell[tile_n + 1]) {
-      const uint32_t c = cell[tile_n];
+    if (has_next && cell[dpad(tile_n)] == cell[dpad(tile_n + 1)]) {
+      const uint32_t c = cell[dpad(tile_n)];
       uint64_t known = base + tile_n - 1, step = 1, hi = N;
       while (true) {
         const uint64_t probe = known + step;
@@ -496,7 +500,8 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const int li = t0 + i;
-    const bool starts = (li == 0) ? (!has_prev || cell[0] != cell[1]) : (cell[li] != cell[li + 1]);
+    const bool starts =
+        (li == 0) ? (!has_prev || cell[dpad(0)] != cell[dpad(1)]) : (cell[dpad(li)] != cell[dpad(li + 1)]);
     if (li < (int)tile_n && starts) runmax = (uint32_t)li + 1;
     st[i] = runmax;
   }
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
     const int li = t0 + i;
     if (li < (int)tile_n) {
       if (li == (int)tile_n - 1) runmin = tile_n;
-      else if (cell[li + 1] != cell[li + 2]) runmin = min(runmin, (uint32_t)li + 1);
+      else if (cell[dpad(li + 1)] != cell[dpad(li + 2)]) runmin = min(runmin, (uint32_t)li + 1);
     }
     en[i] = runmin;
   }
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
       const uint32_t sl = max(st[i], prev_max), el = min(en[i], next_min);
       const uint64_t sg = sl ? base + sl - 1 : fs;
       const uint64_t eg = (el == tile_n) ? le : base + el;
-      wl[li] = (uint32_t)(eg - sg);
+      wl[dpad(li)] = (uint32_t)(eg - sg);
     }
   }
   __syncthreads();
@@ -561,7 +566,7 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
       const int li = (c + i) * TB + threadIdx.x;
       if (li < (int)tile_n) {
         const uint64_t e = base + li;
-        const uint32_t w = wl[li];
+        const uint32_t w = wl[dpad(li)];
         // one snapshot: the counter's words 1-3 are zero, which folds the
         // first round's second product
         const uint64_t U = a.n_snap > 1 ? particle_U(local_id(a, snaps[i], ids[i]), snaps[i], a.seed)
@@ -582,7 +587,7 @@ __global__ __launch_bounds__(TB) void k_density(BuildArgs a, const uint32_t *__r
       const uint64_t e = base + li;
       const uint32_t snap = a.n_snap > 1 ? (uint32_t)((uint64_t)skey[e] >> sdb) : 0u;
       const uint64_t U = particle_U(local_id(a, snap, sidx[e]), snap, a.seed);
-      kb_out[e] = (uint16_t)kbin(div_u2p31(U, wl[li]));
+      kb_out[e] = (uint16_t)kbin(div_u2p31(U, wl[dpad(li)]));
     }
   }
 }
