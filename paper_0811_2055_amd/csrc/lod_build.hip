@@ -1108,6 +1108,72 @@ __device__ __forceinline__ bool taken_exact(const BuildArgs &a, const Sorted &s,
   return K < Kt || (K == Kt && s.idx[p] <= It);
 }
 
+// Sum of row[0..n) in an order fixed by n alone, so that every block size and
+// schedule stores the same bits: 64-entry chunks summed by a wave's xor
+// butterfly (lane i holds entry 64c + i, absent entries 0; lane 0's value),
+// groups of 64 chunk sums by one more butterfly, and the group sums added in
+// order by thread 0.  Rows of up to RS_CHUNKS chunks take one pass (the waves
+// load their chunks together); longer rows go group by group.  cs: RS_CHUNKS
+// doubles of LDS; the result is returned to every thread (barriers inside).
+constexpr uint32_t RS_CHUNKS = 256;
+__device__ double row_sum_fixed(const double *row, uint32_t n, double *cs, double *res) {
+  const uint32_t W = blockDim.x / WAVE, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const uint32_t chunks = (n + WAVE - 1) / WAVE;
+  double total = 0.0;   // thread 0's
+  auto chunk_sum = [&](uint32_t c) {
+    double x = c * WAVE + lane < n ? row[c * WAVE + lane] : 0.0;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
+    return x;
+  };
+  auto group_sum = [&](uint32_t g, uint32_t count) {   // wave 0: chunk sums g*64.. of cs
+    double x = g * WAVE + lane < count ? cs[g * WAVE + lane] : 0.0;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
+    return x;
+  };
+  if (chunks <= RS_CHUNKS) {
+    constexpr int CU = 4;   // chunks of a wave loaded together
+    for (uint32_t c0 = w; c0 < chunks; c0 += W * CU) {
+      double x[CU];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const uint32_t c = c0 + u * W;
+        const uint32_t j = min(c * WAVE + lane, n - 1);
+        x[u] = (c < chunks && c * WAVE + lane < n) ? row[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) x[u] += __shfl_xor(x[u], o, WAVE);
+        if (lane == 0 && c0 + u * W < chunks) cs[c0 + u * W] = x[u];
+      }
+    }
+    __syncthreads();
+    if (w == 0)
+      for (uint32_t g = 0; g * WAVE < chunks; ++g) {
+        const double x = group_sum(g, chunks);
+        if (lane == 0) total += x;
+      }
+  } else {
+    for (uint32_t c0 = 0; c0 < chunks; c0 += WAVE) {
+      for (uint32_t c = c0 + w; c < min(chunks, c0 + WAVE); c += W) {
+        const double x = chunk_sum(c);
+        if (lane == 0) cs[c - c0] = x;
+      }
+      __syncthreads();
+      if (w == 0) {
+        const double x = group_sum(0, min(chunks - c0, (uint32_t)WAVE));
+        if (lane == 0) total += x;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) *res = total;
+  __syncthreads();
+  return *res;
+}
+
 // One selecting node, whole block: the n+1 smallest (K, id) among its
 // candidates (children's lists or its own range) form its list, ascending by
 // sorted position; the (n+1)-th smallest is the witness.  The other n are
@@ -1133,7 +1199,8 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   __shared__ uint32_t qpos[QCAP];
   __shared__ uint16_t qpart[QCAP];
   __shared__ uint32_t red32[1024 / WAVE + 1];
-  __shared__ double red64[1024 / WAVE + 1];
+  __shared__ double cs64[RS_CHUNKS];
+  __shared__ double sh_mtot;
   __shared__ uint64_t sh_kt;
   __shared__ uint32_t sh_it, sh_pt;
   __shared__ uint32_t sh_b, sh_below, sh_cnt;
@@ -1370,7 +1437,6 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     if (found != 2u) return found != 0u;
     return taken_exact(a, s, p, Kt, It);
   };
-  double acc = 0.0;
   if (!lists) {
     // Only ranges: one pass writes the list and the stored points, the
     // candidates' data loaded alongside their key bins (contiguous reads).
@@ -1408,7 +1474,6 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
               const double mhat = (double)mm[u] / fmin(1.0, weight_pow(wv[u], a.alpha) / tau);
               store_point_pos(a, t, q[u], ob + j, d);
               mrow[j] = mhat;
-              acc += mhat;
             }
           }
         }
@@ -1495,12 +1560,12 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
           store_point_pos(a, t, q[u], ob + j, d);
         }
         mrow[j] = mhat;
-        acc += mhat;
       }
     }
   }
-  const double tot = block_reduce_sum<double>(acc, red64);   // (barrier inside)
+  __syncthreads();
   if (out_ok) {
+    const double tot = row_sum_fixed(mrow, n, cs64, &sh_mtot);
     const double scale = t.node_mass[v] / tot;
     for (uint32_t j0 = threadIdx.x; j0 < n; j0 += BS * SILP) {
       double mv[SILP];

@@ -114,6 +114,26 @@ def test_schedules_identical():
                 assert v == h[k], k
 
 
+def test_persistent_handoffs_many_levels():
+    """The persistent schedule hands a node from the block that finishes its
+    last selecting child to whichever block reduces it, across XCDs: a deep
+    tree with small nodes (thousands of climbs through ten levels) built in
+    mode 2 with several grids equals the per-level build byte for byte, and
+    the per-level build equals the oracle."""
+    s = synth.small_clustered(200000, 23)
+    p = dict(n=12, max_depth=10, seed=5)
+    ref = olod.lod_build(s.x, s.y, s.z, s.m, n=12, D=10, alpha=1, seed=5)
+    base = lib.build(*to_dev(s), lib.BuildParams(mode=1, **p)).host()
+    compare_tree(base, ref)
+    for thr, grid in ((256, 0), (1024, 0), (64, 4096), (512, 17)):
+        h = lib.build(*to_dev(s), lib.BuildParams(mode=2, select_threads=thr, persistent_blocks=grid, **p)).host()
+        for k, v in base.items():
+            if isinstance(v, np.ndarray):
+                assert np.array_equal(v, h[k]), (thr, grid, k)
+            else:
+                assert v == h[k], (thr, grid, k)
+
+
 def test_repeat_runs_identical():
     s = synth.small_clustered(50000, 22)
     b = lib.Builder(s.n, lib.BuildParams(n=200, max_depth=6, seed=4))
