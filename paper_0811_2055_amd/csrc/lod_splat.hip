@@ -1004,6 +1004,125 @@ __global__ __launch_bounds__(PT) void k_accumulate_cubic(const uint2 *__restrict
   }
 }
 
+// The same sums for narrow blobs: every pixel radius below 1.9 (WIN = 4) or
+// 3.9 (WIN = 8) pixels, so that a blob covers only pixels of the WIN x WIN
+// window that starts at its first admitted pixel (the binning's conservative
+// range: its first pixel, and at most WIN - 1 more, since 2 (h + 1/100)
+// plus the float32 rounding of the range stays below WIN).  The gather form
+// spends a wave's 64 lanes on one record, of which a handful are covered;
+// here the work is split in two phases per chunk of CH records:
+//   A: every lane evaluates one record at IPT window pixels (all lanes busy),
+//      leaves the rounded contributions in LDS and, for each covered pixel
+//      of the tile, sets the record's bit in that pixel's mask;
+//   B: thread p owns pixel p of the tile as before and walks the set bits of
+//      its mask in increasing record order, adding those contributions.
+// The contributions are computed by the same float32 / float64 operations as
+// in k_accumulate_cubic and every pixel adds the same ones in the same
+// order: the image is bit-identical to the gather form's.
+template <int WIN> struct CubicWin {
+  static constexpr int WW = WIN * WIN;           // window pixels per record
+  static constexpr int CH = WIN == 4 ? PT : 64;  // records per chunk
+  static constexpr int IPT = WW * CH / PT;       // window pixels per thread in phase A
+  static constexpr int VS = CH + 1;              // LDS stride of one window pixel's row
+  static constexpr int MW = CH / 32;             // mask words per pixel
+};
+
+template <class RecT, int WIN>
+__global__ __launch_bounds__(PT) void k_accumulate_cubic_win(const uint2 *__restrict__ table,
+                                                             const uint32_t *__restrict__ slice_off, uint32_t nt,
+                                                             const RecT *__restrict__ rec, Cam c,
+                                                             float *__restrict__ partial,
+                                                             float *__restrict__ partial_aux, uint64_t max_slices,
+                                                             uint64_t max_pairs) {
+  constexpr bool AUX = RecInfo<RecT>::aux;
+  using CW = CubicWin<WIN>;
+  constexpr int CH = CW::CH, IPT = CW::IPT, VS = CW::VS, MW = CW::MW;
+  static_assert(IPT * PT == CW::WW * CH && CH % 32 == 0 && PT == TS * TS, "phase A covers every window pixel once");
+  __shared__ float val[CW::WW * VS];             // [window pixel][record]
+  __shared__ float vala[AUX ? CW::WW * VS : 1];
+  __shared__ uint32_t org[CH];                   // window origin in the tile: x0 | y0 << 16 (int16 each)
+  __shared__ uint32_t msk[MW * PT];              // [record / 32][pixel]: bit of each covering record
+  const uint32_t total_slices = (uint32_t)min((uint64_t)slice_off[nt], max_slices);
+  if (blockIdx.x >= total_slices) return;
+  const int px = threadIdx.x % TS, py = threadIdx.x / TS;
+  const int kA = threadIdx.x % CH;                 // phase A: this thread's record in the chunk
+  const int iA = (threadIdx.x / CH) * IPT;         // and its first window pixel
+  // phase B leaves each pixel's mask words cleared for the next chunk
+#pragma unroll
+  for (int wd = 0; wd < MW; ++wd) msk[wd * PT + threadIdx.x] = 0u;
+  __syncthreads();
+  for (uint32_t sl = blockIdx.x; sl < total_slices; sl += gridDim.x) {
+    const uint2 sd = table[sl];
+    const uint32_t t = sd.y & 0xFFFFu;
+    const uint64_t pb = sd.x;
+    const uint64_t pe = min(pb + (sd.y >> 16), max_pairs);
+    const int tx0 = (int)(t % c.tiles_x) * TS, ty0 = (int)(t / c.tiles_x) * TS;
+    float s = 0.0f, cs = 0.0f, s_a = 0.0f, c_a = 0.0f;
+    for (uint64_t c0 = pb; c0 < pe; c0 += CH) {
+      const int nrec = (int)min((uint64_t)CH, pe - c0);
+      // phase A
+      {
+        const bool have = kA < nrec;
+        float u, v, m, h, a;
+        load_rec(rec, have ? c0 + kA : pb, u, v, m, h, a);
+        const int lx = (int)ceilf(u - 0.5f - h - 0.01f), ly = (int)ceilf(v - 0.5f - h - 0.01f);
+        const int x0 = lx - tx0, y0 = ly - ty0;
+        if (iA == 0) org[kA] = ((uint32_t)x0 & 0xFFFFu) | ((uint32_t)y0 << 16);
+        const double h64 = (double)h;
+        const double hh = h64 * h64;
+        const double ih = 1.0 / h64;
+        const float hh32 = (h * h) * 1.001f;
+        const uint32_t bit = 1u << (kA & 31);
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) {
+          const int wi = iA + e;
+          const int tpx = x0 + wi % WIN, tpy = y0 + wi / WIN;   // the pixel in the tile
+          const float cx = (float)(lx + wi % WIN) + 0.5f, cy = (float)(ly + wi / WIN) + 0.5f;
+          const float ox = u - cx, oy = v - cy;
+          float vf = 0.0f, va = 0.0f;
+          if (have && (ox * ox + oy * oy) < hh32) {
+            const double r2 = (double)ox * (double)ox + (double)oy * (double)oy;
+            if (r2 < hh) {
+              double q = 0.0;
+              if (r2 > 0.0) {
+                double y = __builtin_amdgcn_rsq(r2);
+                y = y * (1.5 - (0.5 * r2) * (y * y));
+                q = (r2 * y) * ih;
+              }
+              const double w = (double)m * (kCubicNorm / hh) * cubic_w(q);
+              vf = (float)w;
+              if (AUX) va = (float)(w * (double)a);
+              if ((unsigned)tpx < (unsigned)TS && (unsigned)tpy < (unsigned)TS)
+                atomicOr(&msk[(kA >> 5) * PT + tpy * TS + tpx], bit);
+            }
+          }
+          val[wi * VS + kA] = vf;
+          if (AUX) vala[wi * VS + kA] = va;
+        }
+      }
+      __syncthreads();
+      // phase B: this pixel's covering records in increasing order
+#pragma unroll
+      for (int wd = 0; wd < MW; ++wd) {
+        uint32_t bits = msk[wd * PT + threadIdx.x];
+        msk[wd * PT + threadIdx.x] = 0u;
+        while (bits) {
+          const int k = wd * 32 + __builtin_ctz(bits);
+          bits &= bits - 1u;
+          const uint32_t o = org[k];
+          const int dx = px - (int)(int16_t)(o & 0xFFFFu), dy = py - (int)(int16_t)(o >> 16);
+          const int vi = (dy * WIN + dx) * VS + k;
+          neumaier(s, cs, val[vi]);
+          if (AUX) neumaier(s_a, c_a, vala[vi]);
+        }
+      }
+      __syncthreads();
+    }
+    partial[(uint64_t)sl * (TS * TS) + threadIdx.x] = s + cs;
+    if (AUX) partial_aux[(uint64_t)sl * (TS * TS) + threadIdx.x] = s_a + c_a;
+  }
+}
+
 // Adjoint of the cubic blob, one thread per point over its own footprint
 // (float64 sums): dI/dm = W, dI/dox = m 40/(7 pi h^4) (w'(q)/q) ox, and with a
 // world-space size (radius not clamped) dI/dh = m 40/(7 pi h^3)
@@ -1368,6 +1487,11 @@ lod_status splat_layout(uint64_t max_points, const lod_camera &cam, const splat_
   return LOD_OK;
 }
 
+// Whether a source carries per-point world radii (the cubic blob's pixel
+// radius then varies up to the clamp).
+template <class Src> static bool has_point_radii(const Src &) { return false; }
+static bool has_point_radii(const InterpSrc &s) { return s.ha != nullptr; }
+
 // Binning, accumulation and the final slice sums for any point source and
 // record form.  image_aux receives the attribute channel (RecT carrying one).
 template <class Src, class RecT>
@@ -1435,10 +1559,19 @@ static lod_status launch_splat_src(const Src &src, bool any, const lod_camera &c
   LOD_LAUNCH(k_slice_table, dim3((nt + 255) / 256), dim3(256), 0, st, toff, tcount, soff, nt, stab, L.max_slices);
   const unsigned agrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(16384, L.max_slices));
   if (any) {
-    if constexpr (RecInfo<RecT>::cubic)
-      LOD_LAUNCH(k_accumulate_cubic<RecT>, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial,
-                 partial_aux, L.max_slices, L.max_pairs);
-    else
+    if constexpr (RecInfo<RecT>::cubic) {
+      // narrow blobs take the windowed form (same bits, fewer idle lanes)
+      const float hmax = (c.Fhw > 0.0f || has_point_radii(src)) ? lodh::BLOB_H_MAX : c.hpx;
+      if (hmax < 1.9f)
+        LOD_LAUNCH((k_accumulate_cubic_win<RecT, 4>), dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c,
+                   partial, partial_aux, L.max_slices, L.max_pairs);
+      else if (hmax < 3.9f)
+        LOD_LAUNCH((k_accumulate_cubic_win<RecT, 8>), dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c,
+                   partial, partial_aux, L.max_slices, L.max_pairs);
+      else
+        LOD_LAUNCH(k_accumulate_cubic<RecT>, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial,
+                   partial_aux, L.max_slices, L.max_pairs);
+    } else
       LOD_LAUNCH(k_accumulate<RecT>, dim3(agrid), dim3(PT), 0, st, stab, soff, nt, rec, c, partial, partial_aux,
                  L.max_slices, L.max_pairs);
   }

@@ -34,7 +34,9 @@ def _cams(W, H):
     return out
 
 
-@pytest.mark.parametrize("h", [1.0, 2.5, 6.0, 16.0])
+# radii below 1.9 and 3.9 pixels take the windowed accumulation (4 and 8
+# pixel windows), larger ones the gather form: both sides of each threshold
+@pytest.mark.parametrize("h", [1.0, 1.5, 1.89, 1.95, 2.5, 3.89, 3.95, 6.0, 16.0])
 def test_cubic_fixed_radius_matches_oracle(h):
     s = synth.small_clustered(30000, 401)
     d = to_dev(s)
@@ -69,19 +71,21 @@ def test_cubic_rejects_world_radius_in_orthographic_view():
         lib.splat(*to_dev(s), lib.Camera.ortho(32, 32), blob=lib.Blob.cubic(h_px=17.0))
 
 
-@pytest.mark.parametrize("blob", ["gauss", "cubic"])
+@pytest.mark.parametrize("blob", ["gauss", "cubic", "cubic-1.5", "cubic-5"])
 def test_attribute_channel_matches_oracle(blob):
-    """The second channel sum m a W for a random colour attribute in [0, 1)."""
+    """The second channel sum m a W for a random colour attribute in [0, 1)
+    (cubic radii 2, 1.5 and 5 pixels: both windowed forms and the gather)."""
     import torch
     s = synth.small_clustered(40000, 404)
     a = np.random.default_rng(3).random(s.n).astype(np.float32)
     d = to_dev(s)
     for name, cam, ocam in _cams(160, 120)[:2]:
-        b = lib.Blob.cubic(h_px=2.0) if blob == "cubic" else None
+        hpx = {"cubic": 2.0, "cubic-1.5": 1.5, "cubic-5": 5.0}.get(blob)
+        b = lib.Blob.cubic(h_px=hpx) if hpx else None
         img, aimg = lib.splat_aux(*d, torch.from_numpy(a).cuda(), cam, blob=b)
         plain = lib.splat(*d, cam, blob=b)
-        if blob == "cubic":
-            ref, aref = ocubic.render(ocam, s.x, s.y, s.z, s.m, h_px=2.0, aux=a)
+        if hpx:
+            ref, aref = ocubic.render(ocam, s.x, s.y, s.z, s.m, h_px=hpx, aux=a)
         else:
             ref = osplat.render(ocam, s.x, s.y, s.z, s.m)
             aref = osplat.render(ocam, s.x, s.y, s.z, (s.m.astype(np.float64) * a).astype(np.float32))
