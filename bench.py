@@ -150,10 +150,24 @@ def cpu_baseline(snap, cfg, sample: int, alpha: int, repeats: int):
     """Time the CPU oracle (build + cut + LOD render, numpy, one thread) on the
     first `sample` particles; median of `repeats` runs."""
     import statistics
+    from threadpoolctl import threadpool_limits
+    sub = snap.subset(min(sample, snap.n))
+    # numpy's thread pools held to one thread: the oracle runs on one core
+    with threadpool_limits(limits=1):
+        times = _time_oracle(sub, cfg, alpha, repeats)
+    dt = statistics.median(times)
+    model, avail = host_cpu()
+    whole = "all" if sub.n == snap.n else f"the first {sub.n:,} of {snap.n:,}"
+    return {"value": sub.n / dt / 1e6, "unit": "Mparticles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{whole} particles of the same (shuffled) snapshot, same n and D; numpy oracle build + "
+                       f"cut + orthographic LOD render, single thread, median of {repeats}: {dt:.1f} s"),
+            "cpu_model": model, "host_cpus_available": avail}
+
+
+def _time_oracle(sub, cfg, alpha, repeats):
     from oracle import cut as ocut
     from oracle import lod as olod
     from oracle import splat as osplat
-    sub = snap.subset(min(sample, snap.n))
     times = []
     for _ in range(repeats):
         t0 = time.perf_counter()
@@ -163,13 +177,7 @@ def cpu_baseline(snap, cfg, sample: int, alpha: int, repeats: int):
         px, py, pz, pm = olod.decoded_points(tr, c)
         osplat.render(cam, px, py, pz, pm)
         times.append(time.perf_counter() - t0)
-    dt = statistics.median(times)
-    model, avail = host_cpu()
-    whole = "all" if sub.n == snap.n else f"the first {sub.n:,} of {snap.n:,}"
-    return {"value": sub.n / dt / 1e6, "unit": "Mparticles/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{whole} particles of the same (shuffled) snapshot, same n and D; numpy oracle build + "
-                       f"cut + orthographic LOD render, single thread, median of {repeats}: {dt:.1f} s"),
-            "cpu_model": model, "host_cpus_available": avail}
+    return times
 
 
 def lod_sweep(tree, full_imgs, cams, taus, n, max_draw, sel_ws, lod_ws, N):
@@ -379,7 +387,8 @@ def main():
         build_kernels.add(name)
     # build wall time on the stream, per build (the density kernel overlaps the
     # tree construction on a second stream, so kernel times do not add up to it)
-    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(max(20, args.steps))]
     torch.cuda.synchronize()
     for a, b in bev:
         a.record(stream)
