@@ -986,24 +986,30 @@ struct Segs {
   uint32_t coct[9];
 };
 
-__device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArgs &t, uint32_t v, Segs &g) {
+// A node's children's fields, loaded by one lane each so that the loads of
+// all children are in flight together.
+struct Children {
+  uint64_t pc[8], pb[8], ptb[8];
+  uint32_t sel[8], wit[8], oct[8];
+  double m[8];
+};
+
+__device__ __forceinline__ void build_segments(const BuildArgs &a, const TreeArgs &t, uint32_t v, uint32_t fc,
+                                               int nk, const Children &ch, Segs &g) {
   const uint32_t n = a.n;
-  const uint32_t fc = t.first_child[v];
   uint32_t ns = 0;
   if (fc == NONE) {
     g.base[0] = t.part_begin[v]; g.len[0] = (uint32_t)t.part_count[v]; g.is_list[0] = 0; ns = 1;
   } else {
-    const int nk = __popc((uint32_t)t.child_mask[v]);
     for (int k = 0; k < nk; ++k) {
-      const uint32_t u = fc + k;
-      if (t.part_count[u] > n) {
-        g.base[ns] = (uint64_t)t.sel_idx[u] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
-        g.cwit[ns] = t.wit[u]; g.cob[ns] = t.pt_begin[u]; g.coct[ns] = (uint32_t)(t.prefix[u] & 7u);
+      if (ch.pc[k] > n) {
+        g.base[ns] = (uint64_t)ch.sel[k] * (n + 1); g.len[ns] = n + 1; g.is_list[ns] = 1;
+        g.cwit[ns] = ch.wit[k]; g.cob[ns] = ch.ptb[k]; g.coct[ns] = ch.oct[k];
         ++ns;
       } else if (ns > 0 && !g.is_list[ns - 1]) {
-        g.len[ns - 1] += (uint32_t)t.part_count[u];   // siblings are adjacent in sorted order
+        g.len[ns - 1] += (uint32_t)ch.pc[k];   // siblings are adjacent in sorted order
       } else {
-        g.base[ns] = t.part_begin[u]; g.len[ns] = (uint32_t)t.part_count[u]; g.is_list[ns] = 0;
+        g.base[ns] = ch.pb[k]; g.len[ns] = (uint32_t)ch.pc[k]; g.is_list[ns] = 0;
         ++ns;
       }
     }
@@ -1189,6 +1195,7 @@ __device__ double row_sum_fixed(const double *row, uint32_t n, double *cs, doubl
 __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted &s, const SelArgs &sa,
                             uint32_t v) {
   __shared__ Segs g;
+  __shared__ Children ch;
   __shared__ uint32_t hist[KBINS];
   __shared__ uint64_t ck[SMALL];
   __shared__ uint32_t cidx[SMALL];
@@ -1208,16 +1215,29 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
   const uint32_t n = a.n;
   const int BS = blockDim.x;
   const uint32_t W = BS / WAVE, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  if (threadIdx.x == 0) {
-    build_segments(a, t, v, g);
-    // an internal node's float64 mass: its children's, summed in octant order
-    // (read back by this block after the barriers below)
+  if (threadIdx.x < WAVE) {
     const uint32_t fc = t.first_child[v];
-    if (fc != NONE) {
-      const int nk = __popc((uint32_t)t.child_mask[v]);
-      double M = 0.0;
-      for (int k = 0; k < nk; ++k) M += t.node_mass[fc + k];
-      t.node_mass[v] = M;
+    const int nk = fc == NONE ? 0 : __popc((uint32_t)t.child_mask[v]);
+    if ((int)threadIdx.x < nk) {
+      const uint32_t u = fc + threadIdx.x;
+      ch.pc[threadIdx.x] = t.part_count[u]; ch.pb[threadIdx.x] = t.part_begin[u];
+      ch.ptb[threadIdx.x] = t.pt_begin[u]; ch.sel[threadIdx.x] = t.sel_idx[u];
+      ch.wit[threadIdx.x] = t.wit[u]; ch.oct[threadIdx.x] = (uint32_t)(t.prefix[u] & 7u);
+      ch.m[threadIdx.x] = t.node_mass[u];
+    }
+    // the lanes' LDS writes before lane 0's reads (one wave)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (threadIdx.x == 0) {
+      build_segments(a, t, v, fc, nk, ch, g);
+      // an internal node's float64 mass: its children's, summed in octant
+      // order (read back by this block after the barriers below)
+      if (fc != NONE) {
+        double M = 0.0;
+        for (int k = 0; k < nk; ++k) M += ch.m[k];
+        t.node_mass[v] = M;
+      }
     }
   }
   for (int i = threadIdx.x; i < KBINS; i += BS) hist[i] = 0;
@@ -1369,9 +1389,23 @@ __device__ void select_node(const BuildArgs &a, const TreeArgs &t, const Sorted 
     const uint64_t Ke = ck[e];
     const uint32_t Ie = cidx[e];
     uint32_t rank = 0;
-    for (uint32_t f = 0; f < cc; ++f) {
-      const uint64_t Kf = ck[f];
-      rank += (Kf < Ke || (Kf == Ke && cidx[f] < Ie)) ? 1u : 0u;
+    // eight entries per step, every read issued before any compare (clamped
+    // indices, masked counts), and no branches: the loop is bound by LDS
+    // throughput instead of one read's latency per entry
+    for (uint32_t f0 = 0; f0 < cc; f0 += 8) {
+      uint64_t Kf[8];
+      uint32_t If[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t f = min(f0 + (uint32_t)u, cc - 1);
+        Kf[u] = ck[f];
+        If[u] = cidx[f];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool lt = (Kf[u] < Ke) | ((Kf[u] == Ke) & (If[u] < Ie));
+        rank += (lt & (f0 + (uint32_t)u < cc)) ? 1u : 0u;
+      }
     }
     if (rank == r) { sh_kt = Ke; sh_it = Ie; sh_pt = cpos[e]; }
     if (rank <= r) atomicAdd(&pcnt[cpart[e]], 1u);
