@@ -1640,7 +1640,11 @@ __global__ __launch_bounds__(1024) void k_select_level(BuildArgs a, TreeArgs t, 
   for (uint32_t r = r0 + blockIdx.x; r < r1; r += G) {
     const uint32_t v = t.sel_node[r];
     if (v == NONE || v < b || v >= e || t.part_count[v] <= a.n) continue;
+    // the selecting waves ahead of the copying ones in each CU's instruction
+    // arbitration (the level ends with its last node, not with the copy)
+    __builtin_amdgcn_s_setprio(2);
     select_node(a, t, s, sa, v);
+    __builtin_amdgcn_s_setprio(0);
     if (done && threadIdx.x == 0) atomicAdd(&done[d], 1u);
   }
   if (!leaf_ctl) return;
