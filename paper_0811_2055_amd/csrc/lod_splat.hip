@@ -136,7 +136,9 @@ __device__ __forceinline__ bool axis_range(const Cam &c, float t, uint32_t size,
 // within the point, lane).
 
 constexpr int BW = 64;              // binning block: one wave, one unit
-constexpr int BR = 8;               // rounds of 64 points loaded together
+constexpr int BR = 8;               // rounds of 64 points loaded together by the count pass
+constexpr int BR_FILL = 16;         // and by the fill pass (measured: 1.67 vs 1.78 ms at 150 M points;
+                                    // sixteen in the count pass cost it 0.3 ms)
 
 // decoded float32 coordinate of a stored point (cell coordinate c at depth d,
 // 16-bit offset q): centre of the quantisation cell, exact in float32
@@ -468,17 +470,18 @@ __device__ __forceinline__ uint32_t bin_unit(const Src &src, const Cam &c, uint3
   if (b >= e) return 0;
   typename Src::Cursor cur;
   cur.begin(src, b, e);
-  for (uint64_t k0 = b; k0 < e; k0 += (uint64_t)BR * WAVE) {
-    typename Src::Addr ad[BR];
+  constexpr int R = FILL ? BR_FILL : BR;
+  for (uint64_t k0 = b; k0 < e; k0 += (uint64_t)R * WAVE) {
+    typename Src::Addr ad[R];
 #pragma unroll
-    for (int r = 0; r < BR; ++r) {
+    for (int r = 0; r < R; ++r) {
       const uint64_t k = k0 + (uint64_t)r * WAVE + lane;
       ad[r] = cur.resolve(src, k, k < e);
       cur.end_round(src);
     }
-    float px[BR], py[BR], pz[BR], pm[BR], pa[BR], ph[BR];
+    float px[R], py[R], pz[R], pm[R], pa[R], ph[R];
 #pragma unroll
-    for (int r = 0; r < BR; ++r) {
+    for (int r = 0; r < R; ++r) {
       const uint64_t k = k0 + (uint64_t)r * WAVE + lane;
       cur.fetch(src, ad[r], k < e, px[r], py[r], pz[r], pm[r]);
       pa[r] = (FILL && RecInfo<RecT>::aux) ? cur.attr(src, ad[r]) : 0.0f;
@@ -489,14 +492,14 @@ __device__ __forceinline__ uint32_t bin_unit(const Src &src, const Cam &c, uint3
       // flagged ones staged in sequence order (wave ballot ranks).  A wave's
       // points are mostly consecutive stored points, so its flag loads fall
       // on one or two words.
-      uint64_t pid[BR];
-      uint32_t word[BR];
+      uint64_t pid[R];
+      uint32_t word[R];
 #pragma unroll
-      for (int r = 0; r < BR; ++r) pid[r] = cur.point_index(src, ad[r]);
+      for (int r = 0; r < R; ++r) pid[r] = cur.point_index(src, ad[r]);
 #pragma unroll
-      for (int r = 0; r < BR; ++r) word[r] = src.hl_word(pid[r]);
+      for (int r = 0; r < R; ++r) word[r] = src.hl_word(pid[r]);
 #pragma unroll
-      for (int r = 0; r < BR; ++r) {
+      for (int r = 0; r < R; ++r) {
         const bool in = k0 + (uint64_t)r * WAVE + lane < e && src.hl_test(pid[r], word[r]);
         const uint64_t mask = __ballot(in);
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -508,13 +511,13 @@ __device__ __forceinline__ uint32_t bin_unit(const Src &src, const Cam &c, uint3
         staged += (uint32_t)__popcll(mask);
       }
     }
-    Blob blobs[BR];
+    Blob blobs[R];
 #pragma unroll
-    for (int r = 0; r < BR; ++r)
+    for (int r = 0; r < R; ++r)
       blobs[r] = make_blob(c, k0 + (uint64_t)r * WAVE + lane < e, px[r], py[r], pz[r], pm[r], pa[r], ph[r]);
     // pairs in the order (round, tile row, tile column, lane)
 #pragma unroll
-    for (int r = 0; r < BR; ++r) {
+    for (int r = 0; r < R; ++r) {
       const Blob &bl = blobs[r];
       for (int dy = 0; __ballot(dy < bl.nty); ++dy) {
         for (int dx = 0; __ballot(dy < bl.nty && dx < bl.ntx); ++dx) {
