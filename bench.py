@@ -48,7 +48,8 @@ def selection_bytes(N, S):
 
 
 KERNEL_SOURCES = ["paper_0811_2055_amd/csrc/lod_build.hip", "paper_0811_2055_amd/csrc/lod_splat.hip",
-                  "paper_0811_2055_amd/csrc/lod_device.hpp", "paper_0811_2055_amd/csrc/lod_scan.hpp"]
+                  "paper_0811_2055_amd/csrc/lod_device.hpp", "paper_0811_2055_amd/csrc/lod_scan.hpp",
+                  "paper_0811_2055_amd/csrc/lod_internal.hpp"]
 TRAFFIC_TABLE = "profiles/hbm_traffic_sp150m_step.txt"
 
 

@@ -42,7 +42,7 @@ struct SplatLayout {
 
 constexpr int SPLAT_TS = 16;           // tile edge in pixels
 constexpr uint32_t SPLAT_MAX_TILES = 8192;
-constexpr uint32_t SPLAT_SLICE = 2048; // points per accumulation slice
+constexpr uint32_t SPLAT_SLICE = 4096; // points per accumulation slice (4096: LOD splat 5.05 vs 5.11 ms at 2048)
 constexpr uint32_t SPLAT_MAX_CHUNKS = 64;
 constexpr float BLOB_H_MIN = 1.0f;     // cubic blob: clamp of a projected world radius, pixels
 constexpr float BLOB_H_MAX = 16.0f;
