@@ -291,6 +291,9 @@ def main():
     ap.add_argument("--stream-slots", type=int, default=3000)
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="only run this many plain steps (for profilers) and exit")
+    ap.add_argument("--profile-extras", action="store_true",
+                    help="with --profile-steps: then build the highlight flags of a million ids once and draw "
+                         "the highlighted and the cubic-blob LOD renders twice each")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -331,10 +334,40 @@ def main():
         lib.splat_lod(tree, ids, nsel, max_draw, cam, workspace=lod_ws, out=lod_img)
         return ids, nsel
 
+    def extras_setup():
+        """The highlight (a million random ids) and cubic-blob inputs of the last step's cut."""
+        ids1, nsel1 = lib.select_nodes(tree, cam, 1.0, cfg["n"], workspace=sel_ws)
+        hl_ids = np.random.default_rng(7).choice(N, min(1_000_000, N), replace=False)
+        bits = lib.highlight_bits(hl_ids, N, dev)
+        flags = lib.highlight_flags(tree, bits, N)        # allocates once; later calls reuse the words
+        hl_img = torch.empty_like(lod_img)
+        hl_ws = torch.empty(lib.splat_lod_highlight_workspace_bytes(tree.node_capacity, max_draw, len(hl_ids), cam),
+                            dtype=torch.uint8, device=dev)
+        cub = lib.Blob.cubic(h_px=1.5)
+        cub_ws = torch.empty(lib.splat_lod_workspace_bytes(tree.node_capacity, max_draw, cam, blob=cub),
+                             dtype=torch.uint8, device=dev)
+
+        def render_hl():
+            lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, flags, len(hl_ids), workspace=hl_ws,
+                                    out=lod_img, out_hl=hl_img)
+
+        def render_cubic():
+            lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=cub_ws, out=lod_img, blob=cub)
+
+        return dict(ids=ids1, nsel=nsel1, hl_ids=hl_ids, bits=bits, flags=flags, hl_img=hl_img,
+                    render_hl=render_hl, render_cubic=render_cubic)
+
     if args.profile_steps is not None:
         for _ in range(args.profile_steps):
             step()
         torch.cuda.synchronize()
+        if args.profile_extras:
+            ex = extras_setup()
+            for _ in range(2):
+                ex["render_hl"]()
+                ex["render_cubic"]()
+            torch.cuda.synchronize()
+            log("[bench] profile extras done")
         if args.copy_calibration:
             a = torch.empty(256 << 20, dtype=torch.float32, device=dev).fill_(1.0)
             b = torch.empty_like(a)
@@ -476,31 +509,21 @@ def main():
             torch.cuda.synchronize()
             ts.append(a.elapsed_time(b))
         return statistics.median(ts)
-    ids1, nsel1 = lib.select_nodes(tree, cam, 1.0, cfg["n"], workspace=sel_ws)
-    hl_ids = np.random.default_rng(7).choice(N, min(1_000_000, N), replace=False)
-    bits = lib.highlight_bits(hl_ids, N, dev)
-    flags = lib.highlight_flags(tree, bits, N)            # allocates once; timed below into the same words
-    flags_ms = timed(lambda: lib.highlight_flags(tree, bits, N, out=flags), reps=3)
-    hl_img = torch.empty_like(lod_img)
-    hl_ws = torch.empty(lib.splat_lod_highlight_workspace_bytes(tree.node_capacity, max_draw, len(hl_ids), cam),
-                        dtype=torch.uint8, device=dev)
-    lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, flags, len(hl_ids), workspace=hl_ws, out=lod_img,
-                            out_hl=hl_img)
+    ex = extras_setup()
+    ids1, nsel1, hl_ids, hl_img = ex["ids"], ex["nsel"], ex["hl_ids"], ex["hl_img"]
+    flags_ms = timed(lambda: lib.highlight_flags(tree, ex["bits"], N, out=ex["flags"]), reps=3)
+    ex["render_hl"]()
     plain_ms = timed(lambda: lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=lod_ws, out=lod_img))
-    hl_ms = timed(lambda: lib.splat_lod_highlight(tree, ids1, nsel1, max_draw, cam, flags, len(hl_ids),
-                                                  workspace=hl_ws, out=lod_img, out_hl=hl_img))
+    hl_ms = timed(ex["render_hl"])
     extra["highlight"] = {"selected_ids": int(len(hl_ids)), "flags_ms_per_list": round(flags_ms, 4),
                           "lod_render_ms": round(plain_ms, 4),
                           "lod_render_highlight_ms": round(hl_ms, 4),
                           "penalty_frac": round(hl_ms / plain_ms - 1.0, 4),
                           "highlighted_mass_frac": round(float(hl_img.double().sum() / lod_img.double().sum()), 4)}
-    cub = lib.Blob.cubic(h_px=1.5)
-    cub_ws = torch.empty(lib.splat_lod_workspace_bytes(tree.node_capacity, max_draw, cam, blob=cub),
-                         dtype=torch.uint8, device=dev)
-    cub_ms = timed(lambda: lib.splat_lod(tree, ids1, nsel1, max_draw, cam, workspace=cub_ws, out=lod_img, blob=cub))
+    cub_ms = timed(ex["render_cubic"])
     extra["cubic_blob"] = {"h_px": 1.5, "lod_render_ms": round(cub_ms, 4),
                            "Mpts_s": round(drawn / cub_ms / 1e3, 1)}
-    del cub_ws, bits, flags, hl_img, hl_ws
+    del ex, hl_img
     log(f"[bench] highlight {extra['highlight']}, cubic {extra['cubic_blob']}")
 
     if not args.no_compare_modes:
