@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--stream-slots", type=int, default=3000)
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="only run this many plain steps (for profilers) and exit")
+    ap.add_argument("--pipelined", action="store_true",
+                    help="also time steps alternating over two independent step pipelines on two streams")
     ap.add_argument("--profile-extras", action="store_true",
                     help="with --profile-steps: then build the highlight flags of a million ids once and draw "
                          "the highlighted and the cubic-blob LOD renders twice each")
@@ -551,6 +553,39 @@ def main():
                                     "level, 2: one persistent launch; default grids, wall time with a "
                                     "synchronisation, median of 5 (mode 0: one run); outputs byte-identical")
         log(f"[bench] build ms by schedule: {by_mode}")
+
+    if args.pipelined:
+        # Two independent step pipelines (own tree, workspaces and image; two
+        # streams of default priority), steps alternating between them: the
+        # latency-bound top of one build's selection overlaps the other's work.
+        # Each step is still a whole build + cut + LOD render of the snapshot.
+        other = lib.Builder(N, builder.params, dev)
+        o_sel = torch.empty_like(sel_ws)
+        o_lod = torch.empty_like(lod_ws)
+        o_img = torch.empty_like(lod_img)
+        pipes = [(builder, sel_ws, lod_ws, lod_img, torch.cuda.Stream()),
+                 (other, o_sel, o_lod, o_img, torch.cuda.Stream())]
+
+        def pipe_step(i):
+            bb, sw, lw, img, st = pipes[i % 2]
+            with torch.cuda.stream(st):
+                bb.build(x, y, z, m)
+                ids_p, nsel_p = lib.select_nodes(bb.tree, cam, 1.0, cfg["n"], workspace=sw)
+                lib.splat_lod(bb.tree, ids_p, nsel_p, max_draw, cam, workspace=lw, out=img)
+        for i in range(4):
+            pipe_step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(2 * args.steps):
+            pipe_step(i)
+        torch.cuda.synchronize()
+        p_ms = (time.perf_counter() - t0) * 1e3 / (2 * args.steps)
+        same = bool(torch.equal(lod_img, o_img))
+        extra["pipelined_two_streams"] = {"ms_per_step": round(p_ms, 4), "Mparticles_s": round(N / p_ms / 1e3, 1),
+                                          "steps": 2 * args.steps, "images_equal": same}
+        log(f"[bench] two pipelines: {p_ms:.3f} ms/step, images equal {same}")
+        del other, o_sel, o_lod, o_img, pipes
+        torch.cuda.empty_cache()
 
     if args.stream:
         tree._src = (x, y, z, m)
