@@ -193,10 +193,11 @@ lod_status lod_build_plan(const lod_input *in, const lod_params *p,
  * synchronisation; safe to capture in a HIP graph.  The density step runs on
  * a second stream of the device owned by the library (created by the first
  * call made outside stream capture), forked from and joined back into
- * `stream`; builds on one device must therefore not be issued from several
- * host threads at once.  workspace: device, >= the planned size, 256-byte
- * aligned.  LOD_ECAPACITY when out->node_capacity or point_capacity is below
- * the plan's bound. */
+ * `stream` (the fork is taken under a lock, so builds on several streams may
+ * be issued from several host threads; they share that second stream, each
+ * with its own workspace and tree).  workspace: device, >= the planned size,
+ * 256-byte aligned.  LOD_ECAPACITY when out->node_capacity or point_capacity
+ * is below the plan's bound. */
 lod_status lod_build(const lod_input *in, const lod_params *p, void *workspace,
                      size_t workspace_bytes, lod_tree *out, lod_stream_t stream);
 

@@ -1881,6 +1881,11 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
 struct SideStream {
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // Held from the fork event's record on the caller's stream to the side
+  // stream's wait on it: builds issued by several host threads then each
+  // fork from their own stream.  The join needs no lock: a later record of
+  // it lies later on the side stream, so waiting on it only waits longer.
+  std::mutex mu;
 };
 
 static SideStream *side_stream(hipStream_t st) {
@@ -1964,6 +1969,7 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   SideStream *side = side_stream(st);
   hipStream_t dst = st;
   if (side) {
+    std::lock_guard<std::mutex> lk(side->mu);
     if (hipEventRecord(side->fork, st) != hipSuccess || hipStreamWaitEvent(side->s, side->fork, 0) != hipSuccess)
       return LOD_EDEVICE;
     dst = side->s;

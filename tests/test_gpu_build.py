@@ -145,6 +145,76 @@ def test_repeat_runs_identical():
             assert np.array_equal(v, h2[k]), k
 
 
+def test_builds_on_two_streams_match_builds_alone():
+    """Two builders on two caller streams, launched alternately without
+    waiting: the library's own second stream (the density kernel's), forked
+    from and joined into each caller's stream, serves both.  Every tree equals
+    the one built alone, in the per-level and the persistent schedule."""
+    import torch
+    sa, sb = synth.small_clustered(300000, 41), synth.small_clustered(220000, 42)
+    da, db = to_dev(sa), to_dev(sb)
+    for mode in (1, 2):
+        p = lib.BuildParams(n=400, max_depth=7, seed=3, mode=mode)
+        alone = []
+        for s, d in ((sa, da), (sb, db)):
+            b = lib.Builder(s.n, p)
+            alone.append(b.build(*d).host())
+        torch.cuda.synchronize()
+        builders = [lib.Builder(sa.n, p), lib.Builder(sb.n, p)]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        for _ in range(3):
+            for b, d, st in zip(builders, (da, db), streams):
+                with torch.cuda.stream(st):
+                    b.build(*d)
+        torch.cuda.synchronize()
+        for b, ref in zip(builders, alone):
+            h = b.tree.host()
+            for k, v in ref.items():
+                if isinstance(v, np.ndarray):
+                    assert np.array_equal(v, h[k]), (mode, k)
+                else:
+                    assert v == h[k], (mode, k)
+
+
+def test_builds_from_two_host_threads_match_builds_alone():
+    """Two host threads, each building on its own stream (the library's fork
+    onto its second stream is taken under a lock): every tree equals the one
+    built alone."""
+    import threading
+    import torch
+    sa, sb = synth.small_clustered(300000, 43), synth.small_clustered(260000, 44)
+    da, db = to_dev(sa), to_dev(sb)
+    p = lib.BuildParams(n=400, max_depth=7, seed=6, mode=1)
+    alone = [lib.Builder(s.n, p).build(*d).host() for s, d in ((sa, da), (sb, db))]
+    builders = [lib.Builder(sa.n, p), lib.Builder(sb.n, p)]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(b, d):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for _ in range(4):
+                    b.build(*d)
+            st.synchronize()
+        except Exception as e:          # reported by the main thread
+            errors.append(e)
+    threads = [threading.Thread(target=work, args=(b, d)) for b, d in zip(builders, (da, db))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for b, ref in zip(builders, alone):
+        h = b.tree.host()
+        for k, v in ref.items():
+            if isinstance(v, np.ndarray):
+                assert np.array_equal(v, h[k]), k
+            else:
+                assert v == h[k], k
+
+
 def test_batch_matches_oracle():
     import torch
     parts = [synth.small_clustered(3000, 31), synth.uniform(0, 1), synth.small_clustered(5000, 32),
