@@ -224,3 +224,61 @@ def test_thinned_cut_sampled_pixels(c3):
     err = np.abs(got[ok] - want[ok]) / want[ok]
     log(f"thinned cut pixels: max relative error {err.max():.2e} over {ok.sum()} pixels")
     assert err.max() <= 1e-5
+
+
+def test_cubic_lod_render_block_at_full_size(c3):
+    """The cubic-blob LOD render that the benchmark times (orthographic
+    1024^2, tau = 1 px: every leaf drawn whole, h = 1.5 px, the windowed
+    accumulation) on a 16 x 16 pixel block of the heaviest depth-4 column,
+    against the oracle: every particle near the block is a point of its leaf
+    (the shallowest cell holding at most n particles, from the particle counts
+    of each depth), quantised at the leaf's depth and decoded; the cubic
+    oracle sums the block's pixels in float64.  The particles taken reach 3 px
+    beyond the block, past any blob that touches it."""
+    from oracle import cubic as ocubic
+    s, d, b, tree, h, keys_D = c3
+    n, D, W, hpx = 16000, 8, 1024, 1.5
+    cam = lib.Camera.ortho(W, W)
+    ids, nsel = lib.select_nodes(tree, cam, 1.0, n)
+    k = int(lib._to_numpy(nsel)[0])
+    cut = lib._to_numpy(ids[:k]).astype(np.int64)
+    assert np.all(h["first_child"][cut] == lib.NONE)      # tau 1 draws the leaves
+    assert int(h["pt_count"][cut].astype(np.int64).sum()) == s.n
+    img = lib.splat_lod(tree, ids, nsel, s.n, cam, blob=lib.Blob.cubic(h_px=hpx)).cpu().numpy()
+    # the block: the centre of the heaviest depth-4 (x, y) column
+    c4x = olod.cell_coords(s.x, 4); c4y = olod.cell_coords(s.y, 4)
+    col = np.bincount(c4x + 16 * c4y, minlength=256)
+    cx, cy = int(np.argmax(col) % 16), int(np.argmax(col) // 16)
+    i0, j0 = cx * 64 + 24, cy * 64 + 24
+    x64, y64 = s.x.astype(np.float64) * W, s.y.astype(np.float64) * W
+    near = np.nonzero((x64 > i0 - 3) & (x64 < i0 + 19) & (y64 > j0 - 3) & (y64 < j0 + 19))[0]
+    log(f"cubic block ({i0}, {j0}): {len(near)} particles nearby")
+    # each nearby particle's leaf depth: the shallowest depth whose cell holds <= n
+    leaf_d = np.full(len(near), D, dtype=np.int64)
+    kn = keys_D[near]
+    for dd in range(D - 1, -1, -1):
+        sh = np.uint64(3 * (D - dd))
+        counts = np.bincount((keys_D >> sh).astype(np.int64), minlength=1 << (3 * dd))
+        small = counts[(kn >> sh).astype(np.int64)] <= n
+        leaf_d[small] = dd
+    # each leaf's points: quantised relative to the leaf's cell, then decoded
+    ld = leaf_d.astype(np.uint64)
+    leaf_key = (ld << np.uint64(60)) | (kn >> (np.uint64(3) * (np.uint64(D) - ld)))
+    uniq, inv = np.unique(leaf_key, return_inverse=True)
+    X = np.empty(len(near), np.float32); Y = np.empty_like(X); Z = np.empty_like(X)
+    order = np.argsort(inv, kind="stable")
+    bounds = np.searchsorted(inv[order], np.arange(len(uniq) + 1))
+    for u in range(len(uniq)):
+        at = order[bounds[u]:bounds[u + 1]]
+        dd = int(leaf_d[at[0]])
+        for dst, a in zip((X, Y, Z), (s.x, s.y, s.z)):
+            c = int(olod.cell_coords(a[near[at[:1]]], dd)[0])
+            dst[at] = olod.decode(olod.quantise(a[near[at]], c, dd), c, dd)
+    log(f"cubic block: {len(uniq)} leaves")
+    want = ocubic.render(osplat.Camera(0, W, W), X, Y, Z, s.m[near], h_px=hpx)[j0:j0 + 16, i0:i0 + 16]
+    got = img[j0:j0 + 16, i0:i0 + 16].astype(np.float64)
+    assert np.all((want > 0) | (got == 0))
+    ok = want > 0
+    err = np.abs(got[ok] - want[ok]) / want[ok]
+    log(f"cubic block: max relative error {err.max():.2e} over {ok.sum()} pixels")
+    assert ok.sum() > 200 and err.max() <= 1e-5
