@@ -226,6 +226,34 @@ def test_thinned_cut_sampled_pixels(c3):
     assert err.max() <= 1e-5
 
 
+def _leaf_points(s, keys_D, near, n, D):
+    """Decoded positions of particles `near` as points of their leaves (the
+    tau = 1 cut draws every leaf whole): each particle's leaf is the shallowest
+    cell on its path holding at most n particles (depth D at the deepest), and
+    its 16-bit codes are relative to that cell."""
+    leaf_d = np.full(len(near), D, dtype=np.int64)
+    kn = keys_D[near]
+    for dd in range(D - 1, -1, -1):
+        sh = np.uint64(3 * (D - dd))
+        counts = np.bincount((keys_D >> sh).astype(np.int64), minlength=1 << (3 * dd))
+        small = counts[(kn >> sh).astype(np.int64)] <= n
+        leaf_d[small] = dd
+    ld = leaf_d.astype(np.uint64)
+    leaf_key = (ld << np.uint64(60)) | (kn >> (np.uint64(3) * (np.uint64(D) - ld)))
+    uniq, inv = np.unique(leaf_key, return_inverse=True)
+    X = np.empty(len(near), np.float32); Y = np.empty_like(X); Z = np.empty_like(X)
+    order = np.argsort(inv, kind="stable")
+    bounds = np.searchsorted(inv[order], np.arange(len(uniq) + 1))
+    for u in range(len(uniq)):
+        at = order[bounds[u]:bounds[u + 1]]
+        dd = int(leaf_d[at[0]])
+        for dst, a in zip((X, Y, Z), (s.x, s.y, s.z)):
+            c = int(olod.cell_coords(a[near[at[:1]]], dd)[0])
+            dst[at] = olod.decode(olod.quantise(a[near[at]], c, dd), c, dd)
+    log(f"{len(near)} particles in {len(uniq)} leaves")
+    return X, Y, Z
+
+
 def test_cubic_lod_render_block_at_full_size(c3):
     """The cubic-blob LOD render that the benchmark times (orthographic
     1024^2, tau = 1 px: every leaf drawn whole, h = 1.5 px, the windowed
@@ -253,28 +281,7 @@ def test_cubic_lod_render_block_at_full_size(c3):
     x64, y64 = s.x.astype(np.float64) * W, s.y.astype(np.float64) * W
     near = np.nonzero((x64 > i0 - 3) & (x64 < i0 + 19) & (y64 > j0 - 3) & (y64 < j0 + 19))[0]
     log(f"cubic block ({i0}, {j0}): {len(near)} particles nearby")
-    # each nearby particle's leaf depth: the shallowest depth whose cell holds <= n
-    leaf_d = np.full(len(near), D, dtype=np.int64)
-    kn = keys_D[near]
-    for dd in range(D - 1, -1, -1):
-        sh = np.uint64(3 * (D - dd))
-        counts = np.bincount((keys_D >> sh).astype(np.int64), minlength=1 << (3 * dd))
-        small = counts[(kn >> sh).astype(np.int64)] <= n
-        leaf_d[small] = dd
-    # each leaf's points: quantised relative to the leaf's cell, then decoded
-    ld = leaf_d.astype(np.uint64)
-    leaf_key = (ld << np.uint64(60)) | (kn >> (np.uint64(3) * (np.uint64(D) - ld)))
-    uniq, inv = np.unique(leaf_key, return_inverse=True)
-    X = np.empty(len(near), np.float32); Y = np.empty_like(X); Z = np.empty_like(X)
-    order = np.argsort(inv, kind="stable")
-    bounds = np.searchsorted(inv[order], np.arange(len(uniq) + 1))
-    for u in range(len(uniq)):
-        at = order[bounds[u]:bounds[u + 1]]
-        dd = int(leaf_d[at[0]])
-        for dst, a in zip((X, Y, Z), (s.x, s.y, s.z)):
-            c = int(olod.cell_coords(a[near[at[:1]]], dd)[0])
-            dst[at] = olod.decode(olod.quantise(a[near[at]], c, dd), c, dd)
-    log(f"cubic block: {len(uniq)} leaves")
+    X, Y, Z = _leaf_points(s, keys_D, near, n, D)
     want = ocubic.render(osplat.Camera(0, W, W), X, Y, Z, s.m[near], h_px=hpx)[j0:j0 + 16, i0:i0 + 16]
     got = img[j0:j0 + 16, i0:i0 + 16].astype(np.float64)
     assert np.all((want > 0) | (got == 0))
@@ -282,3 +289,48 @@ def test_cubic_lod_render_block_at_full_size(c3):
     err = np.abs(got[ok] - want[ok]) / want[ok]
     log(f"cubic block: max relative error {err.max():.2e} over {ok.sum()} pixels")
     assert ok.sum() > 200 and err.max() <= 1e-5
+
+
+def test_highlight_at_full_size(c3):
+    """ID highlighting at the benchmark configuration (a million random ids,
+    the tau = 1 cut): the flag of every one of the 229 M stored points equals
+    the membership of its id (numpy over the stored ids), and on a 16 x 16
+    block of the heaviest column the highlight image equals the oracle's
+    Gaussian pixels over the highlighted particles' leaf points near it."""
+    import torch
+    s, d, b, tree, h, keys_D = c3
+    n, D, W, N = 16000, 8, 1024, s.n
+    sel = np.random.default_rng(7).choice(N, 1_000_000, replace=False)
+    bits = lib.highlight_bits(sel, N, "cuda")
+    flags = lib.highlight_flags(tree, bits, N)
+    S = h["n_points"]
+    got = np.unpackbits(lib._to_numpy(flags).view(np.uint8), bitorder="little")[:S].astype(bool)
+    want = np.isin(h["pt_id"], sel)
+    assert np.array_equal(got, want)
+    log(f"flags: {int(want.sum())} of {S} stored points highlighted")
+    cam = lib.Camera.ortho(W, W)
+    ids, nsel = lib.select_nodes(tree, cam, 1.0, n)
+    img = torch.empty((W, W), dtype=torch.float32, device="cuda")
+    hl = torch.empty_like(img)
+    ws = torch.empty(lib.splat_lod_highlight_workspace_bytes(tree.node_capacity, N, len(sel), cam),
+                     dtype=torch.uint8, device="cuda")
+    lib.splat_lod_highlight(tree, ids, nsel, N, cam, flags, len(sel), workspace=ws, out=img, out_hl=hl)
+    hl = hl.cpu().numpy()
+    c4x = olod.cell_coords(s.x, 4); c4y = olod.cell_coords(s.y, 4)
+    col = np.bincount(c4x + 16 * c4y, minlength=256)
+    cx, cy = int(np.argmax(col) % 16), int(np.argmax(col) // 16)
+    i0, j0 = cx * 64 + 24, cy * 64 + 24
+    x64, y64 = s.x.astype(np.float64) * W, s.y.astype(np.float64) * W
+    near = np.nonzero((x64 > i0 - 5) & (x64 < i0 + 21) & (y64 > j0 - 5) & (y64 < j0 + 21))[0]
+    on = np.isin(near, sel)
+    X, Y, Z = _leaf_points(s, keys_D, near[on], n, D)
+    pi, pj = np.meshgrid(np.arange(i0, i0 + 16), np.arange(j0, j0 + 16))
+    pi, pj = pi.ravel(), pj.ravel()
+    want_px = osplat.render_pixels(osplat.Camera(0, W, W), X, Y, Z, s.m[near[on]], pi, pj)
+    got_px = hl[pj, pi].astype(np.float64)
+    assert np.all((want_px > 0) | (got_px == 0))
+    ok = want_px > 0
+    err = np.abs(got_px[ok] - want_px[ok]) / want_px[ok]
+    log(f"highlight block: {int(on.sum())} highlighted particles nearby, max relative error "
+        f"{err.max():.2e} over {ok.sum()} pixels")
+    assert ok.sum() > 50 and err.max() <= 1e-5
