@@ -195,9 +195,12 @@ __global__ __launch_bounds__(TB) void k_upsweep(const uint32_t *__restrict__ key
 // FIRST: the input is the particles themselves (x, y, z, m with ids implicit);
 // keys and fractions come from particle_key.  Otherwise (key, id, fraction,
 // mass) arrays of the previous pass.
+// The fractions ride the sort as 6 bytes per particle: x and y's 16 bits in
+// a 32-bit array, z's in a 16-bit one (18-byte records instead of 20).
 struct ScatterIn {
   const uint32_t *key, *idx;
-  const uint64_t *lo;
+  const uint32_t *lo;
+  const uint16_t *lz;
   const float *x, *y, *z, *m;
 };
 
@@ -205,7 +208,8 @@ template <bool FIRST>
 __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const uint32_t *__restrict__ thist,
                                                  uint64_t n_tiles, ScatterIn in,
                                                  uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
-                                                 uint64_t *__restrict__ lo_out, float *__restrict__ m_out) {
+                                                 uint32_t *__restrict__ lo_out, uint16_t *__restrict__ lz_out,
+                                                 float *__restrict__ m_out) {
   const uint64_t N = a.N;
   constexpr int NW = STB / WAVE;              // waves per block
   constexpr int PER_WAVE = STILE / NW;
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
       const uint64_t e = min(ebase + (uint64_t)r * WAVE, N - 1);
       kk[r] = in.key[e];
       ii[r] = in.idx[e];
-      ll[r] = in.lo[e];
+      ll[r] = (uint64_t)in.lo[e] | ((uint64_t)in.lz[e] << 32);
       mm[r] = in.m[e];
     }
   }
@@ -359,7 +363,10 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
     for (int i = 0; i < SITEMS; ++i) v[i] = stage[i * STB + threadIdx.x];
 #pragma unroll
     for (int i = 0; i < SITEMS; ++i)
-      if ((uint32_t)i * STB + threadIdx.x < tile_n) lo_out[gpos[i]] = v[i];
+      if ((uint32_t)i * STB + threadIdx.x < tile_n) {
+        lo_out[gpos[i]] = (uint32_t)v[i];
+        lz_out[gpos[i]] = (uint16_t)(v[i] >> 32);
+      }
   }
   __syncthreads();
 #pragma unroll
@@ -825,7 +832,8 @@ __global__ void k_ptfinish(BuildArgs a, TreeArgs t) {
 struct Sorted {
   const uint32_t *key;
   const uint32_t *idx;
-  const uint64_t *lo;
+  const uint32_t *lo;   // x and y fractions (16 bits each)
+  const uint16_t *lz;   // z fraction
   const float *m;
   const uint32_t *w;
   const uint16_t *kb;   // log-scale bin of the selection key
@@ -839,7 +847,7 @@ struct PointIn {
 };
 
 __device__ __forceinline__ PointIn read_point(const Sorted &s, uint64_t pos) {
-  return PointIn{s.key[pos], s.idx[pos], s.lo[pos]};
+  return PointIn{s.key[pos], s.idx[pos], (uint64_t)s.lo[pos] | ((uint64_t)s.lz[pos] << 32)};
 }
 
 __device__ __forceinline__ void store_point_pos(const BuildArgs &a, const TreeArgs &t, const PointIn &q,
@@ -1841,7 +1849,8 @@ BuildLayout build_layout(uint64_t N, const lod_params &p, uint32_t n_snap) {
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   L.keyA = take(4 * Np); L.keyB = take(4 * Np);
   L.idxA = take(4 * Np); L.idxB = take(4 * Np);
-  L.loA = take(8 * Np); L.loB = take(8 * Np);
+  L.loA = take(4 * Np); L.loB = take(4 * Np);
+  L.lzA = take(2 * Np); L.lzB = take(2 * Np);
   L.mA = take(4 * Np); L.mB = take(4 * Np);
   L.thist = take(4 * (size_t)RADIX * tiles);
   L.scan32 = take(4 * std::max(scan_tmp_elems<uint32_t>((uint64_t)RADIX * tiles),
@@ -1938,7 +1947,8 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
 
   uint32_t *keyA = (uint32_t *)(W + L.keyA), *keyB = (uint32_t *)(W + L.keyB);
   uint32_t *idxA = (uint32_t *)(W + L.idxA), *idxB = (uint32_t *)(W + L.idxB);
-  uint64_t *loA = (uint64_t *)(W + L.loA), *loB = (uint64_t *)(W + L.loB);
+  uint32_t *loA = (uint32_t *)(W + L.loA), *loB = (uint32_t *)(W + L.loB);
+  uint16_t *lzA = (uint16_t *)(W + L.lzA), *lzB = (uint16_t *)(W + L.lzB);
   float *mA = (float *)(W + L.mA), *mB = (float *)(W + L.mB);
   uint32_t *thist = (uint32_t *)(W + L.thist);
   uint32_t *scan32 = (uint32_t *)(W + L.scan32);
@@ -1952,17 +1962,17 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   // pass 0 reads the particles (keys recomputed, ids implicit) and writes B
   device_scan<uint32_t>(thist, hist_n, scan32, st);
   LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 0, thist, tiles,
-             ScatterIn{nullptr, nullptr, nullptr, in.x, in.y, in.z, in.mass}, keyB, idxB, loB, mB);
-  uint32_t *ks = keyB, *is = idxB; uint64_t *ls = loB; float *ms = mB;
-  uint32_t *kd = keyA, *id = idxA; uint64_t *ld = loA; float *md = mA;
+             ScatterIn{nullptr, nullptr, nullptr, nullptr, in.x, in.y, in.z, in.mass}, keyB, idxB, loB, lzB, mB);
+  uint32_t *ks = keyB, *is = idxB, *ls = loB; uint16_t *zs = lzB; float *ms = mB;
+  uint32_t *kd = keyA, *id = idxA, *ld = loA; uint16_t *zd = lzA; float *md = mA;
   for (int ps = 1; ps < passes; ++ps) {
     LOD_LAUNCH(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
     device_scan<uint32_t>(thist, hist_n, scan32, st);
     LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 8 * ps, thist, tiles,
-               ScatterIn{ks, is, ls, nullptr, nullptr, nullptr, ms}, kd, id, ld, md);
-    std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(ms, md);
+               ScatterIn{ks, is, ls, zs, nullptr, nullptr, nullptr, ms}, kd, id, ld, zd, md);
+    std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(zs, zd); std::swap(ms, md);
   }
-  Sorted s{ks, is, ls, ms, (const uint32_t *)(W + L.w), (const uint16_t *)(W + L.kb)};
+  Sorted s{ks, is, ls, zs, ms, (const uint32_t *)(W + L.w), (const uint16_t *)(W + L.kb)};
 
   // density weights and key bins on the side stream, beside the tree
   // construction; joined before the selection

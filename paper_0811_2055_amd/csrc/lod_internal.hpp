@@ -12,7 +12,7 @@ namespace lodh {
 // Byte offsets of the build workspace arrays (256-byte aligned).
 struct BuildLayout {
   uint64_t tiles, node_cap, point_cap;
-  size_t keyA, keyB, idxA, idxB, loA, loB, mA, mB;
+  size_t keyA, keyB, idxA, idxB, loA, loB, lzA, lzB, mA, mB;
   size_t thist, scan32, scan64;
   size_t w, kb;
   size_t lvl, lsel, cs, sel_idx, sel_node, wit, pend, bflag, bscan, bottom, ctl, leafctl, emit_tot;
