@@ -30,8 +30,8 @@ METRIC = "LOD build Mparticles/s + %HBM roofline; splat Mpts/s; LOD-vs-full imag
 # kernels, point for the splat binning, (point, tile) pair for accumulation).
 KERNEL_BYTES = {
     "k_keygen": 12.0,            # read x,y,z (12); histogram only (masses checked in the first scatter)
-    "k_scatter<true>": 36.0,     # read x,y,z,m (16) write key,id,fraction,mass (20)
-    "k_scatter<false>": 40.0,    # read 20 write 20
+    "k_scatter<true>": 34.0,     # read x,y,z,m (16) write key,id,fractions,mass (18)
+    "k_scatter<false>": 36.0,    # read 18 write 18
     "k_upsweep": 4.0,            # read key
     "k_density": 14.0,           # read key, id (8) write w (4), kbin (2)
 }
