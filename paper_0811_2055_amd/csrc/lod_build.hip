@@ -44,8 +44,11 @@ constexpr int ITEMS = 16;        // elements per thread
 constexpr int TILE = TB * ITEMS; // elements per density tile (4096)
 
 // radix sort tiles: scatter blocks of STB threads x SITEMS elements; the
-// histogram kernels (TB threads) cover the same STILE elements per block
-constexpr int STB = 1024;                    // scatter threads per block
+// histogram kernels (TB threads) cover the same STILE elements per block.
+// 512-thread scatter blocks take 43 KB of LDS, so two run on a CU and one's
+// ranking overlaps the other's stores (1024 threads and 84 KB: one block per
+// CU, 2.5% slower build).
+constexpr int STB = 512;                     // scatter threads per block
 constexpr int SITEMS = 8;                    // elements per scatter thread
 constexpr int STILE = STB * SITEMS;          // elements per sort tile
 constexpr int HITEMS = STILE / TB;           // elements per histogram thread
