@@ -209,7 +209,7 @@ struct ScatterIn {
 
 template <bool FIRST>
 __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const uint32_t *__restrict__ thist,
-                                                 uint64_t n_tiles, ScatterIn in,
+                                                 const uint32_t *__restrict__ tsum, uint64_t n_tiles, ScatterIn in,
                                                  uint32_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
                                                  uint32_t *__restrict__ lo_out, uint16_t *__restrict__ lz_out,
                                                  float *__restrict__ m_out) {
@@ -228,9 +228,12 @@ __global__ __launch_bounds__(STB) void k_scatter(BuildArgs a, int shift, const u
   const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint64_t tbase = tile * STILE;
   const uint64_t ebase = tbase + (uint64_t)w * PER_WAVE + lane;
-  // this tile's global digit offsets, loaded first (every thread, clamped
-  // index) so that waiting for them does not wait for the element loads
-  const uint32_t g0 = thist[(uint64_t)min((int)threadIdx.x, RADIX - 1) * n_tiles + tile];
+  // this tile's global digit offsets (the scan of the digit-major counts: a
+  // 4096-count block's own scan plus the scanned block totals), loaded first
+  // (every thread, clamped index) so that waiting for them does not wait for
+  // the element loads
+  const uint64_t hi = (uint64_t)min((int)threadIdx.x, RADIX - 1) * n_tiles + tile;
+  const uint32_t g0 = thist[hi] + tsum[hi / SCAN_TILE];
   uint32_t kk[ROUNDS], ii[ROUNDS];
   uint64_t ll[ROUNDS];
   float mm[ROUNDS];
@@ -1963,15 +1966,15 @@ lod_status launch_build(const lod_input &in, const lod_params &p, void *ws, cons
   const int kb = key_bits(p, n_snap);
   const int passes = std::max(1, (kb + 7) / 8);
   // pass 0 reads the particles (keys recomputed, ids implicit) and writes B
-  device_scan<uint32_t>(thist, hist_n, scan32, st);
-  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 0, thist, tiles,
+  device_scan_blocks<uint32_t>(thist, hist_n, scan32, st);
+  LOD_LAUNCH(k_scatter<true>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 0, thist, scan32, tiles,
              ScatterIn{nullptr, nullptr, nullptr, nullptr, in.x, in.y, in.z, in.mass}, keyB, idxB, loB, lzB, mB);
   uint32_t *ks = keyB, *is = idxB, *ls = loB; uint16_t *zs = lzB; float *ms = mB;
   uint32_t *kd = keyA, *id = idxA, *ld = loA; uint16_t *zd = lzA; float *md = mA;
   for (int ps = 1; ps < passes; ++ps) {
     LOD_LAUNCH(k_upsweep, dim3((unsigned)tiles), dim3(TB), 0, st, ks, N, 8 * ps, thist, tiles);
-    device_scan<uint32_t>(thist, hist_n, scan32, st);
-    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 8 * ps, thist, tiles,
+    device_scan_blocks<uint32_t>(thist, hist_n, scan32, st);
+    LOD_LAUNCH(k_scatter<false>, dim3((unsigned)tiles), dim3(STB), 0, st, a, 8 * ps, thist, scan32, tiles,
                ScatterIn{ks, is, ls, zs, nullptr, nullptr, nullptr, ms}, kd, id, ld, zd, md);
     std::swap(ks, kd); std::swap(is, id); std::swap(ls, ld); std::swap(zs, zd); std::swap(ms, md);
   }
