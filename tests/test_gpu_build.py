@@ -82,6 +82,31 @@ def test_build_matches_oracle(case, mode):
     assert np.array_equal(wit[sel], ref.witness[sel])
 
 
+# Sizes around the sort's tile edges (4096 elements) and the digit-offset
+# scan's block edges (4096 counts = 16 tiles): one tile short, exact and one
+# over; a single scan block exactly full; two scan blocks, the second ragged;
+# and D = 10 (four 8-bit passes).
+SORT_EDGES = [(4095, 8), (4096, 8), (4097, 8), (12289, 8), (65536, 8), (69633, 8), (40961, 10)]
+
+
+@pytest.mark.parametrize("N,D", SORT_EDGES, ids=[f"N{n}_D{d}" for n, d in SORT_EDGES])
+def test_sort_at_tile_edges(N, D):
+    """The sorted keys and ids equal a stable sort of the depth-D Morton keys
+    (ids ascending within equal keys); a third of the particles share one
+    cell, so equal keys span several tiles."""
+    import torch
+    s = _dup_set(N, 20 + N % 97)
+    print(f"[sort edges] N={N} D={D}", flush=True)
+    keys_D = olod.interleave(*(olod.cell_coords(a, D) for a in (s.x, s.y, s.z)), D)
+    order = np.argsort(keys_D, kind="stable")
+    b = lib.Builder(N, lib.BuildParams(n=64, max_depth=D, alpha=1, seed=1))
+    b.build(*to_dev(s))
+    keys = lib._to_numpy(b.view(0, torch.uint32)).astype(np.uint64)
+    ids = lib._to_numpy(b.view(1, torch.uint32)).astype(np.int64)
+    assert np.array_equal(ids, order)
+    assert np.array_equal(keys, keys_D[order])
+
+
 def test_empty_input():
     import torch
     e = torch.zeros(0, dtype=torch.float32, device="cuda")
